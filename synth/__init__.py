@@ -1,0 +1,93 @@
+"""Seeded synthetic inputs for the RANMAR workloads.
+
+This module holds the input recipes only (seeds, jump lengths, stream offsets,
+request arrivals and sizes) and none of the generator's arithmetic, so that
+the GPU path and the CPU oracle can both draw their inputs from it without
+sharing any of the method's code.
+
+Every generator is a numpy PCG64 stream seeded from ``BASE_SEED`` plus a
+per-workload offset, so a workload is reproducible from its name alone.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 20251202
+SEED_MIN, SEED_MAX = 1, 900_000_000     # seed range accepted by the initialisation
+
+# Workload shapes (name -> parameters).  The sizes follow the paper's use of
+# the generator: one stream per compute unit, each starting at a multiple of a
+# fixed jump length, and jump lengths up to about 2^120.
+SINGLE_STREAM = dict(seed=12345, draws=1_000_000, jump=1 << 20)
+FAMILY_65K = dict(seed=4711, streams=65_536, spacing=1 << 40, draws=4_096)
+BULK_1M = dict(seed=900_000, streams=1 << 20, spacing=1 << 100, draws=1_024)
+BATCH_JUMPS = dict(requests=1_000_000, jump_bits=120)
+SERVE = dict(requests=200_000, count_log10=(2.0, 7.0), offset_bits=120, budget_bytes=64 << 30)
+
+
+def rng(offset: int) -> np.random.Generator:
+    return np.random.default_rng(BASE_SEED + offset)
+
+
+def seeds(n: int, offset: int = 4) -> np.ndarray:
+    """n seeds uniform on [1, 9e8] (int32)."""
+    return rng(offset).integers(SEED_MIN, SEED_MAX + 1, size=n, dtype=np.int64).astype(np.int32)
+
+
+def u128_uniform(g: np.random.Generator, n: int, bits: int = 120):
+    """n integers uniform on [0, 2^bits) as (lo, hi) uint64 limb arrays."""
+    if not 0 < bits <= 128:
+        raise ValueError("bits must be in (0, 128]")
+    lo = g.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False) if bits >= 64 else \
+        g.integers(0, 1 << bits, size=n, dtype=np.uint64)
+    if bits > 64:
+        hb = bits - 64
+        hi = g.integers(0, 1 << hb, size=n, dtype=np.uint64) if hb < 64 else \
+            g.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+    else:
+        hi = np.zeros(n, np.uint64)
+    return lo, hi
+
+
+def u128_to_int(lo, hi) -> list:
+    return [(int(h) << 64) | int(l) for l, h in zip(lo, hi)]
+
+
+def int_to_u128(vals):
+    vals = [int(v) for v in vals]
+    lo = np.array([v & ((1 << 64) - 1) for v in vals], np.uint64)
+    hi = np.array([v >> 64 for v in vals], np.uint64)
+    return lo, hi
+
+
+def batch_jumps(n: int, bits: int = 120, offset: int = 4):
+    """Batched jump requests: (seeds int32[n], J lo uint64[n], J hi uint64[n])."""
+    g = rng(offset)
+    s = g.integers(SEED_MIN, SEED_MAX + 1, size=n, dtype=np.int64).astype(np.int32)
+    lo, hi = u128_uniform(g, n, bits)
+    return s, lo, hi
+
+
+def family_offsets(n: int, spacing: int):
+    """Stream k of a family starts at offset k * spacing: (lo, hi) limbs."""
+    return int_to_u128([k * spacing for k in range(n)])
+
+
+def family_sample(n_streams: int, k: int = 64, offset: int = 2) -> np.ndarray:
+    """Stream 0, the last stream and k distinct streams from 1..n-2."""
+    g = rng(offset)
+    mid = g.choice(np.arange(1, n_streams - 1), size=min(k, max(n_streams - 2, 0)), replace=False)
+    return np.unique(np.concatenate([[0, n_streams - 1], mid]).astype(np.int64))
+
+
+def serve_requests(n: int, qps: float, offset: int = 5, count_log10=(2.0, 7.0), bits: int = 120):
+    """Served requests: Poisson arrival times (s), seeds, offsets and counts.
+
+    Counts are floor(10^U) with U uniform on count_log10 (log-uniform sizes)."""
+    g = rng(offset)
+    gaps = g.exponential(1.0 / qps, size=n)
+    arrival = np.cumsum(gaps) - gaps[0]
+    s = g.integers(SEED_MIN, SEED_MAX + 1, size=n, dtype=np.int64).astype(np.int32)
+    lo, hi = u128_uniform(g, n, bits)
+    counts = np.floor(10.0 ** g.uniform(count_log10[0], count_log10[1], size=n)).astype(np.uint64)
+    return dict(arrival=arrival, seeds=s, off_lo=lo, off_hi=hi, counts=counts)
