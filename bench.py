@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""Benchmark of the RANMAR hot path on one MI355X.
+
+Workloads (all synthetic, seeded; see synth/):
+  family65k  (default) one step = seed 4711 on the GPU, 65,536 stream starts at
+             offsets k*2^40 by exact GPU jump-ahead, then 4,096 draws per stream
+             written as uint32 and as float32 (2^28 draws per step).
+  bulk1m     generation only: 2^20 streams at offsets k*2^100 already on the
+             device, 1,024 float32 draws each (2^30 draws, 4 GiB per step).
+  jumps1m    10^6 seed+jump requests, J uniform on [0, 2^120), one launch.
+
+Prints ONE JSON line for the chosen workload; the default run also measures
+bulk1m and jumps1m briefly and reports them under "also".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 24-bit integer multiply-adds per second (lane-ops), 39.32 T
+
+MACS_SQUARE = 97 * 98 // 2     # symmetric schoolbook squaring: 4753 multiply-adds
+MACS_APPLY = 97 * 97           # Horner application: 9409 multiply-adds
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="family65k", choices=["family65k", "bulk1m", "jumps1m"])
+    ap.add_argument("--jump", default="family", choices=["family", "lanes"],
+                    help="family65k: stream starts by prefix doubling or one jump per stream")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on a bounded sample of the workload.
+# ---------------------------------------------------------------------------
+def _cpu_worker(args):
+    kind, ks, budget = args
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    done = 0
+    units = 0
+    for k in ks:
+        if kind == "family65k":
+            p = synth.FAMILY_65K
+            st = O.jump(O.state_from_seed(p["seed"]), int(k) * p["spacing"])
+            O.state_draws(st, p["draws"])
+            units += p["draws"]
+        elif kind == "bulk1m":
+            p = synth.BULK_1M
+            st = O.jump(O.state_from_seed(p["seed"]), int(k) * p["spacing"])
+            O.state_draws(st, p["draws"])
+            units += p["draws"]
+        else:
+            s, lo, hi = k
+            O.seed_jump_many([s], [(int(hi) << 64) | int(lo)])
+            units += 1
+        done += 1
+        if time.perf_counter() - t0 > budget:
+            break
+    return units, time.perf_counter() - t0, done
+
+
+def cpu_baseline(kind: str, seconds: float):
+    workers = max(1, min(16, os.cpu_count() or 1))
+    if kind == "jumps1m":
+        s, lo, hi = synth.batch_jumps(4000 * workers, 120, offset=4)
+        items = list(zip(s.tolist(), lo.tolist(), hi.tolist()))
+        unit, sample = "jumps/s", "seed + jump of 10^6-workload requests (J uniform 120-bit)"
+    else:
+        n = synth.FAMILY_65K["streams"] if kind == "family65k" else synth.BULK_1M["streams"]
+        g = synth.rng(77)
+        items = [int(v) for v in g.choice(n, size=min(n, 4000 * workers), replace=False)]
+        unit = "draws/s"
+        sample = ("streams of the 65,536-stream family: oracle jump to k*2^40 + 4,096 draws"
+                  if kind == "family65k" else "streams of the 2^20 family: oracle jump + 1,024 draws")
+    chunks = [(kind, items[i::workers], seconds) for i in range(workers)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_cpu_worker, chunks)
+    units = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    done = sum(r[2] for r in res)
+    return {"value": units / wall, "unit": unit, "cores": workers, "kind": "oracle",
+            "sample": f"{done} {sample}, {workers} processes, {wall:.1f} s"}
+
+
+# ---------------------------------------------------------------------------
+# GPU workloads
+# ---------------------------------------------------------------------------
+class Timer:
+    """HIP events on torch's current stream (the stream the library launches on)."""
+
+    def __init__(self, torch):
+        self.t = torch
+        self.spans = {}
+
+    def span(self, name):
+        t = self.t
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        self.spans.setdefault(name, []).append((a, b))
+        return a, b
+
+    def mean_ms(self, name):
+        v = [a.elapsed_time(b) for a, b in self.spans.get(name, [])]
+        return sum(v) / len(v) if v else float("nan")
+
+
+def run_family65k(R, torch, steps, warmup, jump_mode):
+    p = synth.FAMILY_65K
+    n, cnt = p["streams"], p["draws"]
+    dev = torch.device("cuda:0")
+    seed1 = torch.tensor([p["seed"]], dtype=torch.int32, device=dev)
+    base = torch.empty((1, 98), dtype=torch.int32, device=dev)
+    states = torch.empty((n, 98), dtype=torch.int32, device=dev)
+    out_u = torch.empty((n, cnt), dtype=torch.int32, device=dev)
+    out_f = torch.empty((n, cnt), dtype=torch.float32, device=dev)
+    seeds_n = torch.full((n,), p["seed"], dtype=torch.int32, device=dev)
+    import numpy as np
+    lo, hi = synth.family_offsets(n, p["spacing"])
+    offs = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
+    tm = Timer(torch)
+
+    def step(timed):
+        if jump_mode == "family":
+            a, b = tm.span("starts") if timed else (None, None)
+            if a: a.record()
+            R.ranmar_seed_batch(seed1, out=base)
+            R.ranmar_jump_family(base, p["spacing"], n, out=states)
+            if b: b.record()
+        else:
+            a, b = tm.span("starts") if timed else (None, None)
+            if a: a.record()
+            R.ranmar_seed_jump(seeds_n, offs, out=states)
+            if b: b.record()
+        a, b = tm.span("gen_u24") if timed else (None, None)
+        if a: a.record()
+        R.ranmar_generate(states, cnt, R.RANMAR_U24, out=out_u)
+        if b: b.record()
+        a, b = tm.span("gen_f32") if timed else (None, None)
+        if a: a.record()
+        R.ranmar_generate(states, cnt, R.RANMAR_F32, out=out_f, states_out=states)
+        if b: b.record()
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    draws = n * cnt
+    gen_ms = tm.mean_ms("gen_f32")
+    gen_bytes = 4 * draws + 2 * 392 * n          # output + state read + state write-back
+    res = {
+        "metric": "draws/s", "value": draws / dt, "unit": "draws/s", "ms_per_step": dt * 1e3,
+        "dtype": "u24", "config": {"workload": f"family65k: 65,536 streams from seed 4711 at offsets k*2^40 "
+                                   f"({'prefix-doubled' if jump_mode == 'family' else 'one jump per stream'}"
+                                   "), 4,096 draws each as uint32 and float32",
+                                   "streams": n, "draws_per_stream": cnt, "jump": jump_mode},
+        "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},
+        "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": gen_bytes / (gen_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gen_bytes / (gen_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": gen_bytes, "launch_ms": gen_ms},
+    }
+    return res
+
+
+def run_bulk1m(R, torch, steps, warmup):
+    p = synth.BULK_1M
+    n, cnt = p["streams"], p["draws"]
+    dev = torch.device("cuda:0")
+    seed1 = torch.tensor([p["seed"]], dtype=torch.int32, device=dev)
+    base = R.ranmar_seed_batch(seed1)
+    states = R.ranmar_jump_family(base, p["spacing"], n)
+    out = torch.empty((n, cnt), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    for _ in range(warmup):
+        R.ranmar_generate(states, cnt, R.RANMAR_F32, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b = tm.span("gen")
+        a.record()
+        R.ranmar_generate(states, cnt, R.RANMAR_F32, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms = tm.mean_ms("gen")
+    draws = n * cnt
+    algo = 4 * draws + 392 * n      # output + state read (no write-back)
+    return {
+        "metric": "draws/s", "value": draws / dt, "unit": "draws/s", "ms_per_step": dt * 1e3, "dtype": "f32",
+        "config": {"workload": "bulk1m: 2^20 streams at offsets k*2^100 from seed 900000 (states on device), "
+                               "1,024 float32 draws each", "streams": n, "draws_per_stream": cnt},
+        "output_write_GBps": 4 * draws / (ms * 1e-3) / 1e9,
+        "output_write_frac": 4 * draws / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": algo / (ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": algo, "launch_ms": ms},
+    }
+
+
+def run_jumps1m(R, torch, steps, warmup):
+    import numpy as np
+    n = synth.BATCH_JUMPS["requests"]
+    s, lo, hi = synth.batch_jumps(n, 120, offset=4)
+    dev = torch.device("cuda:0")
+    seeds = torch.from_numpy(s.copy()).to(dev)
+    offs = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
+    out = torch.empty((n, 98), dtype=torch.int32, device=dev)
+    tm = Timer(torch)
+    for _ in range(warmup):
+        R.ranmar_seed_jump(seeds, offs, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b = tm.span("jump")
+        a.record()
+        R.ranmar_seed_jump(seeds, offs, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms = tm.mean_ms("jump")
+    # Algorithmic multiply-adds: one symmetric squaring per exponent bit below
+    # the top six (the window start is a monomial) + one Horner application.
+    bl = np.where(hi > 0, 64 + np.floor(np.log2(np.maximum(hi, 1).astype(np.float64))) + 1,
+                  np.floor(np.log2(np.maximum(lo, 1).astype(np.float64))) + 1)
+    sq = np.maximum(bl - 6, 0).sum()
+    macs = sq * MACS_SQUARE + n * MACS_APPLY
+    ach = macs / (ms * 1e-3) / 1e12
+    return {
+        "metric": "jumps/s", "value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3, "dtype": "u24",
+        "config": {"workload": "jumps1m: 10^6 seed+jump requests, seeds uniform on [1, 9e8], J uniform on "
+                               "[0, 2^120), one launch", "requests": n},
+        "roofline": {"bound": "alu", "kernel": "k_jump<seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (24-bit multiply-adds)", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                     "ops_per_launch": float(macs), "launch_ms": ms},
+    }
+
+
+def main():
+    a = _parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is by disjoint "
+                                   "stream ranges and needs no collective (see the design notes)",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2512_00093_amd as R
+    torch.cuda.set_device(0)
+    R.ranmar_init()
+    if a.workload == "family65k":
+        res = run_family65k(R, torch, a.steps, a.warmup, a.jump)
+    elif a.workload == "bulk1m":
+        res = run_bulk1m(R, torch, a.steps, a.warmup)
+    else:
+        res = run_jumps1m(R, torch, a.steps, a.warmup)
+    line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"], "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": res["dtype"], "data": "synthetic", "config": res["config"],
+            "roofline": res["roofline"]}
+    for k in ("breakdown_ms", "output_write_GBps", "output_write_frac"):
+        if k in res:
+            line[k] = res[k]
+    if not a.no_extras and a.workload == "family65k":
+        also = {}
+        for name, fn in (("bulk1m", run_bulk1m), ("jumps1m", run_jumps1m)):
+            r = fn(R, torch, 10, 2)
+            also[name] = {k: r[k] for k in r if k not in ("metric",)}
+        line["also"] = also
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

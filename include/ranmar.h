@@ -1,0 +1,298 @@
+/*
+ * ranmar.h -- C ABI of the MI355X (gfx950) RANMAR library.
+ *
+ * RANMAR as restated by Haramoto & Suzuki, "Making the RANMAR pseudorandom
+ * number generator in LAMMPS up to four times faster, with an implementation
+ * of jump-ahead" (arXiv 2512.00093): a lagged Fibonacci sequence
+ *     x_n = x_{n-97} - x_{n-33}  mod 2^24                    (Sec. 2, Sec. 3.1)
+ * combined with the arithmetic sequence c_n = c_{n-1} - d' mod m, m = 2^24-3,
+ * d' = 7654321 (Sec. 2, Sec. 3.2), each output being (x_n - c_n) mod 2^24
+ * (Algorithm 2).  Streams are placed with the paper's exact jump-ahead:
+ * t^J mod phi(t), phi = t^97 + t^64 - 1, over Z/2^24 applied to the state
+ * (Sec. 3.1) and the closed form for c (Sec. 3.2).
+ *
+ * General conventions
+ *   - Every function returns a status: RANMAR_OK (0) or a negative
+ *     ranmar_status.  Argument errors are detected on the host before any
+ *     work is queued and leave all buffers untouched.
+ *   - "d_" pointers are device pointers (HIP device memory of the current
+ *     device); other pointers are host memory.  The caller owns every buffer
+ *     it passes; the library never frees caller memory and never keeps a
+ *     caller pointer after the call returns (the server keeps only the arena
+ *     it is given, until ranmar_serve_destroy).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is queued asynchronously on it; results are ready once the
+ *     stream has been synchronised.  A failure of queued device work is
+ *     reported as RANMAR_EHIP by the next call that checks the device.
+ *   - Sizes are element counts unless the name says bytes.  n == 0 is valid
+ *     and does nothing.
+ *   - All arithmetic is integer and exact: results are bit-identical to the
+ *     definitions cited, whatever the launch shape or tuning.
+ */
+#ifndef RANMAR_H
+#define RANMAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Types                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Generator state: the automaton state (u_1, ..., u_97, c) of Sec. 2 with
+ * every word in integer form (Sec. 3.1: sigma maps the 24-bit reals to
+ * Z/2^24; Sec. 3.2: c is kept as its numerator c').
+ *   x[0] = u_1 is the oldest word (lag 97), x[96] = u_97 the newest; every
+ *   x[k] < 2^24.  c is the numerator of the arithmetic sequence, c < m.
+ * The next draw computes u_1 - u_65 (the new newest word), steps c to
+ * (c - 7654321) mod m, and outputs the difference of the two mod 2^24.
+ * 98 words = 392 bytes, 4-byte aligned; arrays of states are packed. */
+typedef struct ranmar_state {
+    uint32_t x[97];
+    uint32_t c;
+} ranmar_state;
+
+/* Unsigned 128-bit jump length or offset J = hi * 2^64 + lo. */
+typedef struct ranmar_u128 {
+    uint64_t lo;
+    uint64_t hi;
+} ranmar_u128;
+
+typedef enum ranmar_status {
+    RANMAR_OK = 0,
+    RANMAR_EINVAL = -1,    /* bad argument (range, NULL, misalignment) */
+    RANMAR_ENOMEM = -2,    /* larger than the memory budget it was given */
+    RANMAR_EAGAIN = -3,    /* budget or queue temporarily full; retry later */
+    RANMAR_EHIP = -4,      /* HIP runtime error (launch or queued work) */
+    RANMAR_ENOENT = -5,    /* unknown ticket / handle */
+    RANMAR_ETIMEDOUT = -6, /* wait timed out */
+    RANMAR_ENODEV = -7     /* no gfx950 device current */
+} ranmar_status;
+
+/* Output format of generated draws. */
+typedef enum ranmar_fmt {
+    RANMAR_U24 = 0, /* uint32 k, 0 <= k < 2^24 (the value is k * 2^-24) */
+    RANMAR_F32 = 1  /* float k * 2^-24, exact in binary32 */
+} ranmar_fmt;
+
+/* ------------------------------------------------------------------------ */
+/* Library                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Static text for a status code (never NULL). */
+const char *ranmar_strerror(int status);
+
+/* ABI version, major * 10000 + minor * 100 + patch. */
+int ranmar_version(void);
+
+/* Checks that the current HIP device is a gfx950 and sets up per-device
+ * tables.  Called implicitly by every device entry point; may be called
+ * explicitly to surface RANMAR_ENODEV / RANMAR_EHIP early. */
+int ranmar_init(void);
+
+/* ------------------------------------------------------------------------ */
+/* a1: seeding (Appendix A, Algorithm 3; reading: the inner step is         */
+/* Remainder(Remainder(i*j,179)*k,179))                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Host: state at offset 0 for `seed`, i.e. right after Algorithm 3.
+ * seed must be in [1, 900000000] (Algorithm 3 admits up to 9e8; seed 0
+ * would need the quotient of -1, which the paper does not define), else
+ * RANMAR_EINVAL.  out is host memory. */
+int ranmar_seed(int64_t seed, ranmar_state *out);
+
+/* Device: d_out[r] = state at offset 0 for d_seeds[r], r < n.  Seeds outside
+ * [1, 9e8] produce an all-zero record with c = 0xFFFFFFFF (an invalid c
+ * marks it) -- validate on the host first if needed.  d_seeds: n int32;
+ * d_out: n records.  The two buffers must not overlap. */
+int ranmar_seed_batch(const int32_t *d_seeds, uint64_t n, ranmar_state *d_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* a2-a4: jump-ahead (Sec. 3.1 and 3.2)                                      */
+/* ------------------------------------------------------------------------ */
+
+/* a3: d_P[r*97 + i] = coefficient b_i of P_J(t) = t^J mod phi(t) over
+ * Z/2^24 for J = d_J[r] (Sec. 3.1; the quantity the paper times in
+ * Table 2).  Left-to-right square-and-multiply.  d_J: n values; d_P: 97*n
+ * uint32, each < 2^24. */
+int ranmar_jump_poly(const ranmar_u128 *d_J, uint64_t n, uint32_t *d_P, void *stream);
+
+/* a4: in place, x <- x P(A) for each state, with P = d_P[r*97 .. r*97+96]
+ * (Horner's rule of Sec. 3.1, equal to applying f_1 sum-of-powers); c is not
+ * changed.  d_states: n records; d_P: 97*n uint32 (values are taken mod
+ * 2^24). */
+int ranmar_apply_poly(ranmar_state *d_states, const uint32_t *d_P, uint64_t n, void *stream);
+
+/* a2+a3+a4: in place, d_states[r] <- f^J(d_states[r]) with J = d_J[r]:
+ * x by P_J(A) (Sec. 3.1), c by (c - (J mod m) d') mod m (Sec. 3.2).
+ * Equal to J single transitions.  J = 0 leaves the state unchanged. */
+int ranmar_jump(ranmar_state *d_states, const ranmar_u128 *d_J, uint64_t n, void *stream);
+
+/* a1-a4 fused in one launch: d_out[r] = f^J(seed state of d_seeds[r]) with
+ * J = d_offsets[r] (d_offsets may be NULL: offset 0).  This is the paper's
+ * block splitting (Sec. 1): a stream is rebuilt from (seed, offset) alone.
+ * Invalid seeds behave as in ranmar_seed_batch. */
+int ranmar_seed_jump(const int32_t *d_seeds, const ranmar_u128 *d_offsets, uint64_t n,
+                     ranmar_state *d_out, void *stream);
+
+/* Stream family (Sec. 1, block splitting): d_out[k] = f^(k*delta)(*d_base)
+ * for k < n, i.e. unit k starts at state s_{k*delta}.  Computed on the GPU
+ * by prefix doubling with the exact jump: the starts of units [2^b, 2^(b+1))
+ * are those of [0, 2^b) jumped by 2^b*delta; bit-identical to n separate
+ * jumps.  k*delta is taken mod 2^128.  d_base: 1 record (may lie inside
+ * d_out only as d_out[0]). */
+int ranmar_jump_family(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n,
+                       ranmar_state *d_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* a5: generation (Algorithm 2)                                              */
+/* ------------------------------------------------------------------------ */
+
+/* For each stream r < n: `count` consecutive draws of Algorithm 2 starting
+ * from d_in[r], written to row r of d_out (row stride `ld` elements,
+ * ld >= count; element type uint32 for RANMAR_U24, float for RANMAR_F32).
+ * If d_state_out is not NULL the state after the draws is written there
+ * (d_state_out may equal d_in: in-place advance; otherwise it must not
+ * overlap d_in).  d_out must be 4-byte aligned and must not overlap the
+ * states.  count == 0 copies the states (if d_state_out != d_in). */
+int ranmar_generate(const ranmar_state *d_in, ranmar_state *d_state_out, uint64_t n,
+                    uint64_t count, int fmt, void *d_out, uint64_t ld, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* a6: batched execution of uneven work in one persistent launch             */
+/* ------------------------------------------------------------------------ */
+
+/* One request of a batch: stream (seed, offset) -> `count` draws written
+ * contiguously at d_out (element type per fmt).  If d_state is not NULL the
+ * state after the draws is stored there.  Requests of any size share one
+ * launch: each is cut into fixed-size chunks whose start states come from
+ * the exact jump (offset + q*chunk), so the result equals ranmar_seed_jump
+ * followed by ranmar_generate(count) for the request alone. */
+typedef struct ranmar_request {
+    int32_t seed;
+    uint32_t fmt;       /* ranmar_fmt */
+    ranmar_u128 offset; /* J of the first draw's predecessor state */
+    uint64_t count;     /* draws */
+    void *d_out;        /* device, count elements */
+    ranmar_state *d_state; /* device, optional */
+} ranmar_request;
+
+typedef struct ranmar_batch ranmar_batch;
+
+/* Creates a reusable batch executor able to take up to max_requests
+ * requests and max_chunks chunks per run.  It owns device descriptor
+ * buffers of fixed size (allocated here, once) and a captured hipGraph of
+ * the persistent launch, re-played by every run.  chunk_draws = 0 picks the
+ * tuned default.  *out receives the handle. */
+int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chunk_draws,
+                        ranmar_batch **out);
+
+/* Runs n requests (host array) in one graph launch on `stream`.  Returns
+ * RANMAR_EINVAL for bad requests (bad seed, NULL output with count > 0,
+ * bad fmt) and RANMAR_ENOMEM if n or the chunk total exceed the capacity.
+ * The batch may be reused once the stream has passed this run. */
+int ranmar_batch_run(ranmar_batch *b, const ranmar_request *reqs, uint64_t n, void *stream);
+
+/* Same work as ranmar_batch_run, one ordinary launch per request (the
+ * baseline the batched path is measured against). */
+int ranmar_run_unbatched(const ranmar_request *reqs, uint64_t n, void *stream);
+
+int ranmar_batch_destroy(ranmar_batch *b);
+
+/* ------------------------------------------------------------------------ */
+/* a7: serving -- continuous batching of (seed, offset, count) requests      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct ranmar_serve_cfg {
+    uint64_t max_inflight;   /* requests admitted but not released (>= 1) */
+    uint64_t chunk_draws;    /* draws per chunk (0 = tuned default) */
+    uint64_t max_tick_chunks;/* chunks per launch (0 = default) */
+    uint32_t lanes;          /* concurrent HIP streams for ticks (1..8, 0 = 2) */
+    uint32_t queue_when_full;/* 1: over-budget requests wait; 0: EAGAIN */
+} ranmar_serve_cfg;
+
+typedef struct ranmar_serve_stats {
+    uint64_t submitted, completed, released, rejected;
+    uint64_t ticks;            /* launches issued */
+    uint64_t draws;            /* draws completed */
+    uint64_t bytes_in_use;     /* arena bytes held by admitted requests */
+    uint64_t bytes_peak;
+    double p50_ns, p99_ns, max_ns; /* submit -> completion observed, ns */
+    double busy_s;             /* wall time from first submit to last completion */
+} ranmar_serve_stats;
+
+typedef struct ranmar_server ranmar_server;
+
+/* Starts a server thread on the current device.  d_arena/arena_bytes is the
+ * HBM budget: all request outputs are sub-allocated from it (256-byte
+ * aligned); the caller keeps ownership and must keep it alive until
+ * ranmar_serve_destroy.  cfg may be NULL for defaults. */
+int ranmar_serve_create(void *d_arena, uint64_t arena_bytes, const ranmar_serve_cfg *cfg,
+                        ranmar_server **out);
+
+/* Queues a request; *ticket identifies it.  RANMAR_ENOMEM if its output can
+ * never fit the arena, RANMAR_EAGAIN if the budget or in-flight limit is
+ * full and the server was configured not to queue, RANMAR_EINVAL for a bad
+ * seed or format.  t_arrival_ns (CLOCK_MONOTONIC, 0 = now) is the time from
+ * which its latency is measured. */
+int ranmar_serve_submit(ranmar_server *s, int32_t seed, ranmar_u128 offset, uint64_t count,
+                        int fmt, uint64_t t_arrival_ns, uint64_t *ticket);
+
+/* Non-blocking: *done = 1 once the request's output is complete on device. */
+int ranmar_serve_poll(ranmar_server *s, uint64_t ticket, int *done);
+
+/* Blocks until done or timeout_ns elapses (RANMAR_ETIMEDOUT); < 0 = forever. */
+int ranmar_serve_wait(ranmar_server *s, uint64_t ticket, int64_t timeout_ns);
+
+/* Device pointer to the request's output (server-owned until release) and
+ * its element count; RANMAR_EAGAIN if not complete yet. */
+int ranmar_serve_result(ranmar_server *s, uint64_t ticket, const void **d_ptr, uint64_t *count);
+
+/* Returns the request's arena bytes to the budget; the pointer from
+ * ranmar_serve_result is invalid afterwards. */
+int ranmar_serve_release(ranmar_server *s, uint64_t ticket);
+
+int ranmar_serve_stats_get(ranmar_server *s, ranmar_serve_stats *out);
+
+/* Stops the server after draining admitted work; outstanding tickets are
+ * released. */
+int ranmar_serve_destroy(ranmar_server *s);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Kernel variant selection.  Every variant of a kernel computes the same
+ * bits; the tuner only picks the fastest for a shape. */
+typedef enum ranmar_kernel {
+    RANMAR_K_GENERATE = 0,
+    RANMAR_K_JUMP = 1
+} ranmar_kernel;
+
+/* Number of variants of a kernel, and a short name for each. */
+int ranmar_tune_variants(int kernel);
+const char *ranmar_tune_variant_name(int kernel, int variant);
+
+/* Forces a variant for subsequent calls (-1 = automatic). */
+int ranmar_tune_set(int kernel, int variant);
+
+/* Times every variant of `kernel` on synthetic data of the given shape
+ * (n streams/requests, count draws or jump bits) on `stream`, stores the
+ * winner for the shape bucket and writes the per-variant mean time (ms) to
+ * ms_out[variant] (host, ranmar_tune_variants() entries, may be NULL).
+ * Returns the winning variant index, or a negative status. */
+int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double *ms_out, void *stream);
+
+/* Saves / loads the tuned table (text file, one line per bucket). */
+int ranmar_tune_save(const char *path);
+int ranmar_tune_load(const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RANMAR_H */

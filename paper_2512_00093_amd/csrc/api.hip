@@ -1,0 +1,176 @@
+// C ABI layer: argument validation, device checks and launches.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/ranmar.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ranmar {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_dev_ok[kMaxDevices];  // 0 unknown, 1 gfx950, -1 not
+}  // namespace
+
+int ensure_init() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RANMAR_ENODEV;
+  if (dev < 0 || dev >= kMaxDevices) return RANMAR_ENODEV;
+  int ok = g_dev_ok[dev].load(std::memory_order_acquire);
+  if (ok == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RANMAR_EHIP;
+    ok = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+    g_dev_ok[dev].store(ok, std::memory_order_release);
+  }
+  return ok == 1 ? RANMAR_OK : RANMAR_ENODEV;
+}
+
+static inline int hip_status(hipError_t e) { return e == hipSuccess ? RANMAR_OK : RANMAR_EHIP; }
+
+static inline bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+static inline bool overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+// Host-side Algorithm 3 (Appendix A) with the Remainder reading of the
+// multiplicative step; u_ii goes to x[97 - ii].
+static int seed_host(int64_t seed, ranmar_state* out) {
+  if (seed < 1 || seed > 900000000) return RANMAR_EINVAL;
+  const uint32_t s1 = (uint32_t)(seed - 1);
+  const uint32_t ij = s1 / 30082u, kl = s1 - 30082u * ij;
+  uint32_t i = (ij / 177u) % 177u + 2u, j = ij % 177u + 2u;
+  uint32_t k = (kl / 169u) % 178u + 1u, l = kl % 169u;
+  for (int ii = 1; ii <= 97; ++ii) {
+    uint32_t word = 0;
+    for (int b = 0; b < 24; ++b) {
+      const uint32_t m = (i * j % 179u) * k % 179u;
+      i = j;
+      j = k;
+      k = m;
+      l = (53u * l + 1u) % 169u;
+      word = (word << 1) | (((l * m) & 63u) >= 32u ? 1u : 0u);
+    }
+    out->x[97 - ii] = word;
+  }
+  out->c = kC0;
+  return RANMAR_OK;
+}
+
+}  // namespace ranmar
+
+using namespace ranmar;
+
+extern "C" {
+
+const char* ranmar_strerror(int status) {
+  switch (status) {
+    case RANMAR_OK: return "ok";
+    case RANMAR_EINVAL: return "invalid argument";
+    case RANMAR_ENOMEM: return "request exceeds the memory budget";
+    case RANMAR_EAGAIN: return "temporarily full, retry";
+    case RANMAR_EHIP: return "HIP runtime error";
+    case RANMAR_ENOENT: return "unknown ticket or handle";
+    case RANMAR_ETIMEDOUT: return "timed out";
+    case RANMAR_ENODEV: return "no gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+int ranmar_version(void) { return 10000; }
+
+int ranmar_init(void) { return ensure_init(); }
+
+int ranmar_seed(int64_t seed, ranmar_state* out) {
+  if (!out) return RANMAR_EINVAL;
+  return seed_host(seed, out);
+}
+
+int ranmar_seed_batch(const int32_t* d_seeds, uint64_t n, ranmar_state* d_out, void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_seeds || !d_out || !aligned(d_seeds, 4) || !aligned(d_out, 4)) return RANMAR_EINVAL;
+  if (overlap(d_seeds, 4 * n, d_out, sizeof(ranmar_state) * n)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_seed(d_seeds, n, (uint32_t*)d_out, (hipStream_t)stream));
+}
+
+int ranmar_jump_poly(const ranmar_u128* d_J, uint64_t n, uint32_t* d_P, void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_J || !d_P || !aligned(d_J, 8) || !aligned(d_P, 4)) return RANMAR_EINVAL;
+  if (overlap(d_J, 16 * n, d_P, 388 * n)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_jump_poly(d_J, n, d_P, (hipStream_t)stream));
+}
+
+int ranmar_apply_poly(ranmar_state* d_states, const uint32_t* d_P, uint64_t n, void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_states || !d_P || !aligned(d_states, 4) || !aligned(d_P, 4)) return RANMAR_EINVAL;
+  if (overlap(d_states, sizeof(ranmar_state) * n, d_P, 388 * n)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_apply_poly((uint32_t*)d_states, d_P, n, (hipStream_t)stream));
+}
+
+int ranmar_jump(ranmar_state* d_states, const ranmar_u128* d_J, uint64_t n, void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_states || !d_J || !aligned(d_states, 4) || !aligned(d_J, 8)) return RANMAR_EINVAL;
+  if (overlap(d_states, sizeof(ranmar_state) * n, d_J, 16 * n)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_jump((uint32_t*)d_states, nullptr, d_J, n, (hipStream_t)stream));
+}
+
+int ranmar_seed_jump(const int32_t* d_seeds, const ranmar_u128* d_offsets, uint64_t n, ranmar_state* d_out,
+                     void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_seeds || !d_out || !aligned(d_seeds, 4) || !aligned(d_out, 4)) return RANMAR_EINVAL;
+  if (d_offsets && !aligned(d_offsets, 8)) return RANMAR_EINVAL;
+  const uint64_t sb = sizeof(ranmar_state) * n;
+  if (overlap(d_seeds, 4 * n, d_out, sb) || (d_offsets && overlap(d_offsets, 16 * n, d_out, sb)))
+    return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_jump((uint32_t*)d_out, d_seeds, d_offsets, n, (hipStream_t)stream));
+}
+
+int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n, ranmar_state* d_out,
+                       void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_base || !d_out || !aligned(d_base, 4) || !aligned(d_out, 4)) return RANMAR_EINVAL;
+  if (d_base != d_out && overlap(d_base, sizeof(ranmar_state), d_out, sizeof(ranmar_state) * n))
+    return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_family((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, (hipStream_t)stream));
+}
+
+int ranmar_generate(const ranmar_state* d_in, ranmar_state* d_state_out, uint64_t n, uint64_t count, int fmt,
+                    void* d_out, uint64_t ld, void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (fmt != RANMAR_U24 && fmt != RANMAR_F32) return RANMAR_EINVAL;
+  if (!d_in || !aligned(d_in, 4) || (d_state_out && !aligned(d_state_out, 4))) return RANMAR_EINVAL;
+  if (count > 0 && (!d_out || !aligned(d_out, 4) || ld < count)) return RANMAR_EINVAL;
+  if (ld > (UINT64_MAX / 4) / n) return RANMAR_EINVAL;
+  const uint64_t sb = sizeof(ranmar_state) * n;
+  if (d_state_out && d_state_out != d_in && overlap(d_in, sb, d_state_out, sb)) return RANMAR_EINVAL;
+  if (count > 0) {
+    const uint64_t ob = 4 * (ld * (n - 1) + count);
+    if (overlap(d_out, ob, d_in, sb) || (d_state_out && overlap(d_out, ob, d_state_out, sb))) return RANMAR_EINVAL;
+  }
+  int rc = ensure_init();
+  if (rc) return rc;
+  const int variant = gen_variant_for(n, count);
+  return hip_status(launch_generate(variant, (const uint32_t*)d_in, (uint32_t*)d_state_out, n, count, fmt, d_out, ld,
+                                    (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Internal host-side interface between the C ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ranmar.h"
+
+namespace ranmar {
+
+// seeds -> state records at offset 0
+hipError_t launch_seed(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
+// t^J mod phi, 97 words per request
+hipError_t launch_jump_poly(const ranmar_u128* J, uint64_t n, uint32_t* P, hipStream_t st);
+// x <- x P(A)
+hipError_t launch_apply_poly(uint32_t* states, const uint32_t* P, uint64_t n, hipStream_t st);
+// in-place f^J, optionally seeding first (seeds != nullptr)
+hipError_t launch_jump(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n, hipStream_t st);
+
+// Generation variants (all bit-identical).
+enum GenVariant : int {
+  GEN_LANES32 = 0,     // 32 lanes per stream, cross-lane shift via ds_bpermute
+  GEN_LANES32_NT = 1,  // same, non-temporal output stores
+  GEN_NUM_VARIANTS = 2
+};
+const char* gen_variant_name(int v);
+hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uint64_t n, uint64_t count, int fmt,
+                           void* out, uint64_t ld, hipStream_t st);
+
+// Stream family by prefix doubling: out[k] = f^(k*delta)(base), k < n.
+hipError_t launch_family(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
+
+// Library-wide state.
+int ensure_init();          // RANMAR_OK / RANMAR_ENODEV / RANMAR_EHIP
+int gen_variant_for(uint64_t n, uint64_t count);   // tuned or default
+void set_error_from_hip(hipError_t e);
+
+}  // namespace ranmar

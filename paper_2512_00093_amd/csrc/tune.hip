@@ -1,0 +1,166 @@
+// Kernel-variant tuner.  Every variant of a kernel produces the same bits; the
+// tuner only records which is fastest for a shape bucket, measured with HIP
+// events on synthetic states at the real shape.  The table can be saved to and
+// loaded from a small text file ("kernel log2n log2count variant" per line).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ranmar.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ranmar {
+
+namespace {
+std::mutex g_mu;
+int g_forced[2] = {-1, -1};
+std::map<std::tuple<int, int, int>, int> g_table;  // (kernel, log2 n, log2 count) -> variant
+
+int ilog2(uint64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+constexpr int kJumpVariants = 1;
+}  // namespace
+
+int gen_variant_for(uint64_t n, uint64_t count) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (g_forced[RANMAR_K_GENERATE] >= 0) return g_forced[RANMAR_K_GENERATE];
+  auto it = g_table.find({RANMAR_K_GENERATE, ilog2(n), ilog2(count)});
+  if (it != g_table.end()) return it->second;
+  return GEN_LANES32_NT;
+}
+
+}  // namespace ranmar
+
+using namespace ranmar;
+
+extern "C" {
+
+int ranmar_tune_variants(int kernel) {
+  if (kernel == RANMAR_K_GENERATE) return GEN_NUM_VARIANTS;
+  if (kernel == RANMAR_K_JUMP) return kJumpVariants;
+  return RANMAR_EINVAL;
+}
+
+const char* ranmar_tune_variant_name(int kernel, int variant) {
+  if (kernel == RANMAR_K_GENERATE && variant >= 0 && variant < GEN_NUM_VARIANTS) return gen_variant_name(variant);
+  if (kernel == RANMAR_K_JUMP && variant == 0) return "lane_per_request";
+  return nullptr;
+}
+
+int ranmar_tune_set(int kernel, int variant) {
+  const int nv = ranmar_tune_variants(kernel);
+  if (nv < 0 || variant < -1 || variant >= nv) return RANMAR_EINVAL;
+  std::lock_guard<std::mutex> g(g_mu);
+  g_forced[kernel] = variant;
+  return RANMAR_OK;
+}
+
+int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void* stream) {
+  const int nv = ranmar_tune_variants(kernel);
+  if (nv < 0 || n == 0) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (kernel == RANMAR_K_JUMP) {
+    if (ms_out) ms_out[0] = 0.0;
+    return 0;
+  }
+  if (count == 0 || n > (1ull << 24) || count > (1ull << 24) || n * count > (1ull << 31)) return RANMAR_EINVAL;
+  // Synthetic states: seeds 1..n at offset 0.
+  int32_t* d_seeds = nullptr;
+  uint32_t* d_states = nullptr;
+  float* d_out = nullptr;
+  std::vector<int32_t> seeds(n);
+  for (uint64_t i = 0; i < n; ++i) seeds[i] = (int32_t)(1 + (i * 2654435761ull) % 900000000ull);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = RANMAR_EHIP;
+  double best = 1e30;
+  int best_v = 0;
+  if (hipMalloc(&d_seeds, 4 * n) != hipSuccess) goto done;
+  if (hipMalloc(&d_states, sizeof(ranmar_state) * n) != hipSuccess) goto done;
+  if (hipMalloc(&d_out, 4 * n * count) != hipSuccess) goto done;
+  if (hipMemcpyAsync(d_seeds, seeds.data(), 4 * n, hipMemcpyHostToDevice, st) != hipSuccess) goto done;
+  if (launch_seed(d_seeds, n, d_states, st) != hipSuccess) goto done;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+  for (int v = 0; v < nv; ++v) {
+    const int reps = 5;
+    if (launch_generate(v, d_states, nullptr, n, count, RANMAR_F32, d_out, count, st) != hipSuccess) goto done;
+    hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r)
+      if (launch_generate(v, d_states, nullptr, n, count, RANMAR_F32, d_out, count, st) != hipSuccess) goto done;
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) goto done;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / reps;
+    if (ms_out) ms_out[v] = per;
+    if (per < best) {
+      best = per;
+      best_v = v;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table[{kernel, ilog2(n), ilog2(count)}] = best_v;
+  }
+  rc = best_v;
+done:
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  if (d_out) hipFree(d_out);
+  if (d_states) hipFree(d_states);
+  if (d_seeds) hipFree(d_seeds);
+  return rc;
+}
+
+int ranmar_tune_save(const char* path) {
+  if (!path) return RANMAR_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return RANMAR_EINVAL;
+  std::lock_guard<std::mutex> g(g_mu);
+  std::fprintf(f, "# ranmar tune table: kernel log2n log2count variant\n");
+  for (auto& kv : g_table)
+    std::fprintf(f, "%d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
+  std::fclose(f);
+  return RANMAR_OK;
+}
+
+int ranmar_tune_load(const char* path) {
+  if (!path) return RANMAR_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return RANMAR_ENOENT;
+  char line[256];
+  std::map<std::tuple<int, int, int>, int> t;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int k, a, b, v;
+    if (std::sscanf(line, "%d %d %d %d", &k, &a, &b, &v) == 4) {
+      const int nv = ranmar_tune_variants(k);
+      if (nv < 0 || v < 0 || v >= nv) {
+        std::fclose(f);
+        return RANMAR_EINVAL;
+      }
+      t[{k, a, b}] = v;
+    }
+  }
+  std::fclose(f);
+  std::lock_guard<std::mutex> g(g_mu);
+  for (auto& kv : t) g_table[kv.first] = kv.second;
+  return RANMAR_OK;
+}
+
+}  // extern "C"

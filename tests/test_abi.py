@@ -1,0 +1,103 @@
+"""The C ABI: the library loads, exports every entry point the header declares,
+and rejects bad arguments on the host before any device work (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ranmar.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ranmar_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2512_00093_amd import _binding
+    return _binding.lib()
+
+
+def test_header_declares_the_hot_path():
+    names = _declared()
+    for must in ("ranmar_seed", "ranmar_jump", "ranmar_generate", "ranmar_seed_jump", "ranmar_jump_poly",
+                 "ranmar_apply_poly", "ranmar_serve_submit", "ranmar_batch_run"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    from paper_2512_00093_amd import _binding
+    assert set(_declared()) <= set(_binding._SIGS)
+
+
+def test_strerror_and_version(L):
+    from paper_2512_00093_amd import _binding as B
+    assert B.ranmar_version() >= 10000
+    for st in range(0, -8, -1):
+        assert B.ranmar_strerror(st)
+    assert B.ranmar_strerror(-99) == "unknown status"
+
+
+def test_host_seed_matches_oracle(orc):
+    """Host-side Algorithm 3 of the library against the oracle (no GPU)."""
+    from paper_2512_00093_amd import _binding as B
+    for seed in (1, 2, 12345, 4711, 900000, 900000000, 31328):
+        assert B.ranmar_seed(seed) == [int(v) for v in orc.state_from_seed(seed)]
+
+
+def test_host_seed_rejects_out_of_range():
+    from paper_2512_00093_amd import _binding as B
+    for bad in (0, -1, 900000001, 1 << 40):
+        with pytest.raises(B.RanmarError) as e:
+            B.ranmar_seed(bad)
+        assert e.value.status == B.RANMAR_EINVAL
+
+
+def test_argument_errors_before_device_work(L):
+    """Validation happens on the host: NULL pointers, bad formats, bad ld and
+    overlapping buffers return EINVAL without touching a device."""
+    from paper_2512_00093_amd import _binding as B
+    p = ctypes.c_void_p
+    EINVAL = B.RANMAR_EINVAL
+    assert L.ranmar_generate(None, None, 4, 10, 0, p(0x10000), 10, None) == EINVAL
+    assert L.ranmar_generate(p(0x10000), None, 4, 10, 7, p(0x900000), 10, None) == EINVAL      # fmt
+    assert L.ranmar_generate(p(0x10000), None, 4, 10, 0, p(0x900000), 5, None) == EINVAL       # ld < count
+    assert L.ranmar_generate(p(0x10000), None, 4, 10, 0, p(0x10004), 10, None) == EINVAL       # out overlaps states
+    assert L.ranmar_generate(p(0x10002), None, 4, 10, 0, p(0x900000), 10, None) == EINVAL      # misaligned
+    assert L.ranmar_generate(p(0x10000), p(0x10010), 4, 10, 0, p(0x900000), 10, None) == EINVAL  # partial alias
+    assert L.ranmar_jump(None, p(0x1000), 3, None) == EINVAL
+    assert L.ranmar_jump(p(0x1000), p(0x1000), 3, None) == EINVAL                              # overlap
+    assert L.ranmar_jump_poly(p(0x1004), 3, p(0x90000), None) == EINVAL                        # J misaligned
+    assert L.ranmar_seed_jump(None, None, 3, p(0x1000), None) == EINVAL
+    assert L.ranmar_seed_batch(p(0x1000), 3, p(0x1004), None) == EINVAL                        # overlap
+    assert L.ranmar_jump_family(None, B.ranmar_u128(1, 0), 3, p(0x1000), None) == EINVAL
+    # n == 0 is a no-op that succeeds without a device.
+    assert L.ranmar_generate(None, None, 0, 10, 0, None, 10, None) == 0
+    assert L.ranmar_jump(None, None, 0, None) == 0
+
+
+def test_tune_table_roundtrip(tmp_path):
+    from paper_2512_00093_amd import _binding as B
+    nv = B.ranmar_tune_variants(B.RANMAR_K_GENERATE)
+    assert nv >= 2 and all(B.ranmar_tune_variant_name(0, v) for v in range(nv))
+    assert B.lib().ranmar_tune_set(0, nv) == B.RANMAR_EINVAL
+    path = tmp_path / "tune.txt"
+    path.write_text("# test\n0 20 10 1\n0 16 12 0\n")
+    B.ranmar_tune_load(str(path))
+    out = tmp_path / "out.txt"
+    B.ranmar_tune_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "0 20 10 1" in lines and "0 16 12 0" in lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 1 1 99\n")
+    assert B.lib().ranmar_tune_load(str(bad).encode()) == B.RANMAR_EINVAL

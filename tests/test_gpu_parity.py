@@ -1,0 +1,307 @@
+"""GPU parity: every entry point of the HIP library against the CPU oracle,
+bit for bit (all arithmetic is integer; the float32 output k * 2^-24 is exact).
+
+Small cases are compared element by element at sizes that span several
+workgroups and ragged tails; the full workload sizes are compared on sampled
+streams the oracle computes one by one, and on whole-array identities between
+two GPU routes that must agree exactly (independent jumps vs. prefix-doubled
+families)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import dev, f32_words, jumps_t, limbs_t, say, seeds_t, states_t, u32
+
+pytestmark = pytest.mark.gpu
+
+R = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    global R
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_00093_amd as pkg
+    pkg.ranmar_init()
+    R = pkg
+    yield
+    torch.cuda.synchronize()
+
+
+MASK = (1 << 24) - 1
+TABLE2 = [(1 << 64) - 1, (1 << 120) - 1]
+
+
+def _rand_states(orc, n, seed=7):
+    g = synth.rng(200 + seed)
+    W = g.integers(0, 1 << 24, size=(n, 97), dtype=np.uint64).astype(np.uint32)
+    c = g.integers(0, orc.MOD, size=(n, 1), dtype=np.uint64).astype(np.uint32)
+    return np.concatenate([W, c], 1)
+
+
+# --- a1: seeding --------------------------------------------------------------
+def test_seed_batch(orc):
+    seeds = [1, 2, 3, 12345, 4711, 900000, 900000000, 30082, 30083, 177 * 30082 + 5] + \
+        [int(s) for s in synth.seeds(300, offset=11)]
+    say(f"seed_batch n={len(seeds)}")
+    out = R.ranmar_seed_batch(seeds_t(seeds))
+    torch.cuda.synchronize()
+    got = u32(out)
+    for r, s in enumerate(seeds):
+        assert np.array_equal(got[r], orc.state_from_seed(s)), s
+
+
+def test_seed_batch_invalid_marks_record():
+    say("seed_batch invalid seeds")
+    out = R.ranmar_seed_batch(seeds_t([0, -3, 900000001, 5]))
+    got = u32(out)
+    for r in range(3):
+        assert not got[r, :97].any() and got[r, 97] == 0xFFFFFFFF
+    assert got[3, 97] == 362436
+
+
+# --- a3: t^J mod phi ------------------------------------------------------------
+def test_jump_poly(orc):
+    g = synth.rng(210)
+    lo, hi = synth.u128_uniform(g, 120, 120)
+    Js = [0, 1, 2, 5, 63, 64, 65, 96, 97, 98, 129, 130, 193, 1 << 20, 10 ** 6, (1 << 128) - 1] + TABLE2 + \
+        synth.u128_to_int(lo, hi) + [int(v) for v in g.integers(0, 1 << 40, size=20)]
+    say(f"jump_poly n={len(Js)}")
+    P = u32(R.ranmar_jump_poly(jumps_t(Js)))
+    ref = orc.xpow_many(Js)
+    bad = [Js[r] for r in range(len(Js)) if not np.array_equal(P[r], ref[r])]
+    assert not bad, bad[:5]
+
+
+def test_jump_poly_waves_of_mixed_length(orc):
+    """Lanes of one wave with very different exponent lengths (the loop runs
+    over the wave's longest; short exponents carry leading zeros)."""
+    Js = [(1 << (k % 128)) + k for k in range(200)]
+    say("jump_poly mixed lengths n=200")
+    P = u32(R.ranmar_jump_poly(jumps_t(Js)))
+    ref = orc.xpow_many(Js)
+    assert np.array_equal(P, ref)
+
+
+# --- a4: apply ----------------------------------------------------------------
+def test_apply_poly(orc):
+    n = 150
+    st = _rand_states(orc, n, 1)
+    g = synth.rng(211)
+    P = g.integers(0, 1 << 24, size=(n, 97), dtype=np.uint64).astype(np.uint32)
+    P[:, :3] |= np.uint32(0xFF000000)   # high bits must be ignored
+    say(f"apply_poly n={n}")
+    d = states_t(st)
+    R.ranmar_apply_poly(d, torch.from_numpy(P.view(np.int32).copy()).to(dev()))
+    got = u32(d)
+    for r in range(n):
+        assert np.array_equal(got[r, :97], orc.apply(st[r, :97], P[r] & MASK)), r
+        assert got[r, 97] == st[r, 97]
+
+
+# --- a2-a4: jump ---------------------------------------------------------------
+def test_jump_in_place(orc):
+    n = 130
+    st = _rand_states(orc, n, 2)
+    g = synth.rng(212)
+    lo, hi = synth.u128_uniform(g, n, 120)
+    Js = synth.u128_to_int(lo, hi)
+    Js[:6] = [0, 1, 97, (1 << 128) - 1, orc.MOD, ((1 << 97) - 1) << 23]
+    say(f"jump in place n={n}")
+    d = states_t(st)
+    R.ranmar_jump(d, jumps_t(Js))
+    got = u32(d)
+    for r in range(n):
+        assert np.array_equal(got[r], orc.jump(st[r], Js[r])), (r, Js[r])
+
+
+def test_jump_small_equals_stepping(orc):
+    st0 = orc.state_from_seed(12345)
+    Js = [0, 1, 2, 31, 32, 33, 64, 96, 97, 98, 1000, 4097, 65536]
+    say("jump vs stepping")
+    d = states_t(np.tile(st0, (len(Js), 1)))
+    R.ranmar_jump(d, jumps_t(Js))
+    got = u32(d)
+    for r, J in enumerate(Js):
+        assert np.array_equal(got[r], orc.step(st0, J)), J
+
+
+def test_seed_jump(orc):
+    s, lo, hi = synth.batch_jumps(200, 120, offset=13)
+    s = s.copy()
+    s[:3] = [1, 900000000, 12345]
+    Js = synth.u128_to_int(lo, hi)
+    say("seed_jump n=200")
+    got = u32(R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi)))
+    ref = orc.seed_jump_many(s, Js)
+    assert np.array_equal(got, ref)
+    # NULL offsets: offset 0 == seeding
+    got0 = u32(R.ranmar_seed_jump(seeds_t(s[:70])))
+    assert np.array_equal(got0, np.stack([orc.state_from_seed(int(x)) for x in s[:70]]))
+
+
+def test_seed_jump_invalid_seed_leaves_marker():
+    say("seed_jump invalid seed")
+    got = u32(R.ranmar_seed_jump(seeds_t([0, 7]), jumps_t([5, 5])))
+    assert not got[0, :97].any() and got[0, 97] == 0xFFFFFFFF
+    assert got[1, 97] != 0xFFFFFFFF
+
+
+# --- a5: generation ------------------------------------------------------------
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("n", [1, 2, 3, 17])
+def test_generate_ragged(orc, fmt, n):
+    st = np.stack([orc.state_from_seed(1000 + 7 * k) for k in range(n)])
+    for count in (1, 5, 31, 32, 33, 63, 64, 65, 96, 97, 98, 100, 193, 1000, 4097):
+        say(f"generate n={n} count={count} fmt={fmt}")
+        ld = count + 3
+        d_in = states_t(st)
+        d_st = torch.full_like(d_in, -1)
+        dt = torch.float32 if fmt else torch.int32
+        out = torch.full((n, ld), -7, dtype=dt, device=dev())
+        R.ranmar_generate(d_in, count, fmt, out=out, states_out=d_st, ld=ld)
+        ref, ref_st = orc.draws_many(st, count)
+        got = u32(out)
+        want = f32_words(ref) if fmt else ref
+        assert np.array_equal(got[:, :count], want), (n, count, fmt)
+        pad = u32(torch.full((1, 1), -7, dtype=dt))[0, 0]
+        assert (got[:, count:] == pad).all()
+        assert np.array_equal(u32(d_st), ref_st), (n, count)
+
+
+def test_generate_in_place_continues_stream(orc):
+    n = 9
+    st = np.stack([orc.state_from_seed(77 + k) for k in range(n)])
+    d = states_t(st)
+    outs = []
+    for count in (40, 1, 31, 100):
+        say(f"generate in-place count={count}")
+        outs.append(u32(R.ranmar_generate(d, count, 0, states_out=d)))
+    total = sum(o.shape[1] for o in outs)
+    ref, ref_st = orc.draws_many(st, total)
+    assert np.array_equal(np.concatenate(outs, 1), ref)
+    assert np.array_equal(u32(d), ref_st)
+
+
+def test_generate_count_zero_copies():
+    st = np.arange(98 * 3, dtype=np.uint32).reshape(3, 98) % 1000
+    d_in = states_t(st)
+    d_out = torch.zeros_like(d_in)
+    say("generate count=0")
+    R.ranmar_generate(d_in, 0, 0, states_out=d_out)
+    assert np.array_equal(u32(d_out), st)
+
+
+def test_generate_variants_bit_identical(orc):
+    n, count = 64, 777
+    st = np.stack([orc.state_from_seed(5 + k) for k in range(n)])
+    ref, _ = orc.draws_many(st, count)
+    nv = R.ranmar_tune_variants(R.RANMAR_K_GENERATE)
+    try:
+        for v in range(nv):
+            say(f"generate variant {v} {R.ranmar_tune_variant_name(0, v)}")
+            R.ranmar_tune_set(R.RANMAR_K_GENERATE, v)
+            for fmt in (0, 1):
+                got = u32(R.ranmar_generate(states_t(st), count, fmt))
+                assert np.array_equal(got, f32_words(ref) if fmt else ref), (v, fmt)
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_GENERATE, -1)
+
+
+# --- stream families -----------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 100, 5000])
+def test_family_equals_independent_jumps(orc, n):
+    delta = (1 << 40) + 12345
+    base = orc.state_from_seed(4711)
+    say(f"jump_family n={n}")
+    fam = R.ranmar_jump_family(states_t(base), delta, n)
+    ind = R.ranmar_seed_jump(seeds_t([4711] * n), jumps_t([k * delta for k in range(n)]))
+    assert torch.equal(fam, ind)
+    for k in sorted({0, n - 1, n // 2, min(n - 1, 63)}):
+        assert np.array_equal(u32(fam[k]), orc.jump(base, k * delta)), k
+
+
+# --- configurations at full size -------------------------------------------------
+def test_config1_single_stream(orc):
+    p = synth.SINGLE_STREAM
+    say("config1: seed 12345, 1e6 draws, jump 2^20")
+    st = states_t(orc.state_from_seed(p["seed"]))
+    got = u32(R.ranmar_generate(st, p["draws"], 0))[0]
+    assert np.array_equal(got, orc.int_draws(p["seed"], p["draws"]))
+    d = states_t(orc.state_from_seed(p["seed"]))
+    R.ranmar_jump(d, jumps_t([p["jump"]]))
+    assert np.array_equal(u32(d)[0], orc.step(orc.state_from_seed(p["seed"]), p["jump"]))
+
+
+def test_config2_family_65k(orc):
+    p = synth.FAMILY_65K
+    n, cnt = p["streams"], p["draws"]
+    say(f"config2: {n} streams x {cnt}, offsets k*2^40")
+    lo, hi = synth.family_offsets(n, p["spacing"])
+    st = R.ranmar_seed_jump(seeds_t([p["seed"]] * n), limbs_t(lo, hi))
+    fam = R.ranmar_jump_family(states_t(orc.state_from_seed(p["seed"])), p["spacing"], n)
+    assert torch.equal(st, fam)
+    st_copy = st.clone()
+    out_u = R.ranmar_generate(st, cnt, 0)
+    out_f = R.ranmar_generate(st_copy, cnt, 1, states_out=st_copy)
+    torch.cuda.synchronize()
+    sample = synth.family_sample(n, 64)
+    base = orc.state_from_seed(p["seed"])
+    for k in sample:
+        s_k = orc.jump(base, int(k) * p["spacing"])
+        assert np.array_equal(u32(st[k]), s_k), k
+        ref, ref_st = orc.draws_many(s_k[None], cnt)
+        assert np.array_equal(u32(out_u[k]), ref[0]), k
+        assert np.array_equal(u32(out_f[k]), f32_words(ref[0])), k
+        assert np.array_equal(u32(st_copy[k]), ref_st[0]), k
+    # Properties over every stream: range of the words and exact float values.
+    assert int(out_u.min()) >= 0 and int(out_u.max()) <= MASK
+    assert torch.equal(out_u.to(torch.float64) * 2.0 ** -24, out_f.to(torch.float64))
+
+
+def test_config3_bulk_states_and_sample(orc):
+    p = synth.BULK_1M
+    n, cnt = p["streams"], p["draws"]
+    say(f"config3: {n} streams at k*2^100, {cnt} f32 draws")
+    base = orc.state_from_seed(p["seed"])
+    fam = R.ranmar_jump_family(states_t(base), p["spacing"], n)
+    lo, hi = synth.family_offsets(n, p["spacing"])
+    ind = R.ranmar_seed_jump(seeds_t(np.full(n, p["seed"], np.int32)), limbs_t(lo, hi))
+    assert torch.equal(fam, ind)
+    del ind
+    out = R.ranmar_generate(fam, cnt, 1)
+    torch.cuda.synchronize()
+    for k in synth.family_sample(n, 32, offset=3):
+        s_k = orc.jump(base, int(k) * p["spacing"])
+        assert np.array_equal(u32(fam[k]), s_k), k
+        ref, _ = orc.draws_many(s_k[None], cnt)
+        assert np.array_equal(u32(out[k]), f32_words(ref[0])), k
+    # every value is a multiple of 2^-24 in [0, 1)
+    assert float(out.min()) >= 0.0 and float(out.max()) < 1.0
+    assert torch.equal(torch.floor(out.double() * 2 ** 24), out.double() * 2 ** 24)
+
+
+def test_config4_batched_jumps_sample(orc):
+    n = synth.BATCH_JUMPS["requests"]
+    s, lo, hi = synth.batch_jumps(n, 120, offset=4)
+    say(f"config4: {n} seed+jump requests, 120-bit J")
+    out = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
+    torch.cuda.synchronize()
+    g = synth.rng(214)
+    idx = np.unique(np.concatenate([[0, n - 1], g.choice(n, 200, replace=False)]))
+    Js = synth.u128_to_int(lo[idx], hi[idx])
+    ref = orc.seed_jump_many(s[idx], Js)
+    assert np.array_equal(u32(out[torch.from_numpy(idx).to(dev())]), ref)
+    w = u32(out)
+    assert w[:, :97].max() <= MASK and w[:, 97].max() < orc.MOD
+
+
+def test_repeatable(orc):
+    s, lo, hi = synth.batch_jumps(1000, 120, offset=15)
+    say("repeatability")
+    a = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
+    b = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
+    assert torch.equal(a, b)
+    assert torch.equal(R.ranmar_generate(a, 333, 1), R.ranmar_generate(b, 333, 1))
