@@ -45,6 +45,8 @@ def _parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -270,6 +272,13 @@ def main():
     import paper_2512_00093_amd as R
     torch.cuda.set_device(0)
     R.ranmar_init()
+    if a.profile_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if a.workload == "family65k":
         res = run_family65k(R, torch, a.steps, a.warmup, a.jump)
     elif a.workload == "bulk1m":

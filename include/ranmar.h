@@ -122,9 +122,9 @@ int ranmar_seed_batch(const int32_t *d_seeds, uint64_t n, ranmar_state *d_out, v
 int ranmar_jump_poly(const ranmar_u128 *d_J, uint64_t n, uint32_t *d_P, void *stream);
 
 /* a4: in place, x <- x P(A) for each state, with P = d_P[r*97 .. r*97+96]
- * (Horner's rule of Sec. 3.1, equal to applying f_1 sum-of-powers); c is not
- * changed.  d_states: n records; d_P: 97*n uint32 (values are taken mod
- * 2^24). */
+ * and A the companion matrix of the lagged Fibonacci step (Horner's rule of
+ * Sec. 3.1: x P(A) = sum_i b_i x A^i); c is not changed.  d_states: n
+ * records; d_P: 97*n uint32 (values are taken mod 2^24). */
 int ranmar_apply_poly(ranmar_state *d_states, const uint32_t *d_P, uint64_t n, void *stream);
 
 /* a2+a3+a4: in place, d_states[r] <- f^J(d_states[r]) with J = d_J[r]:
@@ -143,8 +143,9 @@ int ranmar_seed_jump(const int32_t *d_seeds, const ranmar_u128 *d_offsets, uint6
  * for k < n, i.e. unit k starts at state s_{k*delta}.  Computed on the GPU
  * by prefix doubling with the exact jump: the starts of units [2^b, 2^(b+1))
  * are those of [0, 2^b) jumped by 2^b*delta; bit-identical to n separate
- * jumps.  k*delta is taken mod 2^128.  d_base: 1 record (may lie inside
- * d_out only as d_out[0]). */
+ * jumps.  The exponent k*delta is used exactly (it may exceed 2^128, unlike the
+ * J of ranmar_jump).  d_base: 1 record (may lie inside d_out only as
+ * d_out[0]). */
 int ranmar_jump_family(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n,
                        ranmar_state *d_out, void *stream);
 
@@ -208,11 +209,14 @@ int ranmar_batch_destroy(ranmar_batch *b);
 /* ------------------------------------------------------------------------ */
 
 typedef struct ranmar_serve_cfg {
-    uint64_t max_inflight;   /* requests admitted but not released (>= 1) */
-    uint64_t chunk_draws;    /* draws per chunk (0 = tuned default) */
-    uint64_t max_tick_chunks;/* chunks per launch (0 = default) */
+    uint64_t max_inflight;   /* requests admitted but not released (0 = 65536) */
+    uint64_t chunk_draws;    /* draws per chunk (0 = 16384) */
+    uint64_t max_tick_chunks;/* chunks per launch (0 = 4096) */
     uint32_t lanes;          /* concurrent HIP streams for ticks (1..8, 0 = 2) */
     uint32_t queue_when_full;/* 1: over-budget requests wait; 0: EAGAIN */
+    uint32_t unbatched;      /* 1: no batching -- each request is one launch of
+                                its own (the baseline); 0: continuous batching */
+    uint32_t reserved;
 } ranmar_serve_cfg;
 
 typedef struct ranmar_serve_stats {
@@ -261,6 +265,16 @@ int ranmar_serve_stats_get(ranmar_server *s, ranmar_serve_stats *out);
 /* Stops the server after draining admitted work; outstanding tickets are
  * released. */
 int ranmar_serve_destroy(ranmar_server *s);
+
+/* Open-loop load driver (benchmark support): submits request r at
+ * t_arrival_s[r] seconds after the call starts (a schedule, not a wait for
+ * the previous request), releases every request as soon as it completes, and
+ * returns when all are released.  Latency of request r, from its scheduled
+ * arrival to the server observing its completion, goes to latency_ns[r]
+ * (may be NULL).  Host arrays of n entries; t_arrival_s non-decreasing.
+ * Returns the first error of any submission (RANMAR_EINVAL, RANMAR_ENOMEM). */
+int ranmar_serve_replay(ranmar_server *s, uint64_t n, const double *t_arrival_s, const int32_t *seeds,
+                        const ranmar_u128 *offsets, const uint64_t *counts, int fmt, double *latency_ns);
 
 /* ------------------------------------------------------------------------ */
 /* Tuning                                                                     */

@@ -60,7 +60,8 @@ class ranmar_request(ctypes.Structure):
 class ranmar_serve_cfg(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_uint64), ("chunk_draws", ctypes.c_uint64),
                 ("max_tick_chunks", ctypes.c_uint64), ("lanes", ctypes.c_uint32),
-                ("queue_when_full", ctypes.c_uint32)]
+                ("queue_when_full", ctypes.c_uint32), ("unbatched", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class ranmar_serve_stats(ctypes.Structure):
@@ -101,6 +102,7 @@ _SIGS = {
     "ranmar_serve_release": (_int, [_vp, _u64]),
     "ranmar_serve_stats_get": (_int, [_vp, ctypes.POINTER(ranmar_serve_stats)]),
     "ranmar_serve_destroy": (_int, [_vp]),
+    "ranmar_serve_replay": (_int, [_vp, _u64, _vp, _vp, _vp, _vp, _int, _vp]),
     "ranmar_tune_variants": (_int, [_int]),
     "ranmar_tune_variant_name": (ctypes.c_char_p, [_int, _int]),
     "ranmar_tune_set": (_int, [_int, _int]),
@@ -314,6 +316,20 @@ def ranmar_serve_stats_get(server) -> ranmar_serve_stats:
 
 def ranmar_serve_destroy(server):
     return _check(lib().ranmar_serve_destroy(server), "ranmar_serve_destroy")
+
+
+def ranmar_serve_replay(server, t_arrival_s, seeds, off_lo, off_hi, counts, fmt: int = RANMAR_F32):
+    """Open-loop replay of a request trace (numpy arrays); returns latencies in ns."""
+    import numpy as np
+    n = len(seeds)
+    t = np.ascontiguousarray(t_arrival_s, np.float64)
+    s = np.ascontiguousarray(seeds, np.int32)
+    off = np.ascontiguousarray(np.stack([np.asarray(off_lo, np.uint64), np.asarray(off_hi, np.uint64)], 1))
+    c = np.ascontiguousarray(counts, np.uint64)
+    lat = np.zeros(n, np.float64)
+    _check(lib().ranmar_serve_replay(server, n, t.ctypes.data, s.ctypes.data, off.ctypes.data, c.ctypes.data, fmt,
+                                     lat.ctypes.data), "ranmar_serve_replay")
+    return lat
 
 
 # --- tuning ----------------------------------------------------------------

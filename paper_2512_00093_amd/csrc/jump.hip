@@ -85,23 +85,7 @@ __global__ __launch_bounds__(64, 2) void k_jump(uint32_t* __restrict__ states, c
   }
   uint32_t j0, j1, j2, j3;
   load_j(J, r, valid, j0, j1, j2, j3);
-
-  uint32_t a[97];
-  xpow_lane(j0, j1, j2, j3, a);
-
-  if (valid) {
-    uint32_t u[97], v[97];
-#pragma unroll
-    for (int k = 0; k < 97; ++k) u[k] = slot[k];
-    const uint32_t c = slot[97];
-    // Park P in the record while the state words sit in registers.
-#pragma unroll
-    for (int k = 0; k < 97; ++k) slot[k] = a[k];
-    horner_apply(u, slot, 1, v);
-#pragma unroll
-    for (int k = 0; k < 97; ++k) slot[k] = v[k] & kMask;
-    slot[97] = c_jump(c, u128_mod_m(j0, j1, j2, j3));
-  }
+  jump_record_lane(slot, valid, j0, j1, j2, j3);
 }
 
 // ---------------------------------------------------------------------------

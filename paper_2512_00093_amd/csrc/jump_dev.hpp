@@ -170,5 +170,26 @@ __device__ __forceinline__ void horner_apply(const uint32_t (&u)[97], const uint
   }
 }
 
+// In-place f^J on one state record per lane (valid lanes only; every lane of
+// the wave must call it, since the powering loop is wave-uniform).  The jump
+// polynomial is parked in the record itself while the state words are held in
+// registers, so no workspace is needed.
+__device__ __forceinline__ void jump_record_lane(uint32_t* slot, bool valid, uint32_t j0, uint32_t j1, uint32_t j2,
+                                                 uint32_t j3) {
+  uint32_t a[97];
+  xpow_lane(j0, j1, j2, j3, a);
+  if (valid) {
+    uint32_t u[97], v[97];
+#pragma unroll
+    for (int k = 0; k < 97; ++k) u[k] = slot[k];
+    const uint32_t c = slot[97];
+#pragma unroll
+    for (int k = 0; k < 97; ++k) slot[k] = a[k];
+    horner_apply(u, slot, 1, v);
+#pragma unroll
+    for (int k = 0; k < 97; ++k) slot[k] = v[k] & kMask;
+    slot[97] = c_jump(c, u128_mod_m(j0, j1, j2, j3));
+  }
+}
 
 }  // namespace ranmar

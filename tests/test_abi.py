@@ -101,3 +101,21 @@ def test_tune_table_roundtrip(tmp_path):
     bad = tmp_path / "bad.txt"
     bad.write_text("0 1 1 99\n")
     assert B.lib().ranmar_tune_load(str(bad).encode()) == B.RANMAR_EINVAL
+
+
+def test_batch_and_serve_argument_errors(L):
+    """Handles and pointers are checked before any device work."""
+    from paper_2512_00093_amd import _binding as B
+    h = ctypes.c_void_p()
+    assert L.ranmar_batch_create(0, 10, 0, ctypes.byref(h)) == B.RANMAR_EINVAL
+    assert L.ranmar_batch_create(10, 10, 1 << 30, ctypes.byref(h)) == B.RANMAR_EINVAL
+    assert L.ranmar_batch_run(None, None, 1, None) == B.RANMAR_EINVAL
+    assert L.ranmar_batch_destroy(None) == B.RANMAR_EINVAL
+    assert L.ranmar_run_unbatched(None, 3, None) == B.RANMAR_EINVAL
+    assert L.ranmar_serve_create(None, 1 << 20, None, ctypes.byref(h)) == B.RANMAR_EINVAL
+    assert L.ranmar_serve_create(ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(h)) == B.RANMAR_EINVAL
+    t = ctypes.c_uint64()
+    assert L.ranmar_serve_submit(None, 1, B.ranmar_u128(0, 0), 10, 0, 0, ctypes.byref(t)) == B.RANMAR_EINVAL
+    assert L.ranmar_serve_release(None, 1) == B.RANMAR_EINVAL
+    assert L.ranmar_serve_destroy(None) == B.RANMAR_EINVAL
+    assert L.ranmar_serve_replay(None, 1, None, None, None, None, 0, None) == B.RANMAR_EINVAL

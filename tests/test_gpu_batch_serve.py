@@ -1,0 +1,279 @@
+"""Batched execution (one persistent, graph-launched kernel for uneven
+requests) and serving (continuous batching under an HBM budget), bit for bit
+against the oracle and against the same requests run alone."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import dev, f32_words, say, states_t, u32
+
+pytestmark = pytest.mark.gpu
+
+R = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    global R
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_00093_amd as pkg
+    pkg.ranmar_init()
+    R = pkg
+    yield
+    torch.cuda.synchronize()
+
+
+def _mixed_requests(k, seed_off, max_count=120_000, with_zero=True):
+    g = synth.rng(300 + seed_off)
+    seeds = g.integers(1, 900_000_001, size=k)
+    lo, hi = synth.u128_uniform(g, k, 120)
+    counts = np.floor(10 ** g.uniform(0, np.log10(max_count), size=k)).astype(np.int64)
+    counts[:6] = [1, 31, 16384, 16385, 32768 + 5, 100_000][:min(6, k)]
+    if with_zero and k > 7:
+        counts[7] = 0
+    fmts = g.integers(0, 2, size=k)
+    return [dict(seed=int(seeds[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=int(counts[i]),
+                 fmt=int(fmts[i])) for i in range(k)]
+
+
+def _alloc(items):
+    for it in items:
+        dt = torch.float32 if it["fmt"] else torch.int32
+        it["out"] = torch.full((max(it["count"], 1),), -3, dtype=dt, device=dev())
+        it["state"] = torch.zeros(98, dtype=torch.int32, device=dev())
+    return items
+
+
+def _check(orc, items, sample=None):
+    idx = range(len(items)) if sample is None else sample
+    for r in idx:
+        it = items[r]
+        st0 = orc.seed_jump_many([it["seed"]], [it["offset"]])[0]
+        ref, ref_st = orc.draws_many(st0[None], it["count"])
+        got = u32(it["out"])[:it["count"]]
+        want = f32_words(ref[0]) if it["fmt"] else ref[0]
+        assert np.array_equal(got, want), (r, it["count"], it["fmt"])
+        assert np.array_equal(u32(it["state"]), ref_st[0]), (r, it["count"])
+
+
+def test_batch_matches_oracle(orc):
+    items = _alloc(_mixed_requests(40, 1))
+    b = R.ranmar_batch_create(64, 4096)
+    try:
+        say(f"batch_run n={len(items)} draws={sum(i['count'] for i in items)}")
+        R.ranmar_batch_run(b, R.make_requests(items))
+        torch.cuda.synchronize()
+        _check(orc, items)
+    finally:
+        R.ranmar_batch_destroy(b)
+
+
+def test_batch_graph_replays_with_eager_work_between(orc):
+    """The captured graph is replayed several times, with the program's own
+    eager launches and synchronisations in between; every replay is checked."""
+    b = R.ranmar_batch_create(200, 2048, 4096)
+    try:
+        for rep in range(4):
+            items = _alloc(_mixed_requests(30 + 40 * (rep % 2), 10 + rep, max_count=40_000))
+            say(f"graph replay {rep}: n={len(items)}")
+            R.ranmar_batch_run(b, R.make_requests(items))
+            # eager work between replays
+            st = states_t(np.stack([orc.state_from_seed(99 + rep)]))
+            eager = R.ranmar_generate(st, 1000, 0)
+            torch.cuda.synchronize()
+            assert np.array_equal(u32(eager)[0], orc.int_draws(99 + rep, 1000))
+            _check(orc, items)
+    finally:
+        R.ranmar_batch_destroy(b)
+
+
+def test_batch_many_jumps_one_launch(orc):
+    """Jump-only requests (count 0, state out): the batched-jump workload."""
+    n = 5000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=21)
+    out = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+    items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                  state=out[i]) for i in range(n)]
+    b = R.ranmar_batch_create(n, 1)
+    try:
+        say(f"batch jumps n={n}")
+        R.ranmar_batch_run(b, R.make_requests(items))
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+    direct = R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev()))
+    assert torch.equal(out, direct)
+    idx = [0, 1, 77, n - 1]
+    ref = orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx]))
+    assert np.array_equal(u32(out)[idx], ref)
+
+
+def test_unbatched_matches_batched(orc):
+    items_a = _alloc(_mixed_requests(20, 2))
+    items_b = _alloc([{k: v for k, v in it.items() if k in ("seed", "offset", "count", "fmt")} for it in items_a])
+    b = R.ranmar_batch_create(32, 1024)
+    try:
+        say("batched vs one launch per request")
+        R.ranmar_batch_run(b, R.make_requests(items_a))
+        R.ranmar_run_unbatched(R.make_requests(items_b))
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+    for x, y in zip(items_a, items_b):
+        assert torch.equal(x["out"], y["out"]) and torch.equal(x["state"], y["state"])
+    _check(orc, items_b, sample=[0, 3, 5, 7])
+
+
+def test_batch_capacity_and_argument_errors():
+    b = R.ranmar_batch_create(4, 8, 1024)
+    try:
+        out = torch.zeros(10_000, dtype=torch.int32, device=dev())
+        ok = dict(seed=5, offset=0, count=100, fmt=0, out=out, state=None)
+        with pytest.raises(R.RanmarError) as e:
+            R.ranmar_batch_run(b, R.make_requests([ok] * 5))           # more requests than capacity
+        assert e.value.status == R.RANMAR_ENOMEM
+        with pytest.raises(R.RanmarError) as e:
+            R.ranmar_batch_run(b, R.make_requests([dict(ok, count=9 * 1024)]))   # more chunks than capacity
+        assert e.value.status == R.RANMAR_ENOMEM
+        for bad in (dict(ok, seed=0), dict(ok, fmt=3), dict(ok, out=None)):
+            with pytest.raises(R.RanmarError) as e:
+                R.ranmar_batch_run(b, R.make_requests([bad]))
+            assert e.value.status == R.RANMAR_EINVAL
+        R.ranmar_batch_run(b, R.make_requests([ok]))
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+
+
+# --- serving -----------------------------------------------------------------
+def _server(arena_bytes, **cfg):
+    arena = torch.empty(arena_bytes // 4, dtype=torch.int32, device=dev())
+    c = R.ranmar_serve_cfg()
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    return R.ranmar_serve_create(arena, c), arena
+
+
+def _result(server, arena, ticket, fmt):
+    ptr, cnt = R.ranmar_serve_result(server, ticket)
+    off = (ptr - arena.data_ptr()) // 4
+    words = u32(arena[off:off + cnt])
+    return words
+
+
+def test_serve_results_match_oracle_and_alone(orc):
+    reqs = _mixed_requests(60, 3, max_count=300_000)
+    srv, arena = _server(256 << 20, max_tick_chunks=16, chunk_draws=4096, lanes=3, queue_when_full=1)
+    outs = {}
+    try:
+        say(f"serve mix n={len(reqs)}")
+        tickets = []
+        for it in reqs:
+            st, t = R.ranmar_serve_submit(srv, it["seed"], it["offset"], it["count"], it["fmt"])
+            assert st == 0
+            tickets.append(t)
+        for r, t in enumerate(tickets):
+            assert R.ranmar_serve_wait(srv, t, 30_000_000_000) == 0
+            outs[r] = _result(srv, arena, t, reqs[r]["fmt"])
+            R.ranmar_serve_release(srv, t)
+        s = R.ranmar_serve_stats_get(srv)
+        assert s.completed == len(reqs) and s.released == len(reqs) and s.bytes_in_use == 0
+        assert s.ticks > 1 and s.p99_ns >= s.p50_ns > 0
+    finally:
+        R.ranmar_serve_destroy(srv)
+    # each result equals the oracle ...
+    for r in range(0, len(reqs), 3):
+        it = reqs[r]
+        st0 = orc.seed_jump_many([it["seed"]], [it["offset"]])[0]
+        ref, _ = orc.draws_many(st0[None], it["count"])
+        assert np.array_equal(outs[r], f32_words(ref[0]) if it["fmt"] else ref[0]), r
+    # ... and the same request served alone gives the same bits.
+    srv2, arena2 = _server(64 << 20, lanes=1)
+    try:
+        for r in (0, 4, 5, 11, 30):
+            it = reqs[r]
+            st, t = R.ranmar_serve_submit(srv2, it["seed"], it["offset"], it["count"], it["fmt"])
+            assert st == 0
+            assert R.ranmar_serve_wait(srv2, t) == 0
+            assert np.array_equal(_result(srv2, arena2, t, it["fmt"]), outs[r]), r
+            R.ranmar_serve_release(srv2, t)
+    finally:
+        R.ranmar_serve_destroy(srv2)
+
+
+def test_serve_budget_admission():
+    srv, arena = _server(1 << 20, queue_when_full=0, lanes=1)
+    try:
+        st, _ = R.ranmar_serve_submit(srv, 7, 0, (1 << 20) // 4 + 1, 1)
+        assert st == R.RANMAR_ENOMEM                       # never fits the budget
+        st, t1 = R.ranmar_serve_submit(srv, 7, 0, 200_000, 1)
+        assert st == 0
+        R.ranmar_serve_wait(srv, t1)
+        st, _ = R.ranmar_serve_submit(srv, 8, 0, 100_000, 1)
+        assert st == R.RANMAR_EAGAIN                       # budget held by t1 until released
+        R.ranmar_serve_release(srv, t1)
+        st, t2 = R.ranmar_serve_submit(srv, 8, 0, 100_000, 1)
+        assert st == 0
+        R.ranmar_serve_wait(srv, t2)
+        R.ranmar_serve_release(srv, t2)
+        assert R.ranmar_serve_stats_get(srv).rejected == 2
+    finally:
+        R.ranmar_serve_destroy(srv)
+    # With queueing, over-budget requests wait for releases and then run.
+    srv, arena = _server(1 << 20, queue_when_full=1, lanes=2)
+    try:
+        sub = [R.ranmar_serve_submit(srv, 9 + i, i, 150_000, 0) for i in range(4)]
+        assert all(st == 0 for st, _ in sub)
+        ts = [t for _, t in sub]
+        R.ranmar_serve_wait(srv, ts[0])
+        assert not R.ranmar_serve_poll(srv, ts[3])     # 4 x 600 KB cannot all fit 1 MiB
+        for t in ts:
+            R.ranmar_serve_wait(srv, t)
+            R.ranmar_serve_release(srv, t)
+        s = R.ranmar_serve_stats_get(srv)
+        assert s.bytes_peak <= 1 << 20 and s.completed == 4
+    finally:
+        R.ranmar_serve_destroy(srv)
+
+
+def test_serve_unbatched_same_bits(orc):
+    reqs = _mixed_requests(12, 4, max_count=80_000, with_zero=False)
+    res = []
+    for unb in (0, 1):
+        srv, arena = _server(64 << 20, unbatched=unb, lanes=2)
+        outs = []
+        try:
+            sub = [R.ranmar_serve_submit(srv, it["seed"], it["offset"], it["count"], it["fmt"]) for it in reqs]
+            assert all(st == 0 for st, _ in sub)
+            ts = [t for _, t in sub]
+            for it, t in zip(reqs, ts):
+                R.ranmar_serve_wait(srv, t)
+                outs.append(_result(srv, arena, t, it["fmt"]))
+                R.ranmar_serve_release(srv, t)
+        finally:
+            R.ranmar_serve_destroy(srv)
+        res.append(outs)
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_serve_replay_driver():
+    n = 400
+    tr = synth.serve_requests(n, qps=20_000, offset=31, count_log10=(2.0, 5.0))
+    srv, arena = _server(512 << 20, lanes=2)
+    try:
+        say(f"replay n={n}")
+        t0 = time.time()
+        lat = R.ranmar_serve_replay(srv, tr["arrival"], tr["seeds"], tr["off_lo"], tr["off_hi"], tr["counts"])
+        wall = time.time() - t0
+        s = R.ranmar_serve_stats_get(srv)
+    finally:
+        R.ranmar_serve_destroy(srv)
+    assert s.completed == n and s.released == n and s.bytes_in_use == 0
+    assert (lat > 0).all() and wall < 30
+    assert s.draws == int(tr["counts"].sum())
