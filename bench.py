@@ -39,7 +39,10 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="family65k", choices=["family65k", "bulk1m", "jumps1m"])
+    ap.add_argument("--workload", default="family65k", choices=["family65k", "bulk1m", "jumps1m", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=synth.SERVE["requests"])
+    ap.add_argument("--serve-qps", type=float, default=1e5)
+    ap.add_argument("--serve-baseline-requests", type=int, default=2000)
     ap.add_argument("--jump", default="family", choices=["family", "lanes"],
                     help="family65k: stream starts by prefix doubling or one jump per stream")
     ap.add_argument("--no-extras", action="store_true")
@@ -261,6 +264,81 @@ def run_jumps1m(R, torch, steps, warmup):
     }
 
 
+def run_jumps1m_batched(R, torch, steps, warmup):
+    """The 10^6 seed+jump requests through the batch executor: one persistent,
+    graph-launched kernel (count 0, state out)."""
+    import numpy as np
+    n = synth.BATCH_JUMPS["requests"]
+    s, lo, hi = synth.batch_jumps(n, 120, offset=4)
+    dev = torch.device("cuda:0")
+    out = torch.empty((n, 98), dtype=torch.int32, device=dev)
+    reqs = (R.ranmar_request * n)()
+    base = out.data_ptr()
+    for i in range(n):
+        reqs[i].seed = int(s[i])
+        reqs[i].fmt = 0
+        reqs[i].offset.lo = int(lo[i])
+        reqs[i].offset.hi = int(hi[i])
+        reqs[i].count = 0
+        reqs[i].d_out = None
+        reqs[i].d_state = base + 392 * i
+    b = R.ranmar_batch_create(n, 1)
+    tm = Timer(torch)
+    try:
+        for _ in range(warmup):
+            R.ranmar_batch_run(b, reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a, e = tm.span("run")
+            a.record()
+            R.ranmar_batch_run(b, reqs)
+            e.record()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+    finally:
+        R.ranmar_batch_destroy(b)
+    return {"value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3,
+            "launch_ms": tm.mean_ms("run"),
+            "config": {"workload": "jumps1m through the batch executor: one graph launch (descriptor copy + "
+                                   "persistent kernel) of 10^6 seed+jump requests"}}
+
+
+def run_serve(R, torch, n_req, qps, n_base):
+    """Open-loop serving: Poisson arrivals, log-uniform counts, 64 GiB budget."""
+    import numpy as np
+    tr = synth.serve_requests(n_req, qps=qps, offset=5)
+    dev = torch.device("cuda:0")
+    arena = torch.empty(synth.SERVE["budget_bytes"] // 4, dtype=torch.int32, device=dev)
+    out = {}
+    for mode, n in (("batched", n_req), ("one_launch_per_request", min(n_base, n_req))):
+        cfg = R.ranmar_serve_cfg()
+        cfg.queue_when_full = 1
+        cfg.lanes = 4 if mode == "batched" else 2
+        cfg.unbatched = 1 if mode != "batched" else 0
+        srv = R.ranmar_serve_create(arena, cfg)
+        try:
+            t0 = time.perf_counter()
+            lat = R.ranmar_serve_replay(srv, tr["arrival"][:n], tr["seeds"][:n], tr["off_lo"][:n], tr["off_hi"][:n],
+                                        tr["counts"][:n], R.RANMAR_F32)
+            wall = time.perf_counter() - t0
+            st = R.ranmar_serve_stats_get(srv)
+        finally:
+            R.ranmar_serve_destroy(srv)
+        draws = float(tr["counts"][:n].sum())
+        out[mode] = {"requests": n, "qps_offered": qps, "p50_ms": float(np.percentile(lat, 50)) / 1e6,
+                     "p99_ms": float(np.percentile(lat, 99)) / 1e6, "max_ms": float(lat.max()) / 1e6,
+                     "draws": draws, "draws_per_s": draws / wall, "wall_s": wall, "ticks": int(st.ticks),
+                     "arena_peak_GiB": st.bytes_peak / 2 ** 30}
+    del arena
+    torch.cuda.synchronize()
+    return {"value": out["batched"]["draws_per_s"], "unit": "draws/s", "serve": out,
+            "config": {"workload": f"serve: {n_req} requests, Poisson arrivals at {qps:g}/s, seed uniform on "
+                                   "[1, 9e8], offset uniform on [0, 2^120), count log-uniform on [1e2, 1e7], "
+                                   "float32 output, 64 GiB budget; baseline = first "
+                                   f"{min(n_base, n_req)} requests served one launch per request"}}
+
+
 def main():
     a = _parse()
     if a.gpus != 1:
@@ -283,6 +361,12 @@ def main():
         res = run_family65k(R, torch, a.steps, a.warmup, a.jump)
     elif a.workload == "bulk1m":
         res = run_bulk1m(R, torch, a.steps, a.warmup)
+    elif a.workload == "serve":
+        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_baseline_requests)
+        print(json.dumps({"metric": "served draws/s (p50/p99 latency)", "value": r["value"], "unit": r["unit"],
+                          "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "config": r["config"],
+                          "serve": r["serve"]}), flush=True)
+        return
     else:
         res = run_jumps1m(R, torch, a.steps, a.warmup)
     line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"], "n_gpus": 1, "steps": a.steps,
@@ -297,6 +381,9 @@ def main():
         for name, fn in (("bulk1m", run_bulk1m), ("jumps1m", run_jumps1m)):
             r = fn(R, torch, 10, 2)
             also[name] = {k: r[k] for k in r if k not in ("metric",)}
+        also["jumps1m_batched"] = run_jumps1m_batched(R, torch, 5, 1)
+        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_baseline_requests)
+        also["serve"] = {"config": r["config"], **r["serve"]}
         line["also"] = also
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)

@@ -23,19 +23,24 @@
 
 namespace ranmar {
 
-__global__ __launch_bounds__(64, 2) void k_batch_tables(const uint8_t* __restrict__ desc, BatchBuffers B) {
+__global__ __launch_bounds__(64) void k_batch_tables(const uint8_t* __restrict__ desc, BatchBuffers B) {
   batch_persistent(TableDesc{desc}, B);
 }
 
-__global__ __launch_bounds__(64, 2) void k_batch_single(SingleDesc d, BatchBuffers B) { batch_persistent(d, B); }
+__global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers B) { batch_persistent(d, B); }
 
 constexpr uint32_t kDefaultChunk = 16384;
 constexpr uint32_t kMaxChunkDraws = 1u << 24;
 
+// Workgroups that fit the device at once (the kernel's occupancy times the
+// number of CUs): every workgroup of the persistent grid is resident.
 static unsigned persistent_grid() {
-  int dev = 0, cus = 256;
+  int dev = 0, cus = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return (unsigned)(cus > 0 ? cus : 256) * 8u;  // two one-wave workgroups per SIMD
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_tables, 64, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 8;
+  return (unsigned)(cus > 0 ? cus : 256) * (unsigned)per_cu;
 }
 
 // P_{qL} for q < nq into ptab (97 words each), on `st`.
@@ -130,7 +135,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   b->L = chunk_draws ? (uint32_t)chunk_draws : kDefaultChunk;
   b->desc_cap = 64 + sizeof(BReq) * b->max_req + 16 + sizeof(BChunk) * b->max_chunks;
   b->grid = persistent_grid();
-  const uint64_t ngroups = (b->max_req + 63) / 64;
+  const uint64_t ngroups = b->max_req + 1;  // request flags + the spare
   hipStream_t st = nullptr;
   bool ok = hipMalloc(&b->d_desc, b->desc_cap) == hipSuccess &&
             hipHostMalloc(&b->h_desc, b->desc_cap, hipHostMallocDefault) == hipSuccess &&
@@ -151,6 +156,11 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
     b->B.ptab = b->d_ptab;
     b->B.queue = b->d_queue;
     b->B.err = b->h_err;
+    b->B.wtab = window_table();
+    b->B.spare = (uint32_t)b->max_req;
+    ok = b->B.wtab != nullptr;
+  }
+  if (ok) {
     b->kdesc = b->d_desc;
     ok = hipGraphCreate(&b->graph, 0) == hipSuccess &&
          hipGraphAddMemcpyNode1D(&b->cpy, b->graph, nullptr, 0, b->d_desc, b->h_desc, b->desc_cap,
@@ -199,7 +209,7 @@ int ranmar_batch_run(ranmar_batch* b, const ranmar_request* reqs, uint64_t n, vo
   BHeader* h = (BHeader*)b->h_desc;
   std::memset(h, 0, sizeof(BHeader));
   h->n_req = (uint32_t)n;
-  h->n_jg = (uint32_t)((n + 63) / 64);
+  h->n_jg = (uint32_t)((n + 1) / 2);
   h->n_chunks = (uint32_t)total;
   h->n_cg = (uint32_t)((total + 1) / 2);
   h->epoch = ++b->epoch;
@@ -252,12 +262,12 @@ std::map<std::pair<int, uintptr_t>, UnbatchedCtx> g_ub;
 
 int ub_reserve(UnbatchedCtx& c, uint64_t nq, hipStream_t st) {
   if (!c.req_states) {
-    if (hipMalloc(&c.req_states, 4 * kWords) != hipSuccess || hipMalloc(&c.done, 4) != hipSuccess ||
+    if (hipMalloc(&c.req_states, 4 * kWords) != hipSuccess || hipMalloc(&c.done, 8) != hipSuccess ||
         hipMalloc(&c.queue, 8) != hipSuccess ||
         hipHostMalloc(&c.err, sizeof(int), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
       return RANMAR_EHIP;
     *c.err = 0;
-    if (hipMemsetAsync(c.done, 0, 4, st) != hipSuccess || hipMemsetAsync(c.queue, 0, 8, st) != hipSuccess)
+    if (hipMemsetAsync(c.done, 0, 8, st) != hipSuccess || hipMemsetAsync(c.queue, 0, 8, st) != hipSuccess)
       return RANMAR_EHIP;
   }
   if (nq > c.cap_chunks) {
@@ -304,7 +314,8 @@ extern "C" int ranmar_run_unbatched(const ranmar_request* reqs, uint64_t n, void
     d.r0 = to_breq(reqs[r]);
     d.L = kDefaultChunk;
     d.epoch = ++c.epoch;
-    BatchBuffers B{c.req_states, c.done, c.ptab, c.queue, c.err};
+    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), c.queue, c.err, 1u};
+    if (!B.wtab) return RANMAR_ENOMEM;
     const uint64_t items = 1 + (nq + 1) / 2;
     const unsigned grid = (unsigned)(items < maxgrid ? items : maxgrid);
     hipLaunchKernelGGL(k_batch_single, dim3(grid), dim3(64), 0, st, d, B);

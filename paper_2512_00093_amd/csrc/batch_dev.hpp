@@ -9,22 +9,22 @@
 // chunk's draws are exactly those of the request's single stream.
 //
 // Work items, taken in order from an atomic counter by one-wave workgroups:
-//   [0, n_jg)           jump groups: 64 requests, one per lane (seed + jump);
+//   [0, n_jg)           jump pairs: each half-wave seeds one request and jumps
+//                       it to its offset (parallel seeding and the windowed
+//                       jump of coop_dev.hpp), then raises the request's flag;
 //   [n_jg, n_jg + n_cg) chunk pairs: each half-wave places one chunk start
-//                       (the Hankel product of P_{qL} with the request's
-//                       window extended by 96 steps, in LDS) and generates the
-//                       chunk's draws.
-// A chunk group waits for the flag of each of its requests' jump groups
-// (flag == run epoch, so flags never need clearing).  All jump groups precede
-// all chunk groups in the queue, so the group a chunk waits for has already
-// been taken by a running wave; the wait is still bounded, and a wait that
-// runs out sets the host-visible error word instead of hanging.
+//                       (P_{qL} applied to the request's start state, in LDS)
+//                       and generates the chunk's draws.
+// A chunk waits for its request's flag (flag == run epoch, so flags never
+// need clearing).  All jump pairs precede all chunk pairs in the queue, so the
+// request a chunk waits for has already been taken by a running wave; the wait
+// is still bounded, and a wait that runs out sets the host-visible error word
+// instead of hanging.
 #pragma once
 
 #include "common.hpp"
+#include "coop_dev.hpp"
 #include "gen_dev.hpp"
-#include "jump_dev.hpp"
-#include "seed_dev.hpp"
 
 namespace ranmar {
 
@@ -66,7 +66,7 @@ struct SingleDesc {
     BHeader h{};
     const uint64_t nq = (r0.count + L - 1) / L;
     h.n_req = 1;
-    h.n_jg = 1;
+    h.n_jg = 1;  // one jump pair, its second half idle
     h.n_chunks = (uint32_t)nq;
     h.n_cg = (uint32_t)((nq + 1) / 2);
     h.epoch = epoch;
@@ -87,42 +87,52 @@ struct SingleDesc {
 
 struct BatchBuffers {
   uint32_t* req_states;    // 98 words per request
-  uint32_t* done;          // one flag per jump group
+  uint32_t* done;          // one flag per request, plus one spare written by idle halves
   const uint32_t* ptab;    // 97 words per q: P_{qL}
+  const uint32_t* wtab;    // window table T[w][d]
   uint32_t* queue;         // [0] next item, [1] finished workgroups
   int* err;                // host-visible error word
+  uint32_t spare;          // index of the spare flag
 };
 
+// LDS per half-wave: the extended window X (193 words) and a polynomial (97).
+constexpr int kHalfLds = 193 + 97;
+
 template <class Desc>
-__device__ __forceinline__ void batch_jump_group(const Desc& D, const BHeader& h, const BatchBuffers& B, uint32_t g) {
+__device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h, const BatchBuffers& B, uint32_t p,
+                                                uint32_t* lds) {
   const uint32_t lane = threadIdx.x;
-  const uint32_t r = g * 64u + lane;
+  const uint32_t half = lane >> 5, l = lane & 31u;
+  const uint32_t r = 2u * p + half;
   const bool active = r < h.n_req;
+  uint32_t* X = lds + half * kHalfLds;
+  uint32_t* Bp = X + 193;
   BReq q{};
   if (active) q = D.req(r);
-  // A request with no draws but a state output is jumped directly in the
-  // caller's state record.
-  uint32_t* slot = (active && q.count == 0 && q.state) ? (uint32_t*)q.state : B.req_states + (uint64_t)r * kWords;
-  bool valid = false;
-  if (active) {
-    valid = seed_state(q.seed, slot);
-    if (!valid) {
-      for (int k = 0; k < 97; ++k) slot[k] = 0;
-      slot[97] = kInvalidC;
-    }
-  }
+  const bool valid = active && seed_half(q.seed, X, l);
+  if (!valid) X[l] = X[l + 32] = X[l + 64] = X[97] = 0;
+  wave_sync();
+  const uint32_t c = X[97];
   const uint32_t j0 = valid ? (uint32_t)q.off_lo : 0u, j1 = valid ? (uint32_t)(q.off_lo >> 32) : 0u;
   const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
-  jump_record_lane(slot, valid, j0, j1, j2, j3);
+  jump_half(X, Bp, B.wtab, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
+  // A request with no draws but a state output is written straight to the
+  // caller's record.
+  uint32_t* slot = (active && q.count == 0 && q.state) ? (uint32_t*)q.state : B.req_states + (uint64_t)r * kWords;
+  if (active) {
+    slot[l] = valid ? X[l] : 0u;
+    slot[l + 32] = valid ? X[l + 32] : 0u;
+    slot[l + 64] = valid ? X[l + 64] : 0u;
+    if (l == 0) {
+      slot[96] = valid ? X[96] : 0u;
+      slot[97] = valid ? c_jump(c, u128_mod_m(j0, j1, j2, j3)) : kInvalidC;
+    }
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  // Every lane stores the same value: no lane-conditional branch here (see
-  // batch_persistent).
-  __hip_atomic_store(&B.done[g], h.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // Every lane of the half stores the same value (idle halves to the spare).
+  __hip_atomic_store(&B.done[active ? r : B.spare], h.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wave_sync();
 }
-
-// LDS per half-wave: the extended window X (193 words), the coefficients of
-// P_{qL} (97) and the chunk's start state (98).
-constexpr int kHalfLds = 193 + 97 + 98;
 
 template <class Desc>
 __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h, const BatchBuffers& B, uint32_t cp,
@@ -132,15 +142,14 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   const uint32_t j = 2u * cp + half;
   const bool active = j < h.n_chunks;
   uint32_t* X = lds + half * kHalfLds;
-  uint32_t* Bc = X + 193;
-  uint32_t* Wn = Bc + 97;
+  uint32_t* Bp = X + 193;
   BChunk ch{};
   BReq rq{};
   if (active) {
     ch = D.chunk(h, j);
     rq = D.req(ch.req);
     uint32_t it = 0;
-    while (__hip_atomic_load(&B.done[ch.req >> 6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != h.epoch) {
+    while (__hip_atomic_load(&B.done[ch.req], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != h.epoch) {
       __builtin_amdgcn_s_sleep(2);
       if (++it > kSpinLimit) {
         __hip_atomic_store(B.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -149,48 +158,30 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  uint32_t c0 = 0;
-  if (active) {
-    const uint32_t* src = B.req_states + (uint64_t)ch.req * kWords;
-    const uint32_t* P = B.ptab + (uint64_t)ch.q * 97u;
-    for (uint32_t k = l; k < 97; k += 32) {
-      X[k] = src[k];
-      Bc[k] = P[k];
-    }
-    c0 = src[97];
+  // Chunk start: the request's start state times P_{qL}(A), c by qL steps.
+  const uint32_t* src = B.req_states + (uint64_t)ch.req * kWords;
+  const uint32_t* P = B.ptab + (uint64_t)ch.q * 97u;
+  X[l] = active ? src[l] : 0u;
+  X[l + 32] = active ? src[l + 32] : 0u;
+  X[l + 64] = active ? src[l + 64] : 0u;
+  Bp[l] = P[l];
+  Bp[l + 32] = P[l + 32];
+  Bp[l + 64] = P[l + 64];
+  if (l == 0) {
+    X[96] = active ? src[96] : 0u;
+    Bp[96] = P[96];
   }
-  __syncthreads();
-  // Extend the window: x_{97+i} = x_i - x_{i+64}, 32 terms per step.
-  for (uint32_t s0 = 0; s0 < 96; s0 += 32) {
-    if (active) X[97 + s0 + l] = X[s0 + l] - X[s0 + l + 64];
-    __syncthreads();
-  }
-  // New window W'[o] = sum_i b_i X[i + o] for o = l, l+32, l+64 (+96 on lane 0).
-  if (active) {
-    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll 4
-    for (int i = 0; i < 97; ++i) {
-      const uint32_t b = Bc[i];
-      a0 = mad24(b, X[i + l], a0);
-      a1 = mad24(b, X[i + l + 32], a1);
-      a2 = mad24(b, X[i + l + 64], a2);
-      if (l == 0) a3 = mad24(b, X[i + 96], a3);
-    }
-    Wn[l] = a0 & kMask;
-    Wn[l + 32] = a1 & kMask;
-    Wn[l + 64] = a2 & kMask;
-    if (l == 0) {
-      Wn[96] = a3 & kMask;
-      Wn[97] = c_jump(c0, (uint32_t)(((uint64_t)ch.q * h.L) % kMod));
-    }
-  }
-  __syncthreads();
+  const uint32_t c0 = active ? src[97] : 0u;
+  wave_sync();
+  apply_half(X, Bp, l);
+  if (l == 0) X[97] = c_jump(c0, (uint32_t)(((uint64_t)ch.q * h.L) % kMod));
+  wave_sync();
   if (active) {
     uint32_t* dst = (ch.last && rq.state) ? (uint32_t*)rq.state : nullptr;
-    gen_stream32<FMT_RUNTIME, true>(l, lane, Wn, dst, ch.draws, rq.fmt == RANMAR_F32,
+    gen_stream32<FMT_RUNTIME, true>(l, lane, X, dst, ch.draws, rq.fmt == RANMAR_F32,
                                     (char*)rq.out + (uint64_t)ch.q * h.L * 4u);
   }
-  __syncthreads();
+  wave_sync();
 }
 
 template <class Desc>
@@ -207,7 +198,7 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
     const uint32_t got = atomicAdd(&B.queue[0], lane == 0 ? 1u : 0u);
     const uint32_t item = __builtin_amdgcn_readfirstlane(got);
     if (item < h.n_jg)
-      batch_jump_group(D, h, B, item);
+      batch_jump_pair(D, h, B, item, lds);
     else if (item < h.n_jg + h.n_cg)
       batch_chunk_pair(D, h, B, item - h.n_jg, lds);
     else

@@ -1,0 +1,219 @@
+// Half-wave cooperative seeding and jump-ahead: one request per 32 lanes,
+// state in LDS.  Low latency for single requests, and no per-lane 200-register
+// working set.
+//
+// Seeding (Appendix A, Algorithm 3) in parallel over the 97 words.  Word ii
+// (0-based) is produced by steps 24 ii .. 24 ii + 23 of two small generators,
+// and both can be jumped in closed form:
+//   - the multiplicative step (i, j, k) <- (j, k, i j k mod 179): with
+//     a = log_2 i etc. (2 is a primitive root mod 179) it is the linear map
+//     (a, b, c) <- (b, c, a + b + c) mod 178, i.e. a 3x3 matrix M, so the
+//     state before word ii is M^(24 ii) applied to the initial logs;
+//   - l <- 53 l + 1 mod 169 is affine, l_(24 ii) = mu_ii l_0 + nu_ii mod 169.
+// Lane l starts words l, l+32, l+64 (and lane 0 word 96) from those closed
+// forms and runs the 24 ordinary steps of each.  The bits are exactly those of
+// the sequential procedure.
+//
+// Jump (Sec. 3): with the exponent J written in 8-bit digits d_w,
+// t^J = prod_w t^(d_w 2^(8w)) (mod phi), and applying these factors to the
+// state one after the other gives f^J exactly (the jumps compose).  The table
+// T[w][d] = t^(d 2^(8w)) mod phi (16 x 256 polynomials, 1.6 MB, computed once
+// per device by the square-and-multiply kernel) turns a 120-bit jump into 15
+// applications instead of ~119 squarings.  Each application is the Hankel
+// product  x'_o = sum_i b_i X_(i+o)  with X the window extended by 96 steps;
+// lane l computes outputs 3l..3l+3 with a sliding register window, so each
+// multiply-add costs half an LDS read.
+#pragma once
+
+#include "common.hpp"
+#include "seed_dev.hpp"
+
+namespace ranmar {
+
+// ---------------------------------------------------------------------------
+// Seeding tables (computed at compile time)
+// ---------------------------------------------------------------------------
+struct SeedTables {
+  uint8_t exp2[178];    // 2^e mod 179
+  uint8_t log2[179];    // log_2 x mod 178 (index 0 unused)
+  uint8_t m[97][9];     // M^(24 ii) mod 178, row-major
+  uint8_t mu[97], nu[97];  // l_(24 ii) = mu l_0 + nu mod 169
+};
+
+constexpr SeedTables make_seed_tables() {
+  SeedTables t{};
+  uint32_t v = 1;
+  for (int e = 0; e < 178; ++e) {
+    t.exp2[e] = (uint8_t)v;
+    t.log2[v] = (uint8_t)e;
+    v = v * 2 % 179;
+  }
+  // M24 = M^24 with M = [[0,1,0],[0,0,1],[1,1,1]] (mod 178)
+  uint32_t M[9] = {0, 1, 0, 0, 0, 1, 1, 1, 1};
+  uint32_t P[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  for (int s = 0; s < 24; ++s) {
+    uint32_t Q[9] = {};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        uint32_t acc = 0;
+        for (int x = 0; x < 3; ++x) acc += M[r * 3 + x] * P[x * 3 + c];
+        Q[r * 3 + c] = acc % 178;
+      }
+    for (int q = 0; q < 9; ++q) P[q] = Q[q];
+  }
+  uint32_t C[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  uint32_t mu = 1, nu = 0;
+  for (int ii = 0; ii < 97; ++ii) {
+    for (int q = 0; q < 9; ++q) t.m[ii][q] = (uint8_t)C[q];
+    t.mu[ii] = (uint8_t)mu;
+    t.nu[ii] = (uint8_t)nu;
+    uint32_t Q[9] = {};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        uint32_t acc = 0;
+        for (int x = 0; x < 3; ++x) acc += P[r * 3 + x] * C[x * 3 + c];
+        Q[r * 3 + c] = acc % 178;
+      }
+    for (int q = 0; q < 9; ++q) C[q] = Q[q];
+    for (int s = 0; s < 24; ++s) {
+      mu = mu * 53 % 169;
+      nu = (nu * 53 + 1) % 169;
+    }
+  }
+  return t;
+}
+
+static __constant__ const SeedTables kSeedTab = make_seed_tables();
+
+// One word of Algorithm 3 from the generators' state before it.
+__device__ __forceinline__ uint32_t seed_word(uint32_t i, uint32_t j, uint32_t k, uint32_t l) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int jj = 0; jj < 24; jj += 3) {
+    const uint32_t m0 = mod179(mul24(mul24(i, j), k));
+    l = mod169(mad24(l, 53u, 1u));
+    acc = (acc << 1) | ((mul24(l, m0) >> 5) & 1u);
+    const uint32_t m1 = mod179(mul24(mul24(j, k), m0));
+    l = mod169(mad24(l, 53u, 1u));
+    acc = (acc << 1) | ((mul24(l, m1) >> 5) & 1u);
+    const uint32_t m2 = mod179(mul24(mul24(k, m0), m1));
+    l = mod169(mad24(l, 53u, 1u));
+    acc = (acc << 1) | ((mul24(l, m2) >> 5) & 1u);
+    i = m0;
+    j = m1;
+    k = m2;
+  }
+  return acc;
+}
+
+__device__ __forceinline__ uint32_t seed_word_at(int ii, uint32_t a0, uint32_t b0, uint32_t c0, uint32_t l0) {
+  const uint8_t* M = kSeedTab.m[ii];
+  const uint32_t a = (M[0] * a0 + M[1] * b0 + M[2] * c0) % 178u;
+  const uint32_t b = (M[3] * a0 + M[4] * b0 + M[5] * c0) % 178u;
+  const uint32_t c = (M[6] * a0 + M[7] * b0 + M[8] * c0) % 178u;
+  const uint32_t l = (kSeedTab.mu[ii] * l0 + kSeedTab.nu[ii]) % 169u;
+  return seed_word(kSeedTab.exp2[a], kSeedTab.exp2[b], kSeedTab.exp2[c], l);
+}
+
+// The 32 lanes of a half-wave (lane index l) write the seeded state to
+// X[0..96] and c to X[97].  Returns false (and writes nothing) for a seed out
+// of [1, 9e8]; the result is uniform over the half.
+__device__ __forceinline__ bool seed_half(int32_t seed, uint32_t* X, uint32_t l) {
+  if (seed < 1 || seed > 900000000) return false;
+  const uint32_t s1 = (uint32_t)seed - 1u;
+  const uint32_t ij = s1 / 30082u;
+  const uint32_t kl = s1 - 30082u * ij;
+  const uint32_t a0 = kSeedTab.log2[(ij / 177u) % 177u + 2u];
+  const uint32_t b0 = kSeedTab.log2[ij % 177u + 2u];
+  const uint32_t c0 = kSeedTab.log2[(kl / 169u) % 178u + 1u];
+  const uint32_t l0 = kl % 169u;
+  // u_(ii+1) goes to x[96 - ii].
+  X[96 - l] = seed_word_at(l, a0, b0, c0, l0);
+  X[64 - l] = seed_word_at(l + 32, a0, b0, c0, l0);
+  X[32 - l] = seed_word_at(l + 64, a0, b0, c0, l0);
+  if (l == 0) {
+    X[0] = seed_word_at(96, a0, b0, c0, l0);
+    X[97] = kC0;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Windowed jump
+// ---------------------------------------------------------------------------
+constexpr int kWinBits = 8;
+constexpr int kWinDigits = 1 << kWinBits;   // 256
+constexpr int kWindows = 128 / kWinBits;    // 16
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// X[0..96] <- X P(A) for the polynomial in B[0..96]; X must have room for
+// 193 words (the window is extended in place).  Half-wave cooperative.
+__device__ __forceinline__ void apply_half(uint32_t* X, const uint32_t* B, uint32_t l) {
+  // X_(97+i) = X_i - X_(i+64), 32 terms per step.
+#pragma unroll
+  for (uint32_t s0 = 0; s0 < 96; s0 += 32) {
+    X[97 + s0 + l] = X[s0 + l] - X[s0 + l + 64];
+    wave_sync();
+  }
+  // Outputs o = 3l .. 3l+3 (o = 96 only kept by lane 31).
+  const uint32_t* Xl = X + 3u * l;
+  uint32_t w0 = Xl[0], w1 = Xl[1], w2 = Xl[2];
+  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 4
+  for (int i = 0; i < 97; ++i) {
+    const uint32_t w3 = Xl[i + 3];
+    const uint32_t b = B[i];
+    a0 = mad24(b, w0, a0);
+    a1 = mad24(b, w1, a1);
+    a2 = mad24(b, w2, a2);
+    a3 = mad24(b, w3, a3);
+    w0 = w1;
+    w1 = w2;
+    w2 = w3;
+  }
+  wave_sync();
+  X[3 * l] = a0 & kMask;
+  X[3 * l + 1] = a1 & kMask;
+  X[3 * l + 2] = a2 & kMask;
+  if (l == 31) X[96] = a3 & kMask;
+  wave_sync();
+}
+
+// In place: X[0..96] <- f_1^J applied to X (the c part is left to the caller).
+// T: the window table, T + (w * 256 + d) * 97.  J given as 32-bit limbs.
+// `nwin`: number of low windows to apply (uniform over the wave).
+__device__ __forceinline__ void jump_half(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
+                                          uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
+  for (int w = 0; w < nwin; ++w) {
+    const uint32_t limb = w < 4 ? j0 : w < 8 ? j1 : w < 12 ? j2 : j3;
+    const uint32_t d = (limb >> (8 * (w & 3))) & 0xFFu;
+    const uint32_t* row = T + ((uint64_t)w * kWinDigits + d) * 97u;
+    B[l] = row[l];
+    B[l + 32] = row[l + 32];
+    B[l + 64] = row[l + 64];
+    if (l == 0) B[96] = row[96];
+    wave_sync();
+    apply_half(X, B, l);
+  }
+}
+
+// Number of 8-bit windows holding the wave's longest exponent.
+__device__ __forceinline__ int wave_windows(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3) {
+  int bl = 0;
+  if (j3)
+    bl = 128 - __clz(j3);
+  else if (j2)
+    bl = 96 - __clz(j2);
+  else if (j1)
+    bl = 64 - __clz(j1);
+  else if (j0)
+    bl = 32 - __clz(j0);
+  return (wave_max_i32(bl) + kWinBits - 1) / kWinBits;
+}
+
+}  // namespace ranmar

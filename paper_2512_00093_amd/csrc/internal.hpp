@@ -17,6 +17,18 @@ hipError_t launch_apply_poly(uint32_t* states, const uint32_t* P, uint64_t n, hi
 // in-place f^J, optionally seeding first (seeds != nullptr)
 hipError_t launch_jump(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n, hipStream_t st);
 
+// Half-wave cooperative variant (windowed jump, parallel seeding).
+hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
+                            hipStream_t st);
+const uint32_t* window_table();   // T[w][d] = t^(d 2^(8w)) mod phi, per device
+
+enum JumpVariant : int {
+  JUMP_LANE_SQMUL = 0,   // one request per lane, square-and-multiply in VGPRs
+  JUMP_HALF_WINDOW = 1,  // one request per half-wave, 8-bit windows in LDS
+  JUMP_NUM_VARIANTS = 2
+};
+int jump_variant_for(uint64_t n);
+
 // Generation variants (all bit-identical).
 enum GenVariant : int {
   GEN_LANES32 = 0,     // 32 lanes per stream, cross-lane shift via ds_bpermute

@@ -31,8 +31,16 @@ int ilog2(uint64_t v) {
   return b;
 }
 
-constexpr int kJumpVariants = 1;
+constexpr int kJumpVariants = JUMP_NUM_VARIANTS;
 }  // namespace
+
+int jump_variant_for(uint64_t n) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (g_forced[RANMAR_K_JUMP] >= 0) return g_forced[RANMAR_K_JUMP];
+  auto it = g_table.find({RANMAR_K_JUMP, ilog2(n), 0});
+  if (it != g_table.end()) return it->second;
+  return JUMP_HALF_WINDOW;
+}
 
 int gen_variant_for(uint64_t n, uint64_t count) {
   std::lock_guard<std::mutex> g(g_mu);
@@ -40,6 +48,74 @@ int gen_variant_for(uint64_t n, uint64_t count) {
   auto it = g_table.find({RANMAR_K_GENERATE, ilog2(n), ilog2(count)});
   if (it != g_table.end()) return it->second;
   return GEN_LANES32_NT;
+}
+
+// Times the jump variants on n seed+jump requests with `bits`-bit offsets.
+static int tune_jump(uint64_t n, int bits, double* ms_out, hipStream_t st) {
+  if (n > (1ull << 24) || bits < 1 || bits > 128) return RANMAR_EINVAL;
+  std::vector<int32_t> seeds(n);
+  std::vector<ranmar_u128> J(n);
+  uint64_t x = 0x9E3779B97F4A7C15ull;
+  auto next = [&x] {
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    return x;
+  };
+  for (uint64_t i = 0; i < n; ++i) {
+    seeds[i] = (int32_t)(1 + next() % 900000000ull);
+    const uint64_t lo = next(), hi = next();
+    J[i].lo = bits >= 64 ? lo : (bits == 64 ? lo : lo & ((1ull << bits) - 1));
+    J[i].hi = bits > 64 ? (bits == 128 ? hi : hi & ((1ull << (bits - 64)) - 1)) : 0;
+  }
+  int32_t* d_seeds = nullptr;
+  ranmar_u128* d_J = nullptr;
+  uint32_t* d_states = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = RANMAR_EHIP;
+  double best = 1e30;
+  int best_v = 0;
+  if (hipMalloc(&d_seeds, 4 * n) != hipSuccess || hipMalloc(&d_J, 16 * n) != hipSuccess ||
+      hipMalloc(&d_states, sizeof(ranmar_state) * n) != hipSuccess)
+    goto done;
+  if (hipMemcpyAsync(d_seeds, seeds.data(), 4 * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d_J, J.data(), 16 * n, hipMemcpyHostToDevice, st) != hipSuccess)
+    goto done;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+  for (int v = 0; v < JUMP_NUM_VARIANTS; ++v) {
+    auto run = [&] {
+      return v == JUMP_HALF_WINDOW ? launch_jump_coop(d_states, d_seeds, d_J, n, st)
+                                   : launch_jump(d_states, d_seeds, d_J, n, st);
+    };
+    if (run() != hipSuccess) goto done;
+    hipEventRecord(e0, st);
+    const int reps = 3;
+    for (int r = 0; r < reps; ++r)
+      if (run() != hipSuccess) goto done;
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) goto done;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / reps;
+    if (ms_out) ms_out[v] = per;
+    if (per < best) {
+      best = per;
+      best_v = v;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table[{RANMAR_K_JUMP, ilog2(n), 0}] = best_v;
+  }
+  rc = best_v;
+done:
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  hipFree(d_states);
+  hipFree(d_J);
+  hipFree(d_seeds);
+  return rc;
 }
 
 }  // namespace ranmar
@@ -56,7 +132,8 @@ int ranmar_tune_variants(int kernel) {
 
 const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_GENERATE && variant >= 0 && variant < GEN_NUM_VARIANTS) return gen_variant_name(variant);
-  if (kernel == RANMAR_K_JUMP && variant == 0) return "lane_per_request";
+  if (kernel == RANMAR_K_JUMP && variant == JUMP_LANE_SQMUL) return "lane_square_multiply";
+  if (kernel == RANMAR_K_JUMP && variant == JUMP_HALF_WINDOW) return "halfwave_window8";
   return nullptr;
 }
 
@@ -74,10 +151,7 @@ int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void
   int rc = ensure_init();
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  if (kernel == RANMAR_K_JUMP) {
-    if (ms_out) ms_out[0] = 0.0;
-    return 0;
-  }
+  if (kernel == RANMAR_K_JUMP) return tune_jump(n, count ? (int)count : 120, ms_out, st);
   if (count == 0 || n > (1ull << 24) || count > (1ull << 24) || n * count > (1ull << 31)) return RANMAR_EINVAL;
   // Synthetic states: seeds 1..n at offset 0.
   int32_t* d_seeds = nullptr;

@@ -305,3 +305,60 @@ def test_repeatable(orc):
     b = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
     assert torch.equal(a, b)
     assert torch.equal(R.ranmar_generate(a, 333, 1), R.ranmar_generate(b, 333, 1))
+
+
+# --- jump variants: per-lane square-and-multiply vs half-wave windowed ---------
+@pytest.fixture(params=[0, 1], ids=["lane_sqmul", "half_window"])
+def jump_variant(request):
+    R.ranmar_tune_set(R.RANMAR_K_JUMP, request.param)
+    yield request.param
+    R.ranmar_tune_set(R.RANMAR_K_JUMP, -1)
+
+
+def test_jump_variant_seeding(orc, jump_variant):
+    """J = 0: pure seeding (the half-wave variant seeds the 97 words in
+    parallel from closed-form jumps of the two small generators)."""
+    seeds = [1, 2, 3, 12345, 4711, 900000, 900000000, 30082, 30083] + \
+        [int(s) for s in synth.seeds(400, offset=17)]
+    say(f"seed via seed_jump variant={jump_variant}")
+    got = u32(R.ranmar_seed_jump(seeds_t(seeds), jumps_t([0] * len(seeds))))
+    assert np.array_equal(got, np.stack([orc.state_from_seed(s) for s in seeds]))
+
+
+def test_jump_variant_edges(orc, jump_variant):
+    g = synth.rng(220)
+    lo, hi = synth.u128_uniform(g, 60, 120)
+    Js = [0, 1, 2, 255, 256, 257, 65535, 1 << 64, (1 << 64) - 1, (1 << 120) - 1, (1 << 128) - 1,
+          ((1 << 97) - 1) << 23] + synth.u128_to_int(lo, hi)
+    seeds = [int(s) for s in synth.seeds(len(Js), offset=18)]
+    seeds[:3] = [0, 900000001, -7]       # invalid seeds leave the marker record
+    say(f"seed_jump edges variant={jump_variant}")
+    got = u32(R.ranmar_seed_jump(seeds_t(seeds), jumps_t(Js)))
+    for r in range(3):
+        assert not got[r, :97].any() and got[r, 97] == 0xFFFFFFFF
+    ref = orc.seed_jump_many(seeds[3:], Js[3:])
+    assert np.array_equal(got[3:], ref)
+    # in-place jump of arbitrary states
+    st = _rand_states(orc, len(Js), 9)
+    d = states_t(st)
+    R.ranmar_jump(d, jumps_t(Js))
+    w = u32(d)
+    for r in range(0, len(Js), 5):
+        assert np.array_equal(w[r], orc.jump(st[r], Js[r])), (r, Js[r])
+
+
+def test_jump_variants_agree_at_scale(jump_variant):
+    n = 20000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=19)
+    say(f"jump variants at n={n}")
+    a = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
+    R.ranmar_tune_set(R.RANMAR_K_JUMP, 1 - jump_variant)
+    b = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
+    assert torch.equal(a, b)
+
+
+def test_tune_run_jump_and_generate():
+    best, ms = R.ranmar_tune_run(R.RANMAR_K_JUMP, 4096, 120)
+    assert best in (0, 1) and all(m > 0 for m in ms)
+    best, ms = R.ranmar_tune_run(R.RANMAR_K_GENERATE, 4096, 4096)
+    assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_GENERATE) and all(m > 0 for m in ms)
