@@ -99,6 +99,8 @@ int ranmar_seed_batch(const int32_t* d_seeds, uint64_t n, ranmar_state* d_out, v
   if (overlap(d_seeds, 4 * n, d_out, sizeof(ranmar_state) * n)) return RANMAR_EINVAL;
   int rc = ensure_init();
   if (rc) return rc;
+  // Few seeds: 32 lanes per seed (latency); many: one lane per seed (throughput).
+  if (n < 4096) return hip_status(launch_seed_coop(d_seeds, n, (uint32_t*)d_out, (hipStream_t)stream));
   return hip_status(launch_seed(d_seeds, n, (uint32_t*)d_out, (hipStream_t)stream));
 }
 
@@ -154,6 +156,8 @@ int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n
     return RANMAR_EINVAL;
   int rc = ensure_init();
   if (rc) return rc;
+  const hipError_t e = launch_family_window((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, (hipStream_t)stream);
+  if (e != hipErrorInvalidValue) return hip_status(e);
   return hip_status(launch_family((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, (hipStream_t)stream));
 }
 

@@ -17,10 +17,26 @@ __global__ __launch_bounds__(256) void k_gen32(const uint32_t* __restrict__ sin,
                         (char*)out + s * ld * 4u);
 }
 
+// Wide-store variant: eight half-waves per workgroup, each with a 512-byte LDS
+// transpose buffer.
+template <int FMT, bool NT>
+__global__ __launch_bounds__(256) void k_gen32_wide(const uint32_t* __restrict__ sin, uint32_t* sout, uint64_t n,
+                                                    uint64_t count, void* __restrict__ out, uint64_t ld) {
+  __shared__ uint32_t bufs[8 * 128];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t l = lane & 31u;
+  const uint64_t s = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2u + (lane >> 5);
+  if (s >= n) return;
+  gen_stream32_wide<FMT, NT>(l, lane, sin + s * kWords, sout ? sout + s * kWords : nullptr, count,
+                             FMT == RANMAR_F32, (char*)out + s * ld * 4u, bufs + (threadIdx.x >> 5) * 128);
+}
+
 const char* gen_variant_name(int v) {
   switch (v) {
     case GEN_LANES32: return "lanes32";
     case GEN_LANES32_NT: return "lanes32_nt";
+    case GEN_WIDE4: return "lanes32_wide4";
+    case GEN_WIDE4_NT: return "lanes32_wide4_nt";
     default: return "?";
   }
 }
@@ -31,7 +47,17 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   const unsigned wg = 256;
   const uint64_t per_wg = wg / 32;
   const dim3 grid((unsigned)((n + per_wg - 1) / per_wg));
+  // The wide stores need 16-byte aligned rows.
+  const bool wide_ok = (((uintptr_t)out & 15) == 0) && (ld % 4 == 0);
+  if (!wide_ok && variant == GEN_WIDE4) variant = GEN_LANES32;
+  if (!wide_ok && variant == GEN_WIDE4_NT) variant = GEN_LANES32_NT;
   switch (variant) {
+    case GEN_WIDE4:
+      hipLaunchKernelGGL((k_gen32_wide<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+      break;
+    case GEN_WIDE4_NT:
+      hipLaunchKernelGGL((k_gen32_wide<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+      break;
     case GEN_LANES32_NT:
       hipLaunchKernelGGL((k_gen32<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
       break;

@@ -21,6 +21,9 @@ hipError_t launch_jump(uint32_t* states, const int32_t* seeds, const ranmar_u128
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                             hipStream_t st);
 const uint32_t* window_table();   // T[w][d] = t^(d 2^(8w)) mod phi, per device
+hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
+// Family by table factors; hipErrorInvalidValue if an exponent needs > 128 bits.
+hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
 
 enum JumpVariant : int {
   JUMP_LANE_SQMUL = 0,   // one request per lane, square-and-multiply in VGPRs
@@ -33,7 +36,9 @@ int jump_variant_for(uint64_t n);
 enum GenVariant : int {
   GEN_LANES32 = 0,     // 32 lanes per stream, cross-lane shift via ds_bpermute
   GEN_LANES32_NT = 1,  // same, non-temporal output stores
-  GEN_NUM_VARIANTS = 2
+  GEN_WIDE4 = 2,       // four blocks per step, LDS transpose, 16-byte stores
+  GEN_WIDE4_NT = 3,    // same, non-temporal
+  GEN_NUM_VARIANTS = 4
 };
 const char* gen_variant_name(int v);
 hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uint64_t n, uint64_t count, int fmt,

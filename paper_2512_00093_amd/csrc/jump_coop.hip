@@ -65,6 +65,114 @@ __global__ __launch_bounds__(256) void k_jump_coop(uint32_t* __restrict__ states
   }
 }
 
+// Seeding only, 32 lanes per seed (for few seeds: a lane-per-seed launch would
+// run Algorithm 3's 2328 dependent steps on one lane).
+__global__ __launch_bounds__(256) void k_seed_coop(const int32_t* __restrict__ seeds, uint64_t n,
+                                                   uint32_t* __restrict__ out) {
+  __shared__ uint32_t lds[8 * 98];
+  const uint32_t hw = threadIdx.x >> 5, l = threadIdx.x & 31u;
+  const uint64_t r = (uint64_t)blockIdx.x * 8u + hw;
+  if (r >= n) return;  // a whole half-wave leaves together
+  uint32_t* X = lds + hw * 98;
+  const bool valid = seed_half(seeds[r], X, l);
+  wave_sync();
+  uint32_t* slot = out + r * kWords;
+  slot[l] = valid ? X[l] : 0u;
+  slot[l + 32] = valid ? X[l + 32] : 0u;
+  slot[l + 64] = valid ? X[l + 64] : 0u;
+  if (l == 0) {
+    slot[96] = valid ? X[96] : 0u;
+    slot[97] = valid ? X[97] : kInvalidC;
+  }
+}
+
+// One doubling round of a stream family: for k < cnt,
+// out[dst0 + k] = out[k] jumped by the exponent whose nonzero 8-bit digits
+// are given (window w_i, digit d_i): one table factor per digit.
+struct FamilyDigits {
+  uint32_t n;
+  uint32_t jmod;           // exponent mod m
+  uint16_t w[16], d[16];
+};
+
+__global__ __launch_bounds__(256) void k_family_round_coop(uint32_t* __restrict__ out,
+                                                           const uint32_t* __restrict__ T, uint64_t cnt,
+                                                           uint64_t dst0, FamilyDigits dg) {
+  __shared__ uint32_t lds[8 * kHalfWords];
+  const uint32_t hw = threadIdx.x >> 5, l = threadIdx.x & 31u;
+  const uint64_t k = (uint64_t)blockIdx.x * 8u + hw;
+  if (k >= cnt) return;  // a whole half-wave leaves together
+  uint32_t* X = lds + hw * kHalfWords;
+  uint32_t* B = X + 193;
+  const uint32_t* src = out + k * kWords;
+  X[l] = src[l];
+  X[l + 32] = src[l + 32];
+  X[l + 64] = src[l + 64];
+  if (l == 0) X[96] = src[96];
+  const uint32_t c = src[97];
+  for (uint32_t i = 0; i < dg.n; ++i) {
+    const uint32_t* row = T + ((uint64_t)dg.w[i] * kWinDigits + dg.d[i]) * 97u;
+    B[l] = row[l];
+    B[l + 32] = row[l + 32];
+    B[l + 64] = row[l + 64];
+    if (l == 0) B[96] = row[96];
+    wave_sync();
+    apply_half(X, B, l);
+  }
+  uint32_t* dst = out + (dst0 + k) * kWords;
+  dst[l] = X[l];
+  dst[l + 32] = X[l + 32];
+  dst[l + 64] = X[l + 64];
+  if (l == 0) {
+    dst[96] = X[96];
+    dst[97] = c_jump(c, dg.jmod);
+  }
+}
+
+hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_seed_coop, dim3((unsigned)((n + 7) / 8)), dim3(256), 0, st, seeds, n, out);
+  return hipGetLastError();
+}
+
+// Family by doubling rounds that each apply the table factors of 2^b delta.
+// Returns hipErrorInvalidValue (nothing launched) when some 2^b delta needs
+// more than 128 bits; the caller then uses the polynomial path.
+hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st) {
+  int nb = 0;
+  while (nb < 64 && (1ull << nb) < n) ++nb;
+  const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
+  int dbits = 0;
+  for (unsigned __int128 t = D; t; t >>= 1) ++dbits;
+  if (nb > 0 && dbits + nb - 1 > 128) return hipErrorInvalidValue;
+  const uint32_t* T = window_table();
+  if (!T) return hipErrorOutOfMemory;
+  if (base != out) {
+    hipError_t e = hipMemcpyAsync(out, base, 4 * kWords, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  const uint64_t dmod = (uint64_t)(D % kMod);
+  uint64_t pow2 = 1;
+  for (int b = 0; b < nb; ++b) {
+    const unsigned __int128 E = D << b;  // < 2^128 by the check above
+    FamilyDigits dg{};
+    for (int w = 0; w < kWindows; ++w) {
+      const uint32_t d = (uint32_t)(E >> (kWinBits * w)) & 0xFFu;
+      if (d) {
+        dg.w[dg.n] = (uint16_t)w;
+        dg.d[dg.n] = (uint16_t)d;
+        ++dg.n;
+      }
+    }
+    dg.jmod = (uint32_t)((dmod * pow2) % kMod);
+    pow2 = pow2 * 2 % kMod;
+    const uint64_t half = 1ull << b;
+    const uint64_t cnt = (n - half < half) ? n - half : half;
+    hipLaunchKernelGGL(k_family_round_coop, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out, T, cnt, half, dg);
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Window table, one per device, built by the square-and-multiply kernel.
 // ---------------------------------------------------------------------------

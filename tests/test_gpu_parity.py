@@ -362,3 +362,27 @@ def test_tune_run_jump_and_generate():
     assert best in (0, 1) and all(m > 0 for m in ms)
     best, ms = R.ranmar_tune_run(R.RANMAR_K_GENERATE, 4096, 4096)
     assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_GENERATE) and all(m > 0 for m in ms)
+
+
+def test_seed_batch_both_paths(orc):
+    """< 4096 seeds: 32 lanes per seed; >= 4096: one lane per seed."""
+    seeds = [int(s) for s in synth.seeds(5000, offset=23)]
+    say("seed_batch n=5000 (lane path) and n=100 (half-wave path)")
+    big = u32(R.ranmar_seed_batch(seeds_t(seeds)))
+    small = u32(R.ranmar_seed_batch(seeds_t(seeds[:100])))
+    assert np.array_equal(big[:100], small)
+    for r in (0, 1, 99, 2500, 4999):
+        assert np.array_equal(big[r], orc.state_from_seed(seeds[r])), r
+
+
+def test_family_polynomial_path(orc):
+    """Exponents 2^b delta above 128 bits take the squaring-chain path."""
+    delta = (1 << 121) + 1
+    n = 129
+    base = orc.state_from_seed(777)
+    say("jump_family wide exponents n=129")
+    fam = u32(R.ranmar_jump_family(states_t(base), delta, n))
+    for k in (0, 1, 2, 64, 100, 127):      # k * delta < 2^128 for the oracle
+        assert np.array_equal(fam[k], orc.jump(base, k * delta)), k
+    # stream 128 (exponent above 2^128) by the group law: 128 delta = 127 delta + delta
+    assert np.array_equal(fam[128], orc.jump(orc.jump(base, 127 * delta), delta))
