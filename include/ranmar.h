@@ -198,6 +198,15 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
  * The batch may be reused once the stream has passed this run. */
 int ranmar_batch_run(ranmar_batch *b, const ranmar_request *reqs, uint64_t n, void *stream);
 
+/* ranmar_batch_run split in two: ranmar_batch_prepare validates the requests
+ * and writes their descriptors into the batch's pinned staging buffer (host
+ * work only, same errors as ranmar_batch_run); ranmar_batch_launch launches
+ * the graph for the prepared batch on `stream` (RANMAR_EINVAL if nothing is
+ * prepared).  prepare waits for the batch's previous launch to have read the
+ * staging buffer. */
+int ranmar_batch_prepare(ranmar_batch *b, const ranmar_request *reqs, uint64_t n);
+int ranmar_batch_launch(ranmar_batch *b, void *stream);
+
 /* Same work as ranmar_batch_run, one ordinary launch per request (the
  * baseline the batched path is measured against). */
 int ranmar_run_unbatched(const ranmar_request *reqs, uint64_t n, void *stream);

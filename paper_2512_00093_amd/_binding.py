@@ -92,6 +92,8 @@ _SIGS = {
     "ranmar_generate": (_int, [_vp, _vp, _u64, _u64, _int, _vp, _u64, _vp]),
     "ranmar_batch_create": (_int, [_u64, _u64, _u64, ctypes.POINTER(_vp)]),
     "ranmar_batch_run": (_int, [_vp, ctypes.POINTER(ranmar_request), _u64, _vp]),
+    "ranmar_batch_prepare": (_int, [_vp, ctypes.POINTER(ranmar_request), _u64]),
+    "ranmar_batch_launch": (_int, [_vp, _vp]),
     "ranmar_run_unbatched": (_int, [ctypes.POINTER(ranmar_request), _u64, _vp]),
     "ranmar_batch_destroy": (_int, [_vp]),
     "ranmar_serve_create": (_int, [_vp, _u64, ctypes.POINTER(ranmar_serve_cfg), ctypes.POINTER(_vp)]),
@@ -261,6 +263,14 @@ def ranmar_batch_create(max_requests: int, max_chunks: int, chunk_draws: int = 0
 
 def ranmar_batch_run(batch, reqs, stream=None):
     return _check(lib().ranmar_batch_run(batch, reqs, len(reqs), _stream(stream)), "ranmar_batch_run")
+
+
+def ranmar_batch_prepare(batch, reqs):
+    return _check(lib().ranmar_batch_prepare(batch, reqs, len(reqs)), "ranmar_batch_prepare")
+
+
+def ranmar_batch_launch(batch, stream=None):
+    return _check(lib().ranmar_batch_launch(batch, _stream(stream)), "ranmar_batch_launch")
 
 
 def ranmar_run_unbatched(reqs, stream=None):

@@ -102,6 +102,7 @@ struct ranmar_batch {
   hipGraphNode_t cpy = nullptr, kern = nullptr;
   hipEvent_t last = nullptr;
   bool launched = false;
+  size_t prepared_bytes = 0;  // descriptor bytes staged by prepare, 0 = none
   BatchBuffers B{};
   const uint8_t* kdesc = nullptr;  // kernel argument storage for the graph node
 };
@@ -186,14 +187,11 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   return RANMAR_OK;
 }
 
-int ranmar_batch_run(ranmar_batch* b, const ranmar_request* reqs, uint64_t n, void* stream) {
+int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n) {
   if (!b || (n && !reqs)) return RANMAR_EINVAL;
+  b->prepared_bytes = 0;
   if (n > b->max_req) return RANMAR_ENOMEM;
   if (n == 0) return RANMAR_OK;
-  if (*(volatile int*)b->h_err) {
-    *(volatile int*)b->h_err = 0;
-    return RANMAR_EHIP;
-  }
   uint64_t total = 0;
   for (uint64_t r = 0; r < n; ++r) {
     uint64_t nq = 0;
@@ -203,7 +201,6 @@ int ranmar_batch_run(ranmar_batch* b, const ranmar_request* reqs, uint64_t n, vo
   }
   if (total > b->max_chunks) return RANMAR_ENOMEM;
   const uint64_t chunk_off = (64 + sizeof(BReq) * n + 15) & ~15ull;
-  const size_t bytes = chunk_off + sizeof(BChunk) * total;
   // The staging buffer may still be read by the previous run's copy.
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
   BHeader* h = (BHeader*)b->h_desc;
@@ -229,6 +226,19 @@ int ranmar_batch_run(ranmar_batch* b, const ranmar_request* reqs, uint64_t n, vo
       ch[j].last = (q + 1 == nq) ? 1u : 0u;
     }
   }
+  b->prepared_bytes = chunk_off + sizeof(BChunk) * total;
+  return RANMAR_OK;
+}
+
+int ranmar_batch_launch(ranmar_batch* b, void* stream) {
+  if (!b || !b->prepared_bytes) return RANMAR_EINVAL;
+  if (*(volatile int*)b->h_err) {
+    *(volatile int*)b->h_err = 0;
+    b->prepared_bytes = 0;
+    return RANMAR_EHIP;
+  }
+  const size_t bytes = b->prepared_bytes;
+  b->prepared_bytes = 0;
   if (hipGraphExecMemcpyNodeSetParams1D(b->exec, b->cpy, b->d_desc, b->h_desc, bytes, hipMemcpyHostToDevice) !=
       hipSuccess)
     return RANMAR_EHIP;
@@ -236,6 +246,14 @@ int ranmar_batch_run(ranmar_batch* b, const ranmar_request* reqs, uint64_t n, vo
   if (hipEventRecord(b->last, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
   b->launched = true;
   return RANMAR_OK;
+}
+
+int ranmar_batch_run(ranmar_batch* b, const ranmar_request* reqs, uint64_t n, void* stream) {
+  if (!b || (n && !reqs)) return RANMAR_EINVAL;
+  if (n == 0) return n > b->max_req ? RANMAR_ENOMEM : RANMAR_OK;
+  const int rc = ranmar_batch_prepare(b, reqs, n);
+  if (rc) return rc;
+  return ranmar_batch_launch(b, stream);
 }
 
 int ranmar_batch_destroy(ranmar_batch* b) {

@@ -8,7 +8,8 @@
 // jump (Sec. 3.2): the jumps compose exactly (f^a o f^b = f^(a+b)), so every
 // chunk's draws are exactly those of the request's single stream.
 //
-// Work items, taken in order from an atomic counter by one-wave workgroups:
+// Work items, taken in order from an atomic counter by one-wave workgroups
+// (jump pairs g at a time when there are many):
 //   [0, n_jg)           jump pairs: each half-wave seeds one request and jumps
 //                       it to its offset (parallel seeding and the windowed
 //                       jump of coop_dev.hpp), then raises the request's flag;
@@ -128,9 +129,14 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
       slot[97] = valid ? c_jump(c, u128_mod_m(j0, j1, j2, j3)) : kInvalidC;
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  // Every lane of the half stores the same value (idle halves to the spare).
-  __hip_atomic_store(&B.done[active ? r : B.spare], h.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // Only requests with draws have chunks waiting for them.  The release fence
+  // writes back this XCD's L2, so it is skipped when no request of the pair
+  // has consumers (jump-only batches); the test is wave-uniform.
+  if (__any(active && q.count > 0)) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Every lane of the half stores the same value (idle halves to the spare).
+    __hip_atomic_store(&B.done[active ? r : B.spare], h.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   wave_sync();
 }
 
@@ -189,6 +195,11 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
   const BHeader h = D.header();
   const uint32_t lane = threadIdx.x;
   __shared__ uint32_t lds[2 * kHalfLds];
+  // Jump pairs are taken g at a time when there are many (one queue atomic per
+  // g pairs instead of per pair); small batches keep g = 1 for latency.
+  uint32_t g = h.n_jg / (2u * gridDim.x);
+  g = g < 1u ? 1u : (g > 8u ? 8u : g);
+  const uint32_t n_ju = (h.n_jg + g - 1) / g;
   for (;;) {
     // Dequeue without a lane-conditional branch: every lane executes the
     // atomic, lane 0 adding 1 and the others 0, and lane 0's result is taken.
@@ -197,12 +208,14 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
     // the loop body so that lanes 1..63 re-enter the body on a stale item.)
     const uint32_t got = atomicAdd(&B.queue[0], lane == 0 ? 1u : 0u);
     const uint32_t item = __builtin_amdgcn_readfirstlane(got);
-    if (item < h.n_jg)
-      batch_jump_pair(D, h, B, item, lds);
-    else if (item < h.n_jg + h.n_cg)
-      batch_chunk_pair(D, h, B, item - h.n_jg, lds);
-    else
+    if (item < n_ju) {
+      const uint32_t p1 = (item + 1) * g < h.n_jg ? (item + 1) * g : h.n_jg;
+      for (uint32_t p = item * g; p < p1; ++p) batch_jump_pair(D, h, B, p, lds);
+    } else if (item < n_ju + h.n_cg) {
+      batch_chunk_pair(D, h, B, item - n_ju, lds);
+    } else {
       break;
+    }
   }
   // The last workgroup out resets the counters for the next launch.
   if (lane == 0) {

@@ -111,6 +111,8 @@ def test_batch_and_serve_argument_errors(L):
     assert L.ranmar_batch_create(10, 10, 1 << 30, ctypes.byref(h)) == B.RANMAR_EINVAL
     assert L.ranmar_batch_run(None, None, 1, None) == B.RANMAR_EINVAL
     assert L.ranmar_batch_destroy(None) == B.RANMAR_EINVAL
+    assert L.ranmar_batch_prepare(None, None, 1) == B.RANMAR_EINVAL
+    assert L.ranmar_batch_launch(None, None) == B.RANMAR_EINVAL
     assert L.ranmar_run_unbatched(None, 3, None) == B.RANMAR_EINVAL
     assert L.ranmar_serve_create(None, 1 << 20, None, ctypes.byref(h)) == B.RANMAR_EINVAL
     assert L.ranmar_serve_create(ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(h)) == B.RANMAR_EINVAL

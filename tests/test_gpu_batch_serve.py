@@ -277,3 +277,21 @@ def test_serve_replay_driver():
     assert s.completed == n and s.released == n and s.bytes_in_use == 0
     assert (lat > 0).all() and wall < 30
     assert s.draws == int(tr["counts"].sum())
+
+
+def test_batch_prepare_then_launch(orc):
+    items = _alloc(_mixed_requests(10, 6, max_count=50_000))
+    b = R.ranmar_batch_create(16, 256)
+    try:
+        with pytest.raises(R.RanmarError) as e:
+            R.ranmar_batch_launch(b)                     # nothing prepared
+        assert e.value.status == R.RANMAR_EINVAL
+        R.ranmar_batch_prepare(b, R.make_requests(items))
+        say("batch prepare + launch")
+        R.ranmar_batch_launch(b)
+        with pytest.raises(R.RanmarError):
+            R.ranmar_batch_launch(b)                     # a preparation is launched once
+        torch.cuda.synchronize()
+        _check(orc, items)
+    finally:
+        R.ranmar_batch_destroy(b)
