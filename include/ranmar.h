@@ -281,6 +281,8 @@ int ranmar_serve_destroy(ranmar_server *s);
  * returns when all are released.  Latency of request r, from its scheduled
  * arrival to the server observing its completion, goes to latency_ns[r]
  * (may be NULL).  Host arrays of n entries; t_arrival_s non-decreasing.
+ * Requests submitted meanwhile through ranmar_serve_submit are left to their
+ * submitter.  One replay per server at a time (RANMAR_EINVAL otherwise).
  * Returns the first error of any submission (RANMAR_EINVAL, RANMAR_ENOMEM). */
 int ranmar_serve_replay(ranmar_server *s, uint64_t n, const double *t_arrival_s, const int32_t *seeds,
                         const ranmar_u128 *offsets, const uint64_t *counts, int fmt, double *latency_ns);

@@ -1,16 +1,22 @@
 // Batched execution of uneven requests in one persistent launch (host side).
 //
-// ranmar_batch_run: the request and chunk tables are written to a pinned host
-// staging buffer and the run is one launch of a captured graph
+// ranmar_batch_prepare cuts the requests into slices and chunks, spreads them
+// over up to 64 bins of about equal work (one jump counted as one chunk) and
+// writes the header, bin, slice and chunk tables to a pinned host staging
+// buffer.  A request that straddles two bins is split at a chunk boundary; the
+// second part is a request of its own (offset + first draw), so the draws are
+// unchanged.  ranmar_batch_launch is one launch of a captured graph
 //     [memcpy staging -> device tables]  ->  [persistent kernel]
-// whose memcpy size is set per run; the kernel's arguments never change (they
-// point at the batch's own device buffers), so the graph is built once.
+// whose memcpy size and grid are set per launch (the grid: as many workgroups
+// per bin as the bin has items, up to what the device holds at once).  The
+// copy also zeroes the bins' queue counters.
 //
 // ranmar_run_unbatched: the same kernel launched once per request with the
 // request passed by value (no tables, no graph): the baseline the batched path
 // is measured against.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -23,7 +29,7 @@
 
 namespace ranmar {
 
-__global__ __launch_bounds__(64) void k_batch_tables(const uint8_t* __restrict__ desc, BatchBuffers B) {
+__global__ __launch_bounds__(64) void k_batch_tables(uint8_t* desc, BatchBuffers B) {
   batch_persistent(TableDesc{desc}, B);
 }
 
@@ -32,14 +38,13 @@ __global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers 
 constexpr uint32_t kDefaultChunk = 16384;
 constexpr uint32_t kMaxChunkDraws = 1u << 24;
 
-// Workgroups that fit the device at once (the kernel's occupancy times the
-// number of CUs): every workgroup of the persistent grid is resident.
-static unsigned persistent_grid() {
+// Workgroups of `kernel` (block size `threads`) that fit the device at once
+// (occupancy times the number of CUs): every workgroup of the grid is resident.
+static unsigned persistent_grid(const void* kernel, int threads) {
   int dev = 0, cus = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_tables, 64, 0) != hipSuccess ||
-      per_cu <= 0)
-    per_cu = 8;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 2;
   return (unsigned)(cus > 0 ? cus : 256) * (unsigned)per_cu;
 }
 
@@ -88,7 +93,7 @@ static BReq to_breq(const ranmar_request& q) {
 using namespace ranmar;
 
 struct ranmar_batch {
-  uint64_t max_req = 0, max_chunks = 0;
+  uint64_t max_req = 0, max_chunks = 0, max_slices = 0;
   uint32_t L = kDefaultChunk;
   size_t desc_cap = 0;
   uint8_t* d_desc = nullptr;
@@ -96,7 +101,9 @@ struct ranmar_batch {
   uint32_t *d_req_states = nullptr, *d_done = nullptr, *d_queue = nullptr, *d_ptab = nullptr;
   int* h_err = nullptr;
   uint32_t epoch = 0;
-  unsigned grid = 0;
+  unsigned workers_max = 0;   // one-wave workgroups the device holds at once
+  unsigned grid_node = 0;     // workgroups of the graph's kernel node now
+  unsigned grid_prepared = 0; // workgroups for the prepared tables
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t cpy = nullptr, kern = nullptr;
@@ -104,8 +111,22 @@ struct ranmar_batch {
   bool launched = false;
   size_t prepared_bytes = 0;  // descriptor bytes staged by prepare, 0 = none
   BatchBuffers B{};
-  const uint8_t* kdesc = nullptr;  // kernel argument storage for the graph node
+  uint8_t* kdesc = nullptr;   // kernel argument storage for the graph node
+  void* kargs[2] = {nullptr, nullptr};
 };
+
+static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned grid) {
+  hipKernelNodeParams kp{};
+  b->kargs[0] = (void*)&b->kdesc;
+  b->kargs[1] = (void*)&b->B;
+  kp.func = (void*)k_batch_tables;
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(64);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = b->kargs;
+  kp.extra = nullptr;
+  return kp;
+}
 
 static void batch_free(ranmar_batch* b) {
   if (!b) return;
@@ -123,6 +144,12 @@ static void batch_free(ranmar_batch* b) {
   delete b;
 }
 
+// Byte offsets of the slice and chunk tables for n requests in nb bins.
+static uint64_t req_offset(uint32_t nb) { return 64 + sizeof(BBin) * (uint64_t)nb; }
+static uint64_t chunk_offset(uint64_t n, uint32_t nb) {
+  return (req_offset(nb) + sizeof(BReq) * (n + nb) + 15) & ~15ull;
+}
+
 extern "C" {
 
 int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chunk_draws, ranmar_batch** out) {
@@ -133,20 +160,21 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   ranmar_batch* b = new ranmar_batch();
   b->max_req = max_requests;
   b->max_chunks = max_chunks ? max_chunks : 1;
+  b->max_slices = b->max_req + kMaxBins;  // each bin boundary splits at most one request
   b->L = chunk_draws ? (uint32_t)chunk_draws : kDefaultChunk;
-  b->desc_cap = 64 + sizeof(BReq) * b->max_req + 16 + sizeof(BChunk) * b->max_chunks;
-  b->grid = persistent_grid();
-  const uint64_t ngroups = b->max_req + 1;  // request flags + the spare
+  b->desc_cap = chunk_offset(b->max_req, kMaxBins) + sizeof(BChunk) * b->max_chunks;
+  b->workers_max = std::max<unsigned>(persistent_grid((const void*)k_batch_tables, 64), kMaxBins);
+  const uint64_t nflags = b->max_slices + 1;  // slice flags + the spare
   hipStream_t st = nullptr;
   bool ok = hipMalloc(&b->d_desc, b->desc_cap) == hipSuccess &&
             hipHostMalloc(&b->h_desc, b->desc_cap, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(&b->h_err, sizeof(int), hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
-            hipMalloc(&b->d_req_states, 4 * kWords * b->max_req) == hipSuccess &&
-            hipMalloc(&b->d_done, 4 * ngroups) == hipSuccess && hipMalloc(&b->d_queue, 8) == hipSuccess &&
+            hipMalloc(&b->d_req_states, 4 * kWords * b->max_slices) == hipSuccess &&
+            hipMalloc(&b->d_done, 4 * nflags) == hipSuccess && hipMalloc(&b->d_queue, 8) == hipSuccess &&
             hipMalloc(&b->d_ptab, 4 * 97 * b->max_chunks) == hipSuccess && hipEventCreate(&b->last) == hipSuccess;
   if (ok) {
     *b->h_err = 0;
-    ok = hipMemset(b->d_done, 0, 4 * ngroups) == hipSuccess && hipMemset(b->d_queue, 0, 8) == hipSuccess &&
+    ok = hipMemset(b->d_done, 0, 4 * nflags) == hipSuccess && hipMemset(b->d_queue, 0, 8) == hipSuccess &&
          hipStreamCreate(&st) == hipSuccess;
   }
   if (ok) ok = fill_ptab(b->d_ptab, b->max_chunks, b->L, st) == hipSuccess;
@@ -158,7 +186,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
     b->B.queue = b->d_queue;
     b->B.err = b->h_err;
     b->B.wtab = window_table();
-    b->B.spare = (uint32_t)b->max_req;
+    b->B.spare = (uint32_t)b->max_slices;
     ok = b->B.wtab != nullptr;
   }
   if (ok) {
@@ -167,16 +195,11 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
          hipGraphAddMemcpyNode1D(&b->cpy, b->graph, nullptr, 0, b->d_desc, b->h_desc, b->desc_cap,
                                  hipMemcpyHostToDevice) == hipSuccess;
     if (ok) {
-      hipKernelNodeParams kp{};
-      void* args[] = {(void*)&b->kdesc, (void*)&b->B};
-      kp.func = (void*)k_batch_tables;
-      kp.gridDim = dim3(b->grid);
-      kp.blockDim = dim3(64);
-      kp.sharedMemBytes = 0;
-      kp.kernelParams = args;
-      kp.extra = nullptr;
+      const unsigned grid = b->workers_max;
+      const hipKernelNodeParams kp = kernel_params(b, grid);
       ok = hipGraphAddKernelNode(&b->kern, b->graph, &b->cpy, 1, &kp) == hipSuccess &&
            hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+      b->grid_node = grid;
     }
   }
   if (!ok) {
@@ -200,32 +223,87 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     total += nq;
   }
   if (total > b->max_chunks) return RANMAR_ENOMEM;
-  const uint64_t chunk_off = (64 + sizeof(BReq) * n + 15) & ~15ull;
+  // Bins: about 4 units of work (jumps + chunks) per bin at least, at most 64.
+  const uint64_t cost = n + total;
+  const uint32_t nb = (uint32_t)std::min<uint64_t>(kMaxBins, std::max<uint64_t>(1, cost / 4));
+  const uint64_t T = (cost + nb - 1) / nb;  // work per bin; >= 4 when nb > 1
+  const uint64_t req_off = req_offset(nb), chunk_off = chunk_offset(n, nb);
   // The staging buffer may still be read by the previous run's copy.
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
   BHeader* h = (BHeader*)b->h_desc;
-  std::memset(h, 0, sizeof(BHeader));
-  h->n_req = (uint32_t)n;
-  h->n_jg = (uint32_t)((n + 1) / 2);
-  h->n_chunks = (uint32_t)total;
-  h->n_cg = (uint32_t)((total + 1) / 2);
-  h->epoch = ++b->epoch;
-  h->L = b->L;
-  h->chunk_off = chunk_off;
-  BReq* rq = (BReq*)(b->h_desc + 64);
+  BBin* bins = (BBin*)(b->h_desc + 64);
+  BReq* sl = (BReq*)(b->h_desc + req_off);
   BChunk* ch = (BChunk*)(b->h_desc + chunk_off);
-  uint64_t j = 0;
+  std::memset(b->h_desc, 0, req_off);
+  const uint64_t L = b->L;
+  uint64_t ns = 0, nc = 0, fill = 0;
+  uint32_t x = 0;
   for (uint64_t r = 0; r < n; ++r) {
-    rq[r] = to_breq(reqs[r]);
-    const uint64_t nq = (reqs[r].count + b->L - 1) / b->L;
-    for (uint64_t q = 0; q < nq; ++q, ++j) {
-      ch[j].req = (uint32_t)r;
-      ch[j].q = (uint32_t)q;
-      const uint64_t rem = reqs[r].count - q * b->L;
-      ch[j].draws = (uint32_t)(rem < b->L ? rem : b->L);
-      ch[j].last = (q + 1 == nq) ? 1u : 0u;
+    const ranmar_request& q = reqs[r];
+    const uint64_t nq = (q.count + L - 1) / L;
+    uint64_t first = 0;  // chunks of request r placed so far
+    for (;;) {
+      const uint64_t left = nq - first;
+      uint64_t take = left;
+      if (x + 1 < nb) {
+        // Chunks that still fit beside this slice's jump.
+        const uint64_t room = fill + 1 < T ? T - fill - 1 : 0;
+        if (fill > 0 && (fill + 1 > T || (left > 0 && room == 0))) {
+          bins[x].ns = (uint32_t)(ns - bins[x].s0);
+          bins[x].nk = (uint32_t)(nc - bins[x].k0);
+          ++x;
+          bins[x].s0 = (uint32_t)ns;
+          bins[x].k0 = (uint32_t)nc;
+          fill = 0;
+          continue;
+        }
+        if (take > room) take = room;
+      }
+      const uint64_t d0 = first * L;
+      BReq& s = sl[ns];
+      s = to_breq(q);
+      const unsigned __int128 off = ((unsigned __int128)q.offset.hi << 64 | q.offset.lo) + d0;
+      s.off_lo = (uint64_t)off;
+      s.off_hi = (uint64_t)(off >> 64);
+      s.count = std::min<uint64_t>(q.count - d0, take * L);
+      s.out = q.count ? s.out + 4 * d0 : s.out;
+      s.state = (first + take == nq) ? s.state : 0;
+      for (uint64_t k = 0; k < take; ++k, ++nc) {
+        ch[nc].req = (uint32_t)ns;
+        ch[nc].q = (uint32_t)k;
+        const uint64_t rem = s.count - k * L;
+        ch[nc].draws = (uint32_t)(rem < L ? rem : L);
+        ch[nc].last = (k + 1 == take) ? 1u : 0u;
+      }
+      ++ns;
+      fill += 1 + take;
+      first += take;
+      if (first == nq) break;
     }
   }
+  bins[x].ns = (uint32_t)(ns - bins[x].s0);
+  bins[x].nk = (uint32_t)(nc - bins[x].k0);
+  const uint32_t nbu = x + 1;
+  // Workgroups per bin: as many as the fullest bin has items, within the
+  // device.  Jump pairs are taken g at a time when a bin has many.
+  const uint32_t wpb_max = b->workers_max / nbu;
+  uint32_t wpb = 1;
+  for (uint32_t i = 0; i < nbu; ++i) {
+    const uint32_t n_jg = (bins[i].ns + 1) / 2;
+    uint32_t g = n_jg / (2u * wpb_max);
+    g = g < 1u ? 1u : (g > 8u ? 8u : g);
+    bins[i].g = g;
+    bins[i].n_ju = (n_jg + g - 1) / g;
+    bins[i].n_cg = (bins[i].nk + 1) / 2;
+    wpb = std::max(wpb, std::min(wpb_max, bins[i].n_ju + bins[i].n_cg));
+  }
+  h->n_bins = nbu;
+  h->n_workers = nbu * wpb;
+  h->epoch = ++b->epoch;
+  h->L = b->L;
+  h->req_off = req_off;
+  h->chunk_off = chunk_off;
+  b->grid_prepared = h->n_workers;
   b->prepared_bytes = chunk_off + sizeof(BChunk) * total;
   return RANMAR_OK;
 }
@@ -242,6 +320,11 @@ int ranmar_batch_launch(ranmar_batch* b, void* stream) {
   if (hipGraphExecMemcpyNodeSetParams1D(b->exec, b->cpy, b->d_desc, b->h_desc, bytes, hipMemcpyHostToDevice) !=
       hipSuccess)
     return RANMAR_EHIP;
+  if (b->grid_prepared != b->grid_node) {
+    const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared);
+    if (hipGraphExecKernelNodeSetParams(b->exec, b->kern, &kp) != hipSuccess) return RANMAR_EHIP;
+    b->grid_node = b->grid_prepared;
+  }
   if (hipGraphLaunch(b->exec, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
   if (hipEventRecord(b->last, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
   b->launched = true;
@@ -323,7 +406,7 @@ extern "C" int ranmar_run_unbatched(const ranmar_request* reqs, uint64_t n, void
     *(volatile int*)c.err = 0;
     return RANMAR_EHIP;
   }
-  const unsigned maxgrid = persistent_grid();
+  const unsigned maxgrid = persistent_grid((const void*)k_batch_single, 64);
   for (uint64_t r = 0; r < n; ++r) {
     const uint64_t nq = (reqs[r].count + kDefaultChunk - 1) / kDefaultChunk;
     rc = ub_reserve(c, nq ? nq : 1, st);

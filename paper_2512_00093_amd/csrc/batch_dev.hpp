@@ -8,19 +8,24 @@
 // jump (Sec. 3.2): the jumps compose exactly (f^a o f^b = f^(a+b)), so every
 // chunk's draws are exactly those of the request's single stream.
 //
-// Work items, taken in order from an atomic counter by one-wave workgroups
-// (jump pairs g at a time when there are many):
-//   [0, n_jg)           jump pairs: each half-wave seeds one request and jumps
-//                       it to its offset (parallel seeding and the windowed
-//                       jump of coop_dev.hpp), then raises the request's flag;
-//   [n_jg, n_jg + n_cg) chunk pairs: each half-wave places one chunk start
-//                       (P_{qL} applied to the request's start state, in LDS)
-//                       and generates the chunk's draws.
-// A chunk waits for its request's flag (flag == run epoch, so flags never
-// need clearing).  All jump pairs precede all chunk pairs in the queue, so the
-// request a chunk waits for has already been taken by a running wave; the wait
-// is still bounded, and a wait that runs out sets the host-visible error word
-// instead of hanging.
+// The work is split into bins (up to 64).  A bin is a contiguous range of
+// slices (a slice is a request or an exact part of one: offset + first draw,
+// its own seed + jump) and of their chunks, and has its own queue counter on
+// its own 256-byte line: one counter shared by the whole grid serialises
+// every dequeue at one memory channel.  Workgroup w serves bin w mod n_bins.
+// Items of a bin, taken in order from its counter by one-wave workgroups:
+//   [0, n_ju)            jump groups: g jump pairs; each half-wave seeds one
+//                        slice and jumps it to its offset (parallel seeding
+//                        and the windowed jump of coop_dev.hpp), then raises
+//                        the slice's flag;
+//   [n_ju, n_ju + n_cg)  chunk pairs: each half-wave places one chunk start
+//                        (P_{qL} applied to the slice's start state, in LDS)
+//                        and generates the chunk's draws.
+// A chunk waits for its slice's flag (flag == run epoch, so flags never need
+// clearing).  A chunk's slice is in the chunk's own bin and every jump item of
+// a bin precedes its chunk items, so the jump a chunk waits for has already
+// been taken by a running wave; the wait is still bounded, and a wait that
+// runs out sets the host-visible error word instead of hanging.
 #pragma once
 
 #include "common.hpp"
@@ -30,10 +35,17 @@
 namespace ranmar {
 
 struct BHeader {        // 64 bytes
-  uint32_t n_req, n_jg, n_chunks, n_cg;
-  uint32_t epoch, L, pad0, pad1;
+  uint32_t n_bins, n_workers, epoch, L;  // n_workers: one-wave workgroups launched
+  uint64_t req_off;     // byte offset of the slice table from the header
   uint64_t chunk_off;   // byte offset of the chunk table from the header
-  uint64_t pad[3];
+  uint64_t pad[4];
+};
+struct BBin {           // 256 bytes: the counter alone on its line
+  uint32_t ctr;         // next item (0 at launch: the descriptor copy resets it)
+  uint32_t s0, ns;      // slices [s0, s0 + ns)
+  uint32_t k0, nk;      // chunks [k0, k0 + nk)
+  uint32_t g, n_ju, n_cg;  // jump pairs per jump item, jump items, chunk pairs
+  uint32_t pad[56];
 };
 struct BReq {           // 48 bytes
   int32_t seed;
@@ -44,54 +56,91 @@ struct BReq {           // 48 bytes
   uint64_t state;
 };
 struct BChunk {         // 16 bytes
-  uint32_t req, q, draws, last;
+  uint32_t req, q, draws, last;  // slice, chunk index in the slice, draws, last of the slice
 };
-static_assert(sizeof(BHeader) == 64 && sizeof(BReq) == 48 && sizeof(BChunk) == 16, "descriptor layout");
+static_assert(sizeof(BHeader) == 64 && sizeof(BBin) == 256 && sizeof(BReq) == 48 && sizeof(BChunk) == 16,
+              "descriptor layout");
+constexpr uint32_t kMaxBins = 64;
+
+// A bin's ranges, as held in registers (the counter is only touched atomically).
+struct BinInfo {
+  uint32_t s0, ns, k0, nk, g, n_ju, n_cg;
+};
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // x ~100 cycles per sleep: about 0.2 s
 
 // Descriptor access: either tables in device memory, or a single request
 // passed by value (the one-launch-per-request path).
 struct TableDesc {
-  const uint8_t* desc;
+  uint8_t* desc;
   __device__ __forceinline__ BHeader header() const { return *(const BHeader*)desc; }
-  __device__ __forceinline__ BReq req(uint32_t r) const { return ((const BReq*)(desc + 64))[r]; }
+  __device__ __forceinline__ BinInfo bin(uint32_t x) const {
+    const BBin* b = (const BBin*)(desc + 64) + x;
+    return BinInfo{b->s0, b->ns, b->k0, b->nk, b->g, b->n_ju, b->n_cg};
+  }
+  __device__ __forceinline__ uint32_t* counter(uint32_t x, uint32_t*) const { return &((BBin*)(desc + 64))[x].ctr; }
+  __device__ __forceinline__ BReq req(const BHeader& h, uint32_t r) const {
+    return ((const BReq*)(desc + h.req_off))[r];
+  }
   __device__ __forceinline__ BChunk chunk(const BHeader& h, uint32_t j) const {
     return ((const BChunk*)(desc + h.chunk_off))[j];
   }
+  // The counters are reset by the next launch's descriptor copy.
+  __device__ __forceinline__ void finish(uint32_t*) const {}
 };
 struct SingleDesc {
   BReq r0;
   uint32_t L, epoch;
   __device__ __forceinline__ BHeader header() const {
     BHeader h{};
-    const uint64_t nq = (r0.count + L - 1) / L;
-    h.n_req = 1;
-    h.n_jg = 1;  // one jump pair, its second half idle
-    h.n_chunks = (uint32_t)nq;
-    h.n_cg = (uint32_t)((nq + 1) / 2);
+    h.n_bins = 1;
+    h.n_workers = gridDim.x;
     h.epoch = epoch;
     h.L = L;
     return h;
   }
-  __device__ __forceinline__ BReq req(uint32_t) const { return r0; }
+  __device__ __forceinline__ BinInfo bin(uint32_t) const {
+    BinInfo b;
+    const uint64_t nq = (r0.count + L - 1) / L;
+    b.s0 = 0;
+    b.ns = 1;  // one jump pair, its second half idle
+    b.k0 = 0;
+    b.nk = (uint32_t)nq;
+    b.g = 1;
+    b.n_ju = 1;
+    b.n_cg = (uint32_t)((nq + 1) / 2);
+    return b;
+  }
+  __device__ __forceinline__ uint32_t* counter(uint32_t, uint32_t* queue) const { return queue; }
+  __device__ __forceinline__ BReq req(const BHeader&, uint32_t) const { return r0; }
   __device__ __forceinline__ BChunk chunk(const BHeader& h, uint32_t j) const {
     BChunk c;
     c.req = 0;
     c.q = j;
     const uint64_t first = (uint64_t)j * h.L;
     c.draws = (uint32_t)((r0.count - first) < h.L ? (r0.count - first) : h.L);
-    c.last = (j + 1 == h.n_chunks) ? 1u : 0u;
+    c.last = (first + h.L >= r0.count) ? 1u : 0u;
     return c;
+  }
+  // The last workgroup out resets the counters for the next launch.
+  __device__ __forceinline__ void finish(uint32_t* queue) const {
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const uint32_t f = atomicAdd(&queue[1], 1u);
+      if (f == gridDim.x - 1) {
+        atomicExch(&queue[0], 0u);
+        atomicExch(&queue[1], 0u);
+      }
+    }
   }
 };
 
 struct BatchBuffers {
-  uint32_t* req_states;    // 98 words per request
-  uint32_t* done;          // one flag per request, plus one spare written by idle halves
+  uint32_t* req_states;    // 98 words per slice
+  uint32_t* done;          // one flag per slice, plus one spare written by idle halves
   const uint32_t* ptab;    // 97 words per q: P_{qL}
   const uint32_t* wtab;    // window table T[w][d]
-  uint32_t* queue;         // [0] next item, [1] finished workgroups
+  uint32_t* queue;         // single-request launches: [0] next item, [1] finished workgroups
   int* err;                // host-visible error word
   uint32_t spare;          // index of the spare flag
 };
@@ -99,17 +148,39 @@ struct BatchBuffers {
 // LDS per half-wave: the extended window X (193 words) and a polynomial (97).
 constexpr int kHalfLds = 193 + 97;
 
+// Hand-off of a slice's start state from the wave that jumped it to the waves
+// that generate its chunks, which may run on other XCDs (each XCD has its own
+// L2).  The producer writes the words with device-scope stores, which are
+// written through to the device's coherence point and acknowledged from
+// there; publish_wait waits for those acknowledgements (vmcnt = 0) before
+// the flag is stored.  The consumers poll the flag and then read the words
+// with device-scope loads, which are served from the coherence point rather
+// than from a possibly stale L2 line.  This gives the same visibility as an
+// agent-scope release/acquire pair without that pair's whole-L2 writeback
+// and invalidate (one of each per slice and per chunk).
+__device__ __forceinline__ void dev_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t dev_load(uint32_t* p) {
+  return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void publish_wait() {
+  __builtin_amdgcn_s_waitcnt(0);  // all counters zero: every store above has been acknowledged
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps the flag store after it in program order
+}
+
 template <class Desc>
-__device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h, const BatchBuffers& B, uint32_t p,
-                                                uint32_t* lds) {
+__device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h, const BatchBuffers& B,
+                                                const BinInfo& bn, uint32_t p, uint32_t* lds) {
   const uint32_t lane = threadIdx.x;
   const uint32_t half = lane >> 5, l = lane & 31u;
-  const uint32_t r = 2u * p + half;
-  const bool active = r < h.n_req;
+  const uint32_t rl = 2u * p + half;
+  const bool active = rl < bn.ns;
+  const uint32_t r = bn.s0 + rl;
   uint32_t* X = lds + half * kHalfLds;
   uint32_t* Bp = X + 193;
   BReq q{};
-  if (active) q = D.req(r);
+  if (active) q = D.req(h, r);
   const bool valid = active && seed_half(q.seed, X, l);
   if (!valid) X[l] = X[l + 32] = X[l + 64] = X[97] = 0;
   wave_sync();
@@ -118,22 +189,24 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
   jump_half(X, Bp, B.wtab, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
   // A request with no draws but a state output is written straight to the
-  // caller's record.
+  // caller's record.  The words go out as device-scope stores (written
+  // through to the device's coherence point, see publish_wait), so chunks on
+  // other XCDs can read them without an L2 writeback here or an L2
+  // invalidate there.
   uint32_t* slot = (active && q.count == 0 && q.state) ? (uint32_t*)q.state : B.req_states + (uint64_t)r * kWords;
   if (active) {
-    slot[l] = valid ? X[l] : 0u;
-    slot[l + 32] = valid ? X[l + 32] : 0u;
-    slot[l + 64] = valid ? X[l + 64] : 0u;
+    dev_store(slot + l, valid ? X[l] : 0u);
+    dev_store(slot + l + 32, valid ? X[l + 32] : 0u);
+    dev_store(slot + l + 64, valid ? X[l + 64] : 0u);
     if (l == 0) {
-      slot[96] = valid ? X[96] : 0u;
-      slot[97] = valid ? c_jump(c, u128_mod_m(j0, j1, j2, j3)) : kInvalidC;
+      dev_store(slot + 96, valid ? X[96] : 0u);
+      dev_store(slot + 97, valid ? c_jump(c, u128_mod_m(j0, j1, j2, j3)) : kInvalidC);
     }
   }
-  // Only requests with draws have chunks waiting for them.  The release fence
-  // writes back this XCD's L2, so it is skipped when no request of the pair
-  // has consumers (jump-only batches); the test is wave-uniform.
+  // Only slices with draws have chunks waiting for them (the test is
+  // wave-uniform).
   if (__any(active && q.count > 0)) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    publish_wait();
     // Every lane of the half stores the same value (idle halves to the spare).
     __hip_atomic_store(&B.done[active ? r : B.spare], h.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -141,19 +214,23 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
 }
 
 template <class Desc>
-__device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h, const BatchBuffers& B, uint32_t cp,
-                                                 uint32_t* lds) {
+__device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h, const BatchBuffers& B,
+                                                 const BinInfo& bn, uint32_t cp, uint32_t* lds) {
   const uint32_t lane = threadIdx.x;
   const uint32_t half = lane >> 5, l = lane & 31u;
-  const uint32_t j = 2u * cp + half;
-  const bool active = j < h.n_chunks;
+  const uint32_t jl = 2u * cp + half;
+  const bool active = jl < bn.nk;
+  const uint32_t j = bn.k0 + jl;
   uint32_t* X = lds + half * kHalfLds;
   uint32_t* Bp = X + 193;
   BChunk ch{};
   BReq rq{};
+  if (active) ch = D.chunk(h, j);
+  // P_{qL} does not depend on the slice: fetch it before waiting.
+  const uint32_t* P = B.ptab + (uint64_t)ch.q * 97u;
+  const uint32_t p0 = P[l], p1 = P[l + 32], p2 = P[l + 64], p3 = P[96];
   if (active) {
-    ch = D.chunk(h, j);
-    rq = D.req(ch.req);
+    rq = D.req(h, ch.req);
     uint32_t it = 0;
     while (__hip_atomic_load(&B.done[ch.req], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != h.epoch) {
       __builtin_amdgcn_s_sleep(2);
@@ -163,21 +240,22 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
       }
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  // Chunk start: the request's start state times P_{qL}(A), c by qL steps.
-  const uint32_t* src = B.req_states + (uint64_t)ch.req * kWords;
-  const uint32_t* P = B.ptab + (uint64_t)ch.q * 97u;
-  X[l] = active ? src[l] : 0u;
-  X[l + 32] = active ? src[l + 32] : 0u;
-  X[l + 64] = active ? src[l + 64] : 0u;
-  Bp[l] = P[l];
-  Bp[l + 32] = P[l + 32];
-  Bp[l + 64] = P[l + 64];
+  // No loads below may be moved above the wait (the fence emits no code at
+  // this scope; the words are read with device-scope loads).
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  // Chunk start: the slice's start state times P_{qL}(A), c by qL steps.
+  uint32_t* src = B.req_states + (uint64_t)ch.req * kWords;
+  X[l] = active ? dev_load(src + l) : 0u;
+  X[l + 32] = active ? dev_load(src + l + 32) : 0u;
+  X[l + 64] = active ? dev_load(src + l + 64) : 0u;
+  Bp[l] = p0;
+  Bp[l + 32] = p1;
+  Bp[l + 64] = p2;
   if (l == 0) {
-    X[96] = active ? src[96] : 0u;
-    Bp[96] = P[96];
+    X[96] = active ? dev_load(src + 96) : 0u;
+    Bp[96] = p3;
   }
-  const uint32_t c0 = active ? src[97] : 0u;
+  const uint32_t c0 = active ? dev_load(src + 97) : 0u;
   wave_sync();
   apply_half(X, Bp, l);
   if (l == 0) X[97] = c_jump(c0, (uint32_t)(((uint64_t)ch.q * h.L) % kMod));
@@ -190,42 +268,36 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   wave_sync();
 }
 
+// One-wave workgroups; workgroup w serves bin w mod n_bins.  The bin index
+// and everything derived from it stay wave-uniform (scalar registers).
 template <class Desc>
 __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B) {
   const BHeader h = D.header();
   const uint32_t lane = threadIdx.x;
   __shared__ uint32_t lds[2 * kHalfLds];
-  // Jump pairs are taken g at a time when there are many (one queue atomic per
-  // g pairs instead of per pair); small batches keep g = 1 for latency.
-  uint32_t g = h.n_jg / (2u * gridDim.x);
-  g = g < 1u ? 1u : (g > 8u ? 8u : g);
-  const uint32_t n_ju = (h.n_jg + g - 1) / g;
+  if (blockIdx.x >= h.n_workers) return;
+  const uint32_t x = blockIdx.x % h.n_bins;
+  const BinInfo bn = D.bin(x);
+  uint32_t* ctr = D.counter(x, B.queue);
+  const uint32_t n_jg = (bn.ns + 1) / 2;
   for (;;) {
     // Dequeue without a lane-conditional branch: every lane executes the
     // atomic, lane 0 adding 1 and the others 0, and lane 0's result is taken.
     // (With `if (lane == 0) item = atomicAdd(...)` only lane 0 holds the item,
     // and the compiler may merge that branch with other lane-0 branches of
     // the loop body so that lanes 1..63 re-enter the body on a stale item.)
-    const uint32_t got = atomicAdd(&B.queue[0], lane == 0 ? 1u : 0u);
+    const uint32_t got = atomicAdd(ctr, lane == 0 ? 1u : 0u);
     const uint32_t item = __builtin_amdgcn_readfirstlane(got);
-    if (item < n_ju) {
-      const uint32_t p1 = (item + 1) * g < h.n_jg ? (item + 1) * g : h.n_jg;
-      for (uint32_t p = item * g; p < p1; ++p) batch_jump_pair(D, h, B, p, lds);
-    } else if (item < n_ju + h.n_cg) {
-      batch_chunk_pair(D, h, B, item - n_ju, lds);
+    if (item < bn.n_ju) {
+      const uint32_t p1 = (item + 1) * bn.g < n_jg ? (item + 1) * bn.g : n_jg;
+      for (uint32_t p = item * bn.g; p < p1; ++p) batch_jump_pair(D, h, B, bn, p, lds);
+    } else if (item < bn.n_ju + bn.n_cg) {
+      batch_chunk_pair(D, h, B, bn, item - bn.n_ju, lds);
     } else {
       break;
     }
   }
-  // The last workgroup out resets the counters for the next launch.
-  if (lane == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t f = atomicAdd(&B.queue[1], 1u);
-    if (f == gridDim.x - 1) {
-      atomicExch(&B.queue[0], 0u);
-      atomicExch(&B.queue[1], 0u);
-    }
-  }
+  D.finish(B.queue);
 }
 
 }  // namespace ranmar

@@ -24,6 +24,14 @@ constexpr uint32_t kC0 = 362436u;      // c'_0
 constexpr uint32_t kWords = 98;        // words per ranmar_state record
 constexpr uint32_t kInvalidC = 0xFFFFFFFFu;  // c of a record made from a bad seed
 
+// Device memory seen through the global address space.  A pointer rebuilt
+// from a 64-bit integer (the batch descriptors) is generic to the compiler,
+// and generic ("flat") stores also count against the LDS wait counter: a loop
+// that waits for an LDS permute would then wait for its own stores as well.
+// Only for pointers into device memory (never LDS).
+typedef __attribute__((address_space(1))) uint32_t gu32;
+__device__ __forceinline__ gu32* gptr(void* p) { return (gu32*)p; }
+
 // (m - (k d' mod m)): adding this mod m steps c forward by k draws.
 constexpr uint32_t c_step(uint64_t k) { return (uint32_t)(kMod - (k * kD) % kMod) % kMod; }
 

@@ -186,18 +186,33 @@ __device__ __forceinline__ void apply_half(uint32_t* X, const uint32_t* B, uint3
 
 // In place: X[0..96] <- f_1^J applied to X (the c part is left to the caller).
 // T: the window table, T + (w * 256 + d) * 97.  J given as 32-bit limbs.
-// `nwin`: number of low windows to apply (uniform over the wave).
+// `nwin`: number of low windows to apply (uniform over the wave).  The next
+// window's row is loaded while the current one is applied.
+__device__ __forceinline__ const uint32_t* window_row(const uint32_t* __restrict__ T, uint32_t j0, uint32_t j1,
+                                                      uint32_t j2, uint32_t j3, int w) {
+  const uint32_t limb = w < 4 ? j0 : w < 8 ? j1 : w < 12 ? j2 : j3;
+  const uint32_t d = (limb >> (8 * (w & 3))) & 0xFFu;
+  return T + ((uint64_t)w * kWinDigits + d) * 97u;
+}
+
 __device__ __forceinline__ void jump_half(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
                                           uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
+  if (nwin <= 0) return;
+  const uint32_t* row = window_row(T, j0, j1, j2, j3, 0);
+  uint32_t r0 = row[l], r1 = row[l + 32], r2 = row[l + 64], r3 = row[96];
   for (int w = 0; w < nwin; ++w) {
-    const uint32_t limb = w < 4 ? j0 : w < 8 ? j1 : w < 12 ? j2 : j3;
-    const uint32_t d = (limb >> (8 * (w & 3))) & 0xFFu;
-    const uint32_t* row = T + ((uint64_t)w * kWinDigits + d) * 97u;
-    B[l] = row[l];
-    B[l + 32] = row[l + 32];
-    B[l + 64] = row[l + 64];
-    if (l == 0) B[96] = row[96];
+    B[l] = r0;
+    B[l + 32] = r1;
+    B[l + 64] = r2;
+    if (l == 0) B[96] = r3;
     wave_sync();
+    if (w + 1 < nwin) {
+      row = window_row(T, j0, j1, j2, j3, w + 1);
+      r0 = row[l];
+      r1 = row[l + 32];
+      r2 = row[l + 64];
+      r3 = row[96];
+    }
     apply_half(X, B, l);
   }
 }

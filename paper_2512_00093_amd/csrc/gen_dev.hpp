@@ -24,6 +24,7 @@
 namespace ranmar {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
 
 // Runtime-format variant of the output stage (FMT_RUNTIME): both encodings
 // are formed and the word for the stream's format is stored, so two half-waves
@@ -41,7 +42,7 @@ __device__ __forceinline__ void emit(void* row, uint64_t idx, uint32_t k, bool i
     const uint32_t fw = __float_as_uint((float)k * 0x1p-24f);
     w = is_f32 ? fw : k;
   }
-  uint32_t* p = (uint32_t*)row + idx;
+  gu32* p = gptr(row) + idx;
   if (NT)
     __builtin_nontemporal_store(w, p);
   else
@@ -62,12 +63,13 @@ __device__ __forceinline__ void gen_stream32(uint32_t l, uint32_t lane, const ui
 
   if (count == 0) {
     if (dst && dst != W) {
-      dst[l] = s97 & kMask;
-      dst[32 + l] = s65 & kMask;
-      dst[64 + l] = s33 & kMask;
+      gu32* d = gptr(dst);
+      d[l] = s97 & kMask;
+      d[32 + l] = s65 & kMask;
+      d[64 + l] = s33 & kMask;
       if (l == 0) {
-        dst[96] = rprev & kMask;
-        dst[97] = c0;
+        d[96] = rprev & kMask;
+        d[97] = c0;
       }
     }
     return;
@@ -121,12 +123,13 @@ __device__ __forceinline__ void gen_stream32(uint32_t l, uint32_t lane, const ui
     // The new window x_{count+1..count+97} is covered by what the lanes hold:
     // s97 -> slot l-rr (l >= rr), s65 -> 32+l-rr, s33 -> 64+l-rr,
     // lane 0's rprev -> 96-rr, v -> 97+l-rr (l < rr); c_count sits in lane rr-1.
-    if (l >= rr) dst[l - rr] = s97 & kMask;
-    dst[32 + l - rr] = s65 & kMask;
-    dst[64 + l - rr] = s33 & kMask;
-    if (lead) dst[96 - rr] = rprev & kMask;
-    if (l < rr) dst[97 + l - rr] = v & kMask;
-    if (l == rr - 1) dst[97] = c;
+    gu32* d = gptr(dst);
+    if (l >= rr) d[l - rr] = s97 & kMask;
+    d[32 + l - rr] = s65 & kMask;
+    d[64 + l - rr] = s33 & kMask;
+    if (lead) d[96 - rr] = rprev & kMask;
+    if (l < rr) d[97 + l - rr] = v & kMask;
+    if (l == rr - 1) d[97] = c;
   }
 }
 
@@ -168,7 +171,7 @@ __device__ __forceinline__ void gen_stream32_wide(uint32_t l, uint32_t lane, con
     rprev = rot;
     return y;
   };
-  u32x4* row4 = (u32x4*)out_row;
+  gu32x4* row4 = (gu32x4*)out_row;
   // Four blocks (roles (A, B, C) -> (B, C, A)), transposed through LDS and
   // stored as 16 bytes per lane.
   auto macro = [&](uint32_t& A, uint32_t& B, uint32_t& C, uint64_t m) {
@@ -206,7 +209,7 @@ __device__ __forceinline__ void gen_stream32_wide(uint32_t l, uint32_t lane, con
     s33 = t;
   }
   // Remaining full blocks one at a time, then the last block.
-  uint32_t* row = (uint32_t*)out_row + l;
+  gu32* row = gptr(out_row) + l;
   uint64_t q = nmacro * 4;
   for (; q + 1 < nblk; ++q) {
     const uint32_t y = step(s97, s33);
@@ -229,12 +232,13 @@ __device__ __forceinline__ void gen_stream32_wide(uint32_t l, uint32_t lane, con
       row[q * 32u] = y;
   }
   if (dst) {
-    if (l >= rr) dst[l - rr] = s97 & kMask;
-    dst[32 + l - rr] = s65 & kMask;
-    dst[64 + l - rr] = s33 & kMask;
-    if (lead) dst[96 - rr] = rprev & kMask;
-    if (l < rr) dst[97 + l - rr] = v & kMask;
-    if (l == rr - 1) dst[97] = c;
+    gu32* d = gptr(dst);
+    if (l >= rr) d[l - rr] = s97 & kMask;
+    d[32 + l - rr] = s65 & kMask;
+    d[64 + l - rr] = s33 & kMask;
+    if (lead) d[96 - rr] = rprev & kMask;
+    if (l < rr) d[97 + l - rr] = v & kMask;
+    if (l == rr - 1) d[97] = c;
   }
 }
 

@@ -51,6 +51,7 @@ struct Req {
   uint64_t count, next = 0, pending = 0;
   uint64_t aoff = 0, bytes = 0;
   uint64_t t_arr = 0, t_done = 0;
+  uint64_t tag = 0;  // replay: request index + 1; 0 for ordinary submissions
   int st = QUEUED;
 };
 
@@ -98,6 +99,8 @@ struct ranmar_server {
   std::condition_variable cv_srv, cv_done;
 
   std::vector<double> lat;
+  bool track_done = false;       // keep completed tickets in done_q (replay)
+  std::vector<uint64_t> done_q;  // tickets completed since the last drain
   uint64_t submitted = 0, completed = 0, released = 0, rejected = 0, ticks = 0, draws = 0;
   uint64_t t_first = 0, t_last = 0;
   int err = 0;
@@ -142,7 +145,18 @@ struct ranmar_server {
     ++completed;
     draws += R.count;
     t_last = when;
+    if (track_done) done_q.push_back(t);
   }
+
+  void release_locked(std::unordered_map<uint64_t, Req>::iterator it) {
+    dealloc(it->second.aoff, it->second.count ? it->second.bytes : 0);
+    --inflight;
+    ++released;
+    reqs.erase(it);
+  }
+
+  int submit_locked(int32_t seed, ranmar_u128 offset, uint64_t count, int fmt, uint64_t t_arrival_ns, uint64_t tag,
+                    uint64_t* ticket);
 
   // Server thread body.
   void loop() {
@@ -211,13 +225,18 @@ struct ranmar_server {
           if (cfg.unbatched) break;  // one request per launch
         }
         if (ln.reqbuf.empty()) continue;
-        int rc = cfg.unbatched ? ranmar_run_unbatched(ln.reqbuf.data(), ln.reqbuf.size(), ln.st)
-                               : ranmar_batch_run(ln.b, ln.reqbuf.data(), ln.reqbuf.size(), ln.st);
-        if (rc == RANMAR_OK && hipEventRecord(ln.ev, ln.st) != hipSuccess) rc = RANMAR_EHIP;
-        if (rc != RANMAR_OK) err = rc;
         ln.busy = true;  // its event (or the failure) is picked up above
         ++ticks;
         progress = true;
+        // Descriptor preparation and the launch run without the lock, so
+        // submissions and releases go on meanwhile (only this thread uses the
+        // lane).
+        lk.unlock();
+        int rc = cfg.unbatched ? ranmar_run_unbatched(ln.reqbuf.data(), ln.reqbuf.size(), ln.st)
+                               : ranmar_batch_run(ln.b, ln.reqbuf.data(), ln.reqbuf.size(), ln.st);
+        if (rc == RANMAR_OK && hipEventRecord(ln.ev, ln.st) != hipSuccess) rc = RANMAR_EHIP;
+        lk.lock();
+        if (rc != RANMAR_OK) err = rc;
       }
       if (progress) continue;
       bool any_busy = false;
@@ -235,6 +254,47 @@ struct ranmar_server {
     }
   }
 };
+
+int ranmar_server::submit_locked(int32_t seed, ranmar_u128 offset, uint64_t count, int fmt, uint64_t t_arrival_ns,
+                                 uint64_t tag, uint64_t* ticket) {
+  if (seed < 1 || seed > 900000000 || (fmt != RANMAR_U24 && fmt != RANMAR_F32)) return RANMAR_EINVAL;
+  if (count > (UINT64_MAX - kAlign) / 4) return RANMAR_ENOMEM;
+  const uint64_t nbytes = (4 * count + kAlign - 1) & ~(kAlign - 1);
+  if (nbytes > arena_bytes) {
+    ++rejected;
+    return RANMAR_ENOMEM;
+  }
+  if (!cfg.queue_when_full &&
+      (in_use + queued_bytes + nbytes > arena_bytes || inflight + queue.size() >= cfg.max_inflight)) {
+    ++rejected;
+    return RANMAR_EAGAIN;
+  }
+  const uint64_t t = next_ticket++;
+  Req R{};
+  R.seed = seed;
+  R.fmt = fmt;
+  R.off = offset;
+  R.count = count;
+  R.bytes = nbytes;
+  R.tag = tag;
+  R.t_arr = t_arrival_ns ? t_arrival_ns : now_ns();
+  if (!t_first) t_first = now_ns();
+  ++submitted;
+  if (count == 0) {
+    R.st = ADMITTED;
+    ++inflight;
+    auto& ref = reqs[t] = R;
+    complete(t, ref, now_ns());
+    cv_done.notify_all();
+  } else {
+    reqs[t] = R;
+    queue.push_back(t);
+    queued_bytes += nbytes;
+    cv_srv.notify_one();
+  }
+  *ticket = t;
+  return RANMAR_OK;
+}
 
 extern "C" {
 
@@ -283,44 +343,8 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
 int ranmar_serve_submit(ranmar_server* s, int32_t seed, ranmar_u128 offset, uint64_t count, int fmt,
                         uint64_t t_arrival_ns, uint64_t* ticket) {
   if (!s || !ticket) return RANMAR_EINVAL;
-  if (seed < 1 || seed > 900000000 || (fmt != RANMAR_U24 && fmt != RANMAR_F32)) return RANMAR_EINVAL;
-  if (count > (UINT64_MAX - kAlign) / 4) return RANMAR_ENOMEM;
-  const uint64_t bytes = (4 * count + kAlign - 1) & ~(kAlign - 1);
   std::lock_guard<std::mutex> g(s->mu);
-  if (bytes > s->arena_bytes) {
-    ++s->rejected;
-    return RANMAR_ENOMEM;
-  }
-  if (!s->cfg.queue_when_full &&
-      (s->in_use + s->queued_bytes + bytes > s->arena_bytes ||
-       s->inflight + s->queue.size() >= s->cfg.max_inflight)) {
-    ++s->rejected;
-    return RANMAR_EAGAIN;
-  }
-  const uint64_t t = s->next_ticket++;
-  Req R{};
-  R.seed = seed;
-  R.fmt = fmt;
-  R.off = offset;
-  R.count = count;
-  R.bytes = bytes;
-  R.t_arr = t_arrival_ns ? t_arrival_ns : now_ns();
-  if (!s->t_first) s->t_first = now_ns();
-  ++s->submitted;
-  if (count == 0) {
-    R.st = ADMITTED;
-    ++s->inflight;
-    auto& ref = s->reqs[t] = R;
-    s->complete(t, ref, now_ns());
-    s->cv_done.notify_all();
-  } else {
-    s->reqs[t] = R;
-    s->queue.push_back(t);
-    s->queued_bytes += bytes;
-    s->cv_srv.notify_one();
-  }
-  *ticket = t;
-  return RANMAR_OK;
+  return s->submit_locked(seed, offset, count, fmt, t_arrival_ns, 0, ticket);
 }
 
 int ranmar_serve_poll(ranmar_server* s, uint64_t ticket, int* done) {
@@ -364,10 +388,7 @@ int ranmar_serve_release(ranmar_server* s, uint64_t ticket) {
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return RANMAR_ENOENT;
   if (it->second.st != DONE) return RANMAR_EAGAIN;
-  s->dealloc(it->second.aoff, it->second.count ? it->second.bytes : 0);
-  --s->inflight;
-  ++s->released;
-  s->reqs.erase(it);
+  s->release_locked(it);
   s->cv_srv.notify_one();
   return RANMAR_OK;
 }
@@ -419,47 +440,36 @@ int ranmar_serve_replay(ranmar_server* s, uint64_t n, const double* t_arrival_s,
                         const ranmar_u128* offsets, const uint64_t* counts, int fmt, double* latency_ns) {
   if (!s || (n && (!t_arrival_s || !seeds || !offsets || !counts))) return RANMAR_EINVAL;
   if (n == 0) return RANMAR_OK;
-  std::vector<uint64_t> tickets(n, 0);
-  std::vector<uint64_t> t_sched(n, 0);
-  std::atomic<uint64_t> submitted{0};
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->track_done) return RANMAR_EINVAL;  // one replay at a time
+    s->track_done = true;
+    s->done_q.clear();
+  }
+  std::atomic<uint64_t> n_rejected{0};
   std::atomic<int> first_err{0};
-  // Releaser: releases requests as they complete, in any order.
+  // Releaser: takes the tickets completed since its last pass (the server
+  // queues them) and releases them, in completion order.
   std::thread rel([&] {
-    std::deque<uint64_t> pend;
-    uint64_t seen = 0, done_count = 0;
-    while (done_count < n) {
-      const uint64_t sub = submitted.load(std::memory_order_acquire);
-      while (seen < sub) pend.push_back(seen++);
-      bool any = false;
-      {
-        std::unique_lock<std::mutex> lk(s->mu);
-        for (auto it = pend.begin(); it != pend.end();) {
-          const uint64_t r = *it;
-          if (tickets[r] == 0) {  // rejected submission
-            ++done_count;
-            it = pend.erase(it);
-            continue;
-          }
-          auto q = s->reqs.find(tickets[r]);
-          if (q != s->reqs.end() && q->second.st == DONE) {
-            if (latency_ns) latency_ns[r] = (double)(q->second.t_done - t_sched[r]);
-            s->dealloc(q->second.aoff, q->second.count ? q->second.bytes : 0);
-            --s->inflight;
-            ++s->released;
-            s->reqs.erase(q);
-            ++done_count;
-            any = true;
-            it = pend.erase(it);
-          } else {
-            ++it;
-          }
-        }
-        if (any) s->cv_srv.notify_one();
-        if (!any && done_count < n) {
-          if (s->err) break;
-          s->cv_done.wait_for(lk, std::chrono::microseconds(200));
-        }
+    std::vector<uint64_t> batch;
+    uint64_t finished = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (finished + n_rejected.load(std::memory_order_acquire) < n) {
+      if (s->done_q.empty()) {
+        if (s->err) break;
+        s->cv_done.wait_for(lk, std::chrono::microseconds(200));
+        continue;
       }
+      batch.swap(s->done_q);
+      for (const uint64_t t : batch) {
+        auto q = s->reqs.find(t);
+        if (q == s->reqs.end() || q->second.tag == 0) continue;  // not ours: left to its submitter
+        if (latency_ns) latency_ns[q->second.tag - 1] = (double)(q->second.t_done - q->second.t_arr);
+        s->release_locked(q);
+        ++finished;
+      }
+      batch.clear();
+      s->cv_srv.notify_one();
     }
   });
   const uint64_t t0 = now_ns();
@@ -469,18 +479,24 @@ int ranmar_serve_replay(ranmar_server* s, uint64_t n, const double* t_arrival_s,
       const uint64_t left = due - now_ns();
       if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
     }
-    t_sched[r] = due;
     uint64_t t = 0;
-    const int rc = ranmar_serve_submit(s, seeds[r], offsets[r], counts[r], fmt, due, &t);
+    int rc;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      rc = s->submit_locked(seeds[r], offsets[r], counts[r], fmt, due, r + 1, &t);
+    }
     if (rc != RANMAR_OK) {
       int z = 0;
       first_err.compare_exchange_strong(z, rc);
-      t = 0;
+      n_rejected.fetch_add(1, std::memory_order_release);
     }
-    tickets[r] = t;
-    submitted.store(r + 1, std::memory_order_release);
   }
   rel.join();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->track_done = false;
+    s->done_q.clear();
+  }
   if (s->err) return s->err;
   return first_err.load();
 }

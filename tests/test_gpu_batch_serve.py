@@ -295,3 +295,25 @@ def test_batch_prepare_then_launch(orc):
         _check(orc, items)
     finally:
         R.ranmar_batch_destroy(b)
+
+
+def test_batch_splits_requests_across_bins(orc):
+    """One long request among short and jump-only ones: the work is spread
+    over many bins, so the long request is cut into parts with their own
+    jumps; every draw and the final state must still be those of the single
+    stream.  Run twice on one batch (the second run with fewer requests, so
+    fewer bins and a smaller grid)."""
+    b = R.ranmar_batch_create(64, 1024)
+    try:
+        for rep, k in enumerate((24, 5)):
+            items = _mixed_requests(k, 40 + rep, max_count=50_000)
+            items[1]["count"] = 3_000_017          # 184 chunks of 16384: split over many bins
+            if k > 3:
+                items[3]["count"] = 0
+            _alloc(items)
+            say(f"bins rep {rep}: n={k} draws={sum(i['count'] for i in items)}")
+            R.ranmar_batch_run(b, R.make_requests(items))
+            torch.cuda.synchronize()
+            _check(orc, items)
+    finally:
+        R.ranmar_batch_destroy(b)
