@@ -15,8 +15,11 @@ bulk1m and jumps1m briefly and reports them under "also".
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
+import re
 import multiprocessing as mp
 import os
 import sys
@@ -31,7 +34,42 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 24-bit integer multiply-adds per second (lane-ops), 39.32 T
 
 MACS_SQUARE = 97 * 98 // 2     # symmetric schoolbook squaring: 4753 multiply-adds
-MACS_APPLY = 97 * 97           # Horner application: 9409 multiply-adds
+MACS_APPLY = 97 * 97           # one application of a polynomial to a window: 9409 multiply-adds
+WIN_BITS = 8                   # windowed jump: one table application per 8-bit digit of J
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest():
+    """Digest of the kernel sources (library and public header)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2512_00093_amd", "csrc", "*"))) + \
+        sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, grid):
+    """HBM bytes (fetched + written) per dispatch of `kernel` at `grid` threads
+    from the committed rocprofv3 counter summaries, or None when no summary was
+    taken from the current kernel sources."""
+    digest = source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
+        with open(path) as fh:
+            text = fh.read()
+        m = re.search(r"Source digest: `([0-9a-f]+)`", text)
+        if not m or m.group(1) != digest:
+            continue
+        for line in text.splitlines():
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) == 5 and kernel in cells[0] and cells[1] == str(grid):
+                return (float(cells[3]) + float(cells[4])) * 2 ** 20
+    return None
 
 
 def _parse():
@@ -41,7 +79,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="family65k", choices=["family65k", "bulk1m", "jumps1m", "serve"])
     ap.add_argument("--serve-requests", type=int, default=synth.SERVE["requests"])
-    ap.add_argument("--serve-qps", type=float, default=1e5)
+    ap.add_argument("--serve-qps", type=float, default=5e5)
+    ap.add_argument("--serve-light-qps", type=float, default=2e4)
     ap.add_argument("--serve-baseline-requests", type=int, default=2000)
     ap.add_argument("--jump", default="family", choices=["family", "lanes"],
                     help="family65k: stream starts by prefix doubling or one jump per stream")
@@ -184,7 +223,8 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
         "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},
         "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": gen_bytes / (gen_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gen_bytes / (gen_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gen_bytes / (gen_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("k_gen32<1, true>", n // 8 * 256),
                      "bytes_per_launch": gen_bytes, "launch_ms": gen_ms},
     }
     return res
@@ -222,7 +262,8 @@ def run_bulk1m(R, torch, steps, warmup):
         "output_write_frac": 4 * draws / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": algo / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": algo, "launch_ms": ms},
+                     "traffic": profiled_traffic("k_gen32<1, true>", n // 8 * 256),
+                     "bytes_per_launch": algo, "launch_ms": ms},
     }
 
 
@@ -247,18 +288,17 @@ def run_jumps1m(R, torch, steps, warmup):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ms = tm.mean_ms("jump")
-    # Algorithmic multiply-adds: one symmetric squaring per exponent bit below
-    # the top six (the window start is a monomial) + one Horner application.
+    # Algorithmic multiply-adds of the windowed jump: one 97 x 97 application
+    # per 8-bit digit of J (the digits up to the highest non-zero one).
     bl = np.where(hi > 0, 64 + np.floor(np.log2(np.maximum(hi, 1).astype(np.float64))) + 1,
-                  np.floor(np.log2(np.maximum(lo, 1).astype(np.float64))) + 1)
-    sq = np.maximum(bl - 6, 0).sum()
-    macs = sq * MACS_SQUARE + n * MACS_APPLY
+                  np.where(lo > 0, np.floor(np.log2(np.maximum(lo, 1).astype(np.float64))) + 1, 0))
+    macs = float(np.ceil(bl / WIN_BITS).sum()) * MACS_APPLY
     ach = macs / (ms * 1e-3) / 1e12
     return {
         "metric": "jumps/s", "value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3, "dtype": "u24",
         "config": {"workload": "jumps1m: 10^6 seed+jump requests, seeds uniform on [1, 9e8], J uniform on "
                                "[0, 2^120), one launch", "requests": n},
-        "roofline": {"bound": "alu", "kernel": "k_jump<seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
+        "roofline": {"bound": "alu", "kernel": "k_jump_coop<seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (24-bit multiply-adds)", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
                      "ops_per_launch": float(macs), "launch_ms": ms},
     }
@@ -365,6 +405,7 @@ def main():
         del src, dst
     if a.workload == "family65k":
         res = run_family65k(R, torch, a.steps, a.warmup, a.jump)
+        _progress("family65k done")
     elif a.workload == "bulk1m":
         res = run_bulk1m(R, torch, a.steps, a.warmup)
     elif a.workload == "serve":
@@ -387,11 +428,18 @@ def main():
         for name, fn in (("bulk1m", run_bulk1m), ("jumps1m", run_jumps1m)):
             r = fn(R, torch, 10, 2)
             also[name] = {k: r[k] for k in r if k not in ("metric",)}
+            _progress(f"{name} done")
         also["jumps1m_batched"] = run_jumps1m_batched(R, torch, 5, 1)
+        _progress("jumps1m_batched done")
         r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_baseline_requests)
         also["serve"] = {"config": r["config"], **r["serve"]}
+        _progress("serve done")
+        r = run_serve(R, torch, a.serve_requests, a.serve_light_qps, a.serve_baseline_requests)
+        also["serve_light"] = {"config": r["config"], **r["serve"]}
+        _progress("serve_light done")
         line["also"] = also
     if not a.no_cpu:
+        _progress("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -309,7 +309,7 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
   if (cfg) s->cfg = *cfg;
   if (!s->cfg.max_inflight) s->cfg.max_inflight = 65536;
   if (!s->cfg.chunk_draws) s->cfg.chunk_draws = 16384;
-  if (!s->cfg.max_tick_chunks) s->cfg.max_tick_chunks = 4096;
+  if (!s->cfg.max_tick_chunks) s->cfg.max_tick_chunks = 16384;
   if (!s->cfg.lanes) s->cfg.lanes = 2;
   if (s->cfg.lanes > 8 || s->cfg.chunk_draws > (1u << 24) || s->cfg.max_tick_chunks > (1u << 22)) {
     delete s;
