@@ -298,7 +298,7 @@ def run_jumps1m(R, torch, steps, warmup):
         "metric": "jumps/s", "value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3, "dtype": "u24",
         "config": {"workload": "jumps1m: 10^6 seed+jump requests, seeds uniform on [1, 9e8], J uniform on "
                                "[0, 2^120), one launch", "requests": n},
-        "roofline": {"bound": "alu", "kernel": "k_jump_coop<seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
+        "roofline": {"bound": "alu", "kernel": "k_jump_grp<8,seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (24-bit multiply-adds)", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
                      "ops_per_launch": float(macs), "launch_ms": ms},
     }

@@ -128,9 +128,7 @@ int ranmar_jump(ranmar_state* d_states, const ranmar_u128* d_J, uint64_t n, void
   if (overlap(d_states, sizeof(ranmar_state) * n, d_J, 16 * n)) return RANMAR_EINVAL;
   int rc = ensure_init();
   if (rc) return rc;
-  if (jump_variant_for(n) == JUMP_HALF_WINDOW)
-    return hip_status(launch_jump_coop((uint32_t*)d_states, nullptr, d_J, n, (hipStream_t)stream));
-  return hip_status(launch_jump((uint32_t*)d_states, nullptr, d_J, n, (hipStream_t)stream));
+  return hip_status(launch_jump_variant(jump_variant_for(n), (uint32_t*)d_states, nullptr, d_J, n, (hipStream_t)stream));
 }
 
 int ranmar_seed_jump(const int32_t* d_seeds, const ranmar_u128* d_offsets, uint64_t n, ranmar_state* d_out,
@@ -143,9 +141,8 @@ int ranmar_seed_jump(const int32_t* d_seeds, const ranmar_u128* d_offsets, uint6
     return RANMAR_EINVAL;
   int rc = ensure_init();
   if (rc) return rc;
-  if (jump_variant_for(n) == JUMP_HALF_WINDOW)
-    return hip_status(launch_jump_coop((uint32_t*)d_out, d_seeds, d_offsets, n, (hipStream_t)stream));
-  return hip_status(launch_jump((uint32_t*)d_out, d_seeds, d_offsets, n, (hipStream_t)stream));
+  return hip_status(
+      launch_jump_variant(jump_variant_for(n), (uint32_t*)d_out, d_seeds, d_offsets, n, (hipStream_t)stream));
 }
 
 int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n, ranmar_state* d_out,

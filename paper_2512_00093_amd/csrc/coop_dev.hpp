@@ -186,34 +186,145 @@ __device__ __forceinline__ void apply_half(uint32_t* X, const uint32_t* B, uint3
 
 // In place: X[0..96] <- f_1^J applied to X (the c part is left to the caller).
 // T: the window table, T + (w * 256 + d) * 97.  J given as 32-bit limbs.
-// `nwin`: number of low windows to apply (uniform over the wave).  The next
+// `nwin`: number of low windows to consider (uniform over the wave); windows
+// whose digit is zero in every lane of the wave are skipped.  The next
 // window's row is loaded while the current one is applied.
+__device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w);
+
 __device__ __forceinline__ const uint32_t* window_row(const uint32_t* __restrict__ T, uint32_t j0, uint32_t j1,
                                                       uint32_t j2, uint32_t j3, int w) {
+  return T + ((uint64_t)w * kWinDigits + window_digit(j0, j1, j2, j3, w)) * 97u;
+}
+
+__device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w) {
   const uint32_t limb = w < 4 ? j0 : w < 8 ? j1 : w < 12 ? j2 : j3;
-  const uint32_t d = (limb >> (8 * (w & 3))) & 0xFFu;
-  return T + ((uint64_t)w * kWinDigits + d) * 97u;
+  return (limb >> (8 * (w & 3))) & 0xFFu;
+}
+
+// First window >= w whose digit is nonzero in some lane of the wave (nwin if
+// none).  A zero digit's factor is T[w][0] = 1, so skipping it is exact.
+__device__ __forceinline__ int next_window(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w, int nwin) {
+  while (w < nwin && !__any(window_digit(j0, j1, j2, j3, w) != 0u)) ++w;
+  return w;
 }
 
 __device__ __forceinline__ void jump_half(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
                                           uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
-  if (nwin <= 0) return;
-  const uint32_t* row = window_row(T, j0, j1, j2, j3, 0);
+  int w = next_window(j0, j1, j2, j3, 0, nwin);
+  if (w >= nwin) return;
+  const uint32_t* row = window_row(T, j0, j1, j2, j3, w);
   uint32_t r0 = row[l], r1 = row[l + 32], r2 = row[l + 64], r3 = row[96];
-  for (int w = 0; w < nwin; ++w) {
+  while (w < nwin) {
     B[l] = r0;
     B[l + 32] = r1;
     B[l + 64] = r2;
     if (l == 0) B[96] = r3;
     wave_sync();
-    if (w + 1 < nwin) {
-      row = window_row(T, j0, j1, j2, j3, w + 1);
+    const int wn = next_window(j0, j1, j2, j3, w + 1, nwin);
+    if (wn < nwin) {
+      row = window_row(T, j0, j1, j2, j3, wn);
       r0 = row[l];
       r1 = row[l + 32];
       r2 = row[l + 64];
       r3 = row[96];
     }
     apply_half(X, B, l);
+    w = wn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Group form: one request per G lanes (G = 8, 16 or 32, a divisor of 96).
+// Lane l computes outputs K l .. K l + K of the Hankel product, K = 96 / G (the
+// extra one, o = 96, kept by lane G-1 only), so 97 of G (K + 1) accumulator
+// slots are useful: 97/104 for G = 8, 97/112 for G = 16, 97/128 for G = 32.
+// Each step of the sliding window is K + 1 multiply-adds per 2 LDS reads.
+// ---------------------------------------------------------------------------
+
+// Seeding by G lanes: lane l computes words l, l+G, ..., and lane 0 word 96.
+template <int G>
+__device__ __forceinline__ bool seed_group(int32_t seed, uint32_t* X, uint32_t l) {
+  if (seed < 1 || seed > 900000000) return false;
+  const uint32_t s1 = (uint32_t)seed - 1u;
+  const uint32_t ij = s1 / 30082u;
+  const uint32_t kl = s1 - 30082u * ij;
+  const uint32_t a0 = kSeedTab.log2[(ij / 177u) % 177u + 2u];
+  const uint32_t b0 = kSeedTab.log2[ij % 177u + 2u];
+  const uint32_t c0 = kSeedTab.log2[(kl / 169u) % 178u + 1u];
+  const uint32_t l0 = kl % 169u;
+#pragma unroll
+  for (uint32_t k = 0; k < 96; k += G) X[96 - (l + k)] = seed_word_at(l + k, a0, b0, c0, l0);
+  if (l == 0) {
+    X[0] = seed_word_at(96, a0, b0, c0, l0);
+    X[97] = kC0;
+  }
+  return true;
+}
+
+// X[0..96] <- X P(A) for the polynomial in B[0..96]; X has room for 193 words.
+template <int G>
+__device__ __forceinline__ void apply_group(uint32_t* X, const uint32_t* B, uint32_t l) {
+  constexpr int K = 96 / G;
+  // X_(97+i) = X_i - X_(i+64): terms within a block of 33 are independent
+  // (each reads words at least 33 back), so only the blocks are ordered.
+#pragma unroll
+  for (uint32_t b0 = 0; b0 < 96; b0 += 33) {
+    const uint32_t b1 = b0 + 33 < 96 ? b0 + 33 : 96;
+#pragma unroll
+    for (uint32_t i = b0 + l; i < b1; i += G) X[97 + i] = X[i] - X[i + 64];
+    wave_sync();
+  }
+  const uint32_t* Xl = X + (uint32_t)K * l;
+  uint32_t w[K], a[K + 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) w[k] = Xl[k];
+#pragma unroll
+  for (int k = 0; k <= K; ++k) a[k] = 0;
+#pragma unroll K
+  for (int i = 0; i < 97; ++i) {
+    const uint32_t wn = Xl[i + K];
+    const uint32_t b = B[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = mad24(b, w[k], a[k]);
+    a[K] = mad24(b, wn, a[K]);
+#pragma unroll
+    for (int k = 0; k + 1 < K; ++k) w[k] = w[k + 1];
+    w[K - 1] = wn;
+  }
+  wave_sync();
+  uint32_t* Xo = X + (uint32_t)K * l;
+#pragma unroll
+  for (int k = 0; k < K; ++k) Xo[k] = a[k] & kMask;
+  if (l == G - 1) X[96] = a[K] & kMask;
+  wave_sync();
+}
+
+// jump_half for G lanes.
+template <int G>
+__device__ __forceinline__ void jump_group(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
+                                           uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
+  constexpr int K = 96 / G;
+  int w = next_window(j0, j1, j2, j3, 0, nwin);
+  if (w >= nwin) return;
+  const uint32_t* row = window_row(T, j0, j1, j2, j3, w);
+  uint32_t r[K + 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] = row[l + G * k];
+  r[K] = row[96];
+  while (w < nwin) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) B[l + G * k] = r[k];
+    if (l == 0) B[96] = r[K];
+    wave_sync();
+    const int wn = next_window(j0, j1, j2, j3, w + 1, nwin);
+    if (wn < nwin) {
+      row = window_row(T, j0, j1, j2, j3, wn);
+#pragma unroll
+      for (int k = 0; k < K; ++k) r[k] = row[l + G * k];
+      r[K] = row[96];
+    }
+    apply_group<G>(X, B, l);
+    w = wn;
   }
 }
 

@@ -26,11 +26,16 @@ hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hip
 hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
 
 enum JumpVariant : int {
-  JUMP_LANE_SQMUL = 0,   // one request per lane, square-and-multiply in VGPRs
-  JUMP_HALF_WINDOW = 1,  // one request per half-wave, 8-bit windows in LDS
-  JUMP_NUM_VARIANTS = 2
+  JUMP_LANE_SQMUL = 0,      // one request per lane, square-and-multiply in VGPRs
+  JUMP_HALF_WINDOW = 1,     // one request per half-wave, 8-bit windows in LDS
+  JUMP_QUARTER_WINDOW = 2,  // one request per 16 lanes, 8-bit windows in LDS
+  JUMP_EIGHTH_WINDOW = 3,   // one request per 8 lanes, 8-bit windows in LDS
+  JUMP_NUM_VARIANTS = 4
 };
 int jump_variant_for(uint64_t n);
+// Seed (seeds != nullptr) and jump with the given variant.
+hipError_t launch_jump_variant(int v, uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
+                               hipStream_t st);
 
 // Generation variants (all bit-identical).
 enum GenVariant : int {

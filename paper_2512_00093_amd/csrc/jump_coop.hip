@@ -65,6 +65,68 @@ __global__ __launch_bounds__(256) void k_jump_coop(uint32_t* __restrict__ states
   }
 }
 
+// The same with G lanes per request (G = 8 or 16), 256 / G requests per
+// workgroup.  The per-request LDS stride is 1 mod 4, so the requests that
+// share one 32-lane LDS pass fall on disjoint bank residues (a group's lanes
+// are K = 96 / G words apart, K a multiple of 2 or 4).
+constexpr int kGroupStride = 193 + 97 + 3;
+
+template <int G, bool SEED>
+__global__ __launch_bounds__(256) void k_jump_grp(uint32_t* __restrict__ states, const int32_t* __restrict__ seeds,
+                                                  const ranmar_u128* __restrict__ J, uint64_t n,
+                                                  const uint32_t* __restrict__ T) {
+  constexpr uint32_t kPerWg = 256 / G;
+  __shared__ uint32_t lds[kPerWg * kGroupStride];
+  const uint32_t q = threadIdx.x / G, l = threadIdx.x % G;
+  const uint64_t r = (uint64_t)blockIdx.x * kPerWg + q;
+  const bool active = r < n;
+  uint32_t* X = lds + q * kGroupStride;
+  uint32_t* B = X + 193;
+  uint32_t* slot = states + (active ? r : 0) * kWords;
+  bool valid = active;
+  uint32_t c = 0;
+  if (SEED) {
+    if (active) valid = seed_group<G>(seeds[r], X, l);
+    wave_sync();
+    c = X[97];
+  } else if (active) {
+#pragma unroll
+    for (int k = 0; k < 96; k += G) X[l + k] = slot[l + k];
+    if (l == 0) X[96] = slot[96];
+    c = slot[97];
+  }
+  uint32_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
+  if (valid && J) {
+    const uint64_t lo = J[r].lo, hi = J[r].hi;
+    j0 = (uint32_t)lo;
+    j1 = (uint32_t)(lo >> 32);
+    j2 = (uint32_t)hi;
+    j3 = (uint32_t)(hi >> 32);
+  }
+  if (!valid) {  // keep the idle group's arithmetic defined
+#pragma unroll
+    for (int k = 0; k < 96; k += G) X[l + k] = 0;
+    if (l == 0) X[96] = 0;
+  }
+  wave_sync();
+  jump_group<G>(X, B, T, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 96; k += G) slot[l + k] = X[l + k];
+    if (l == 0) {
+      slot[96] = X[96];
+      slot[97] = c_jump(c, u128_mod_m(j0, j1, j2, j3));
+    }
+  } else if (SEED && active) {
+#pragma unroll
+    for (int k = 0; k < 96; k += G) slot[l + k] = 0;
+    if (l == 0) {
+      slot[96] = 0;
+      slot[97] = kInvalidC;
+    }
+  }
+}
+
 // Seeding only, 32 lanes per seed (for few seeds: a lane-per-seed launch would
 // run Algorithm 3's 2328 dependent steps on one lane).
 __global__ __launch_bounds__(256) void k_seed_coop(const int32_t* __restrict__ seeds, uint64_t n,
@@ -86,46 +148,43 @@ __global__ __launch_bounds__(256) void k_seed_coop(const int32_t* __restrict__ s
   }
 }
 
-// One doubling round of a stream family: for k < cnt,
-// out[dst0 + k] = out[k] jumped by the exponent whose nonzero 8-bit digits
-// are given (window w_i, digit d_i): one table factor per digit.
-struct FamilyDigits {
-  uint32_t n;
-  uint32_t jmod;           // exponent mod m
-  uint16_t w[16], d[16];
-};
-
-__global__ __launch_bounds__(256) void k_family_round_coop(uint32_t* __restrict__ out,
-                                                           const uint32_t* __restrict__ T, uint64_t cnt,
-                                                           uint64_t dst0, FamilyDigits dg) {
+// One radix-256 round of a stream family: with the first M starts in place,
+// start s in [M, min(n, 256 M)) is start s mod M jumped by (s div M) M delta.
+// MD = M delta (< 2^128), MDmod = MD mod m.  The factors are the table rows
+// of the exponent's nonzero 8-bit digits; for delta = 2^40 and M = 256^i the
+// exponent has one digit, so every start costs one application.
+__global__ __launch_bounds__(256) void k_family_radix(uint32_t* __restrict__ out, const uint32_t* __restrict__ T,
+                                                      uint64_t M, uint64_t cnt, uint64_t md_lo, uint64_t md_hi,
+                                                      uint32_t md_mod) {
   __shared__ uint32_t lds[8 * kHalfWords];
   const uint32_t hw = threadIdx.x >> 5, l = threadIdx.x & 31u;
-  const uint64_t k = (uint64_t)blockIdx.x * 8u + hw;
-  if (k >= cnt) return;  // a whole half-wave leaves together
+  const uint64_t g = (uint64_t)blockIdx.x * 8u + hw;
+  const bool active = g < cnt;
+  const uint64_t s = M + (active ? g : 0);
+  const uint64_t jdig = s / M, src_i = s - jdig * M;
   uint32_t* X = lds + hw * kHalfWords;
   uint32_t* B = X + 193;
-  const uint32_t* src = out + k * kWords;
+  const uint32_t* src = out + src_i * kWords;
   X[l] = src[l];
   X[l + 32] = src[l + 32];
   X[l + 64] = src[l + 64];
   if (l == 0) X[96] = src[96];
   const uint32_t c = src[97];
-  for (uint32_t i = 0; i < dg.n; ++i) {
-    const uint32_t* row = T + ((uint64_t)dg.w[i] * kWinDigits + dg.d[i]) * 97u;
-    B[l] = row[l];
-    B[l + 32] = row[l + 32];
-    B[l + 64] = row[l + 64];
-    if (l == 0) B[96] = row[96];
-    wave_sync();
-    apply_half(X, B, l);
-  }
-  uint32_t* dst = out + (dst0 + k) * kWords;
-  dst[l] = X[l];
-  dst[l + 32] = X[l + 32];
-  dst[l + 64] = X[l + 64];
-  if (l == 0) {
-    dst[96] = X[96];
-    dst[97] = c_jump(c, dg.jmod);
+  // E = jdig * MD, exact: jdig < 256 and E <= (n - 1) delta < 2^128.
+  const unsigned __int128 E = (unsigned __int128)jdig * (((unsigned __int128)md_hi << 64) | md_lo);
+  const uint64_t elo = active ? (uint64_t)E : 0, ehi = active ? (uint64_t)(E >> 64) : 0;
+  const uint32_t j0 = (uint32_t)elo, j1 = (uint32_t)(elo >> 32), j2 = (uint32_t)ehi, j3 = (uint32_t)(ehi >> 32);
+  wave_sync();
+  jump_half(X, B, T, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
+  if (active) {
+    uint32_t* dst = out + s * kWords;
+    dst[l] = X[l];
+    dst[l + 32] = X[l + 32];
+    dst[l + 64] = X[l + 64];
+    if (l == 0) {
+      dst[96] = X[96];
+      dst[97] = c_jump(c, (uint32_t)(jdig * md_mod % kMod));
+    }
   }
 }
 
@@ -135,40 +194,28 @@ hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hip
   return hipGetLastError();
 }
 
-// Family by doubling rounds that each apply the table factors of 2^b delta.
-// Returns hipErrorInvalidValue (nothing launched) when some 2^b delta needs
-// more than 128 bits; the caller then uses the polynomial path.
+// Family by radix-256 rounds (each one launch).  Returns hipErrorInvalidValue
+// (nothing launched) when (n - 1) delta does not fit in 128 bits; the caller
+// then uses the polynomial path.
 hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st) {
-  int nb = 0;
-  while (nb < 64 && (1ull << nb) < n) ++nb;
   const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
-  int dbits = 0;
-  for (unsigned __int128 t = D; t; t >>= 1) ++dbits;
-  if (nb > 0 && dbits + nb - 1 > 128) return hipErrorInvalidValue;
+  const unsigned __int128 kMax = ~(unsigned __int128)0;
+  if (n > 1 && D > kMax / (n - 1)) return hipErrorInvalidValue;
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
   if (base != out) {
     hipError_t e = hipMemcpyAsync(out, base, 4 * kWords, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
   }
-  const uint64_t dmod = (uint64_t)(D % kMod);
-  uint64_t pow2 = 1;
-  for (int b = 0; b < nb; ++b) {
-    const unsigned __int128 E = D << b;  // < 2^128 by the check above
-    FamilyDigits dg{};
-    for (int w = 0; w < kWindows; ++w) {
-      const uint32_t d = (uint32_t)(E >> (kWinBits * w)) & 0xFFu;
-      if (d) {
-        dg.w[dg.n] = (uint16_t)w;
-        dg.d[dg.n] = (uint16_t)d;
-        ++dg.n;
-      }
-    }
-    dg.jmod = (uint32_t)((dmod * pow2) % kMod);
-    pow2 = pow2 * 2 % kMod;
-    const uint64_t half = 1ull << b;
-    const uint64_t cnt = (n - half < half) ? n - half : half;
-    hipLaunchKernelGGL(k_family_round_coop, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out, T, cnt, half, dg);
+  for (uint64_t M = 1; M < n;) {
+    const uint64_t top = (M <= n / 256) ? 256 * M : n;  // starts [M, top) this round
+    const uint64_t cnt = top - M;
+    if ((cnt + 7) / 8 > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    const unsigned __int128 MD = D * M;  // <= (n - 1) delta
+    const uint32_t md_mod = (uint32_t)(MD % kMod);
+    hipLaunchKernelGGL(k_family_radix, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out, T, M, cnt,
+                       (uint64_t)MD, (uint64_t)(MD >> 64), md_mod);
+    M = top;
   }
   return hipGetLastError();
 }
@@ -220,6 +267,30 @@ hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar
   else
     hipLaunchKernelGGL(k_jump_coop<false>, grid, dim3(256), 0, st, states, seeds, J, n, T);
   return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_jump_grp(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
+                                  hipStream_t st) {
+  constexpr uint64_t kPerWg = 256 / G;
+  if (!n) return hipSuccess;
+  if ((n + kPerWg - 1) / kPerWg > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const uint32_t* T = window_table();
+  if (!T) return hipErrorOutOfMemory;
+  const dim3 grid((unsigned)((n + kPerWg - 1) / kPerWg));
+  if (seeds)
+    hipLaunchKernelGGL((k_jump_grp<G, true>), grid, dim3(256), 0, st, states, seeds, J, n, T);
+  else
+    hipLaunchKernelGGL((k_jump_grp<G, false>), grid, dim3(256), 0, st, states, seeds, J, n, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_variant(int v, uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
+                               hipStream_t st) {
+  if (v == JUMP_QUARTER_WINDOW) return launch_jump_grp<16>(states, seeds, J, n, st);
+  if (v == JUMP_EIGHTH_WINDOW) return launch_jump_grp<8>(states, seeds, J, n, st);
+  if (v == JUMP_HALF_WINDOW) return launch_jump_coop(states, seeds, J, n, st);
+  return launch_jump(states, seeds, J, n, st);
 }
 
 }  // namespace ranmar

@@ -20,8 +20,8 @@ namespace ranmar {
 // below 178^3 < 2^23): q = floor(2x * 11997116 / 2^32) = floor(x / 179)
 // on that range (11997116 = ceil(2^31 / 179)).
 __device__ __forceinline__ uint32_t mod179(uint32_t x) {
-  uint32_t q = mulhi24(x << 1, 11997116u);
-  return x - 179u * q;
+  const uint32_t q = mulhi24(x << 1, 11997116u);
+  return x - mul24(q, 179u);  // q < 2^16: the full-rate 24-bit multiply is exact
 }
 
 // y mod 169 for y < 15196: q = floor(y * 6205 / 2^20), 6205 = ceil(2^20/169).

@@ -39,7 +39,9 @@ int jump_variant_for(uint64_t n) {
   if (g_forced[RANMAR_K_JUMP] >= 0) return g_forced[RANMAR_K_JUMP];
   auto it = g_table.find({RANMAR_K_JUMP, ilog2(n), 0});
   if (it != g_table.end()) return it->second;
-  return JUMP_HALF_WINDOW;
+  // Many requests: 8 lanes each (most useful multiply-adds per issue); few:
+  // 32 lanes each (a third of the latency per request, more workgroups).
+  return n >= 16384 ? JUMP_EIGHTH_WINDOW : JUMP_HALF_WINDOW;
 }
 
 int gen_variant_for(uint64_t n, uint64_t count) {
@@ -83,10 +85,7 @@ static int tune_jump(uint64_t n, int bits, double* ms_out, hipStream_t st) {
     goto done;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
   for (int v = 0; v < JUMP_NUM_VARIANTS; ++v) {
-    auto run = [&] {
-      return v == JUMP_HALF_WINDOW ? launch_jump_coop(d_states, d_seeds, d_J, n, st)
-                                   : launch_jump(d_states, d_seeds, d_J, n, st);
-    };
+    auto run = [&] { return launch_jump_variant(v, d_states, d_seeds, d_J, n, st); };
     if (run() != hipSuccess) goto done;
     hipEventRecord(e0, st);
     const int reps = 3;
@@ -134,6 +133,8 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_GENERATE && variant >= 0 && variant < GEN_NUM_VARIANTS) return gen_variant_name(variant);
   if (kernel == RANMAR_K_JUMP && variant == JUMP_LANE_SQMUL) return "lane_square_multiply";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_HALF_WINDOW) return "halfwave_window8";
+  if (kernel == RANMAR_K_JUMP && variant == JUMP_QUARTER_WINDOW) return "lanes16_window8";
+  if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW) return "lanes8_window8";
   return nullptr;
 }
 

@@ -211,11 +211,14 @@ def test_generate_variants_bit_identical(orc):
 
 
 # --- stream families -----------------------------------------------------------
-@pytest.mark.parametrize("n", [1, 2, 3, 64, 100, 5000])
-def test_family_equals_independent_jumps(orc, n):
-    delta = (1 << 40) + 12345
+@pytest.mark.parametrize("n,delta", [(1, (1 << 40) + 12345), (2, (1 << 40) + 12345), (3, (1 << 40) + 12345),
+                                     (64, (1 << 40) + 12345), (100, (1 << 40) + 12345),
+                                     (5000, (1 << 40) + 12345), (70_000, 1 << 40), (200, (1 << 120) + 3)])
+def test_family_equals_independent_jumps(orc, n, delta):
+    """Families are built in radix-256 rounds (1, 2 and 3 rounds here; the
+    last case has 16-digit exponents up to 199 (2^120 + 3) < 2^128)."""
     base = orc.state_from_seed(4711)
-    say(f"jump_family n={n}")
+    say(f"jump_family n={n} delta={delta}")
     fam = R.ranmar_jump_family(states_t(base), delta, n)
     ind = R.ranmar_seed_jump(seeds_t([4711] * n), jumps_t([k * delta for k in range(n)]))
     assert torch.equal(fam, ind)
@@ -307,8 +310,8 @@ def test_repeatable(orc):
     assert torch.equal(R.ranmar_generate(a, 333, 1), R.ranmar_generate(b, 333, 1))
 
 
-# --- jump variants: per-lane square-and-multiply vs half-wave windowed ---------
-@pytest.fixture(params=[0, 1], ids=["lane_sqmul", "half_window"])
+# --- jump variants: per-lane square-and-multiply, half- and quarter-wave windowed ---
+@pytest.fixture(params=[0, 1, 2, 3], ids=["lane_sqmul", "half_window", "lanes16_window", "lanes8_window"])
 def jump_variant(request):
     R.ranmar_tune_set(R.RANMAR_K_JUMP, request.param)
     yield request.param
@@ -352,14 +355,17 @@ def test_jump_variants_agree_at_scale(jump_variant):
     s, lo, hi = synth.batch_jumps(n, 120, offset=19)
     say(f"jump variants at n={n}")
     a = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
-    R.ranmar_tune_set(R.RANMAR_K_JUMP, 1 - jump_variant)
-    b = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
-    assert torch.equal(a, b)
+    for other in range(R.ranmar_tune_variants(R.RANMAR_K_JUMP)):
+        if other == jump_variant:
+            continue
+        R.ranmar_tune_set(R.RANMAR_K_JUMP, other)
+        b = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
+        assert torch.equal(a, b), other
 
 
 def test_tune_run_jump_and_generate():
     best, ms = R.ranmar_tune_run(R.RANMAR_K_JUMP, 4096, 120)
-    assert best in (0, 1) and all(m > 0 for m in ms)
+    assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_JUMP) and all(m > 0 for m in ms)
     best, ms = R.ranmar_tune_run(R.RANMAR_K_GENERATE, 4096, 4096)
     assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_GENERATE) and all(m > 0 for m in ms)
 
