@@ -189,22 +189,26 @@ __device__ __forceinline__ void apply_half(uint32_t* X, const uint32_t* B, uint3
 // `nwin`: number of low windows to consider (uniform over the wave); windows
 // whose digit is zero in every lane of the wave are skipped.  The next
 // window's row is loaded while the current one is applied.
-__device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w);
-
-__device__ __forceinline__ const uint32_t* window_row(const uint32_t* __restrict__ T, uint32_t j0, uint32_t j1,
-                                                      uint32_t j2, uint32_t j3, int w) {
-  return T + ((uint64_t)w * kWinDigits + window_digit(j0, j1, j2, j3, w)) * 97u;
+// Digit w of J in base 2^WB (WB = 8 or 16, J as four 32-bit limbs).
+template <int WB = kWinBits>
+__device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w) {
+  const int bit = w * WB;
+  const uint32_t limb = bit < 32 ? j0 : bit < 64 ? j1 : bit < 96 ? j2 : j3;
+  return (limb >> (bit & 31)) & ((1u << WB) - 1u);
 }
 
-__device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w) {
-  const uint32_t limb = w < 4 ? j0 : w < 8 ? j1 : w < 12 ? j2 : j3;
-  return (limb >> (8 * (w & 3))) & 0xFFu;
+// Row of the factor t^(d 2^(WB w)) in a table of 2^WB rows per window.
+template <int WB = kWinBits>
+__device__ __forceinline__ const uint32_t* window_row(const uint32_t* __restrict__ T, uint32_t j0, uint32_t j1,
+                                                      uint32_t j2, uint32_t j3, int w) {
+  return T + (((uint64_t)w << WB) + window_digit<WB>(j0, j1, j2, j3, w)) * 97u;
 }
 
 // First window >= w whose digit is nonzero in some lane of the wave (nwin if
 // none).  A zero digit's factor is T[w][0] = 1, so skipping it is exact.
+template <int WB = kWinBits>
 __device__ __forceinline__ int next_window(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w, int nwin) {
-  while (w < nwin && !__any(window_digit(j0, j1, j2, j3, w) != 0u)) ++w;
+  while (w < nwin && !__any(window_digit<WB>(j0, j1, j2, j3, w) != 0u)) ++w;
   return w;
 }
 
@@ -299,14 +303,14 @@ __device__ __forceinline__ void apply_group(uint32_t* X, const uint32_t* B, uint
   wave_sync();
 }
 
-// jump_half for G lanes.
-template <int G>
+// jump_half for G lanes, with a table of WB-bit windows.
+template <int G, int WB>
 __device__ __forceinline__ void jump_group(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
                                            uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
   constexpr int K = 96 / G;
-  int w = next_window(j0, j1, j2, j3, 0, nwin);
+  int w = next_window<WB>(j0, j1, j2, j3, 0, nwin);
   if (w >= nwin) return;
-  const uint32_t* row = window_row(T, j0, j1, j2, j3, w);
+  const uint32_t* row = window_row<WB>(T, j0, j1, j2, j3, w);
   uint32_t r[K + 1];
 #pragma unroll
   for (int k = 0; k < K; ++k) r[k] = row[l + G * k];
@@ -316,9 +320,9 @@ __device__ __forceinline__ void jump_group(uint32_t* X, uint32_t* B, const uint3
     for (int k = 0; k < K; ++k) B[l + G * k] = r[k];
     if (l == 0) B[96] = r[K];
     wave_sync();
-    const int wn = next_window(j0, j1, j2, j3, w + 1, nwin);
+    const int wn = next_window<WB>(j0, j1, j2, j3, w + 1, nwin);
     if (wn < nwin) {
-      row = window_row(T, j0, j1, j2, j3, wn);
+      row = window_row<WB>(T, j0, j1, j2, j3, wn);
 #pragma unroll
       for (int k = 0; k < K; ++k) r[k] = row[l + G * k];
       r[K] = row[96];
@@ -328,7 +332,8 @@ __device__ __forceinline__ void jump_group(uint32_t* X, uint32_t* B, const uint3
   }
 }
 
-// Number of 8-bit windows holding the wave's longest exponent.
+// Number of WB-bit windows holding the wave's longest exponent.
+template <int WB = kWinBits>
 __device__ __forceinline__ int wave_windows(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3) {
   int bl = 0;
   if (j3)
@@ -339,7 +344,7 @@ __device__ __forceinline__ int wave_windows(uint32_t j0, uint32_t j1, uint32_t j
     bl = 64 - __clz(j1);
   else if (j0)
     bl = 32 - __clz(j0);
-  return (wave_max_i32(bl) + kWinBits - 1) / kWinBits;
+  return (wave_max_i32(bl) + WB - 1) / WB;
 }
 
 }  // namespace ranmar

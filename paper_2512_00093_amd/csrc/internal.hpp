@@ -20,7 +20,8 @@ hipError_t launch_jump(uint32_t* states, const int32_t* seeds, const ranmar_u128
 // Half-wave cooperative variant (windowed jump, parallel seeding).
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                             hipStream_t st);
-const uint32_t* window_table();   // T[w][d] = t^(d 2^(8w)) mod phi, per device
+const uint32_t* window_table();    // T[w][d] = t^(d 2^(8w)) mod phi, per device
+const uint32_t* window16_table();  // T[w][d] = t^(d 2^(16w)) mod phi, per device (nullptr if it cannot be built)
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
 // Family by table factors; hipErrorInvalidValue if an exponent needs > 128 bits.
 hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
@@ -30,7 +31,8 @@ enum JumpVariant : int {
   JUMP_HALF_WINDOW = 1,     // one request per half-wave, 8-bit windows in LDS
   JUMP_QUARTER_WINDOW = 2,  // one request per 16 lanes, 8-bit windows in LDS
   JUMP_EIGHTH_WINDOW = 3,   // one request per 8 lanes, 8-bit windows in LDS
-  JUMP_NUM_VARIANTS = 4
+  JUMP_EIGHTH_WINDOW16 = 4, // one request per 8 lanes, 16-bit windows (203 MB table)
+  JUMP_NUM_VARIANTS = 5
 };
 int jump_variant_for(uint64_t n);
 // Seed (seeds != nullptr) and jump with the given variant.

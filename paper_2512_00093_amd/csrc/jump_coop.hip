@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_jump_coop(uint32_t* __restrict__ states
 // are K = 96 / G words apart, K a multiple of 2 or 4).
 constexpr int kGroupStride = 193 + 97 + 3;
 
-template <int G, bool SEED>
+template <int G, int WB, bool SEED>
 __global__ __launch_bounds__(256) void k_jump_grp(uint32_t* __restrict__ states, const int32_t* __restrict__ seeds,
                                                   const ranmar_u128* __restrict__ J, uint64_t n,
                                                   const uint32_t* __restrict__ T) {
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_jump_grp(uint32_t* __restrict__ states,
     if (l == 0) X[96] = 0;
   }
   wave_sync();
-  jump_group<G>(X, B, T, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
+  jump_group<G, WB>(X, B, T, j0, j1, j2, j3, wave_windows<WB>(j0, j1, j2, j3), l);
   if (valid) {
 #pragma unroll
     for (int k = 0; k < 96; k += G) slot[l + k] = X[l + k];
@@ -221,23 +221,21 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// Window table, one per device, built by the square-and-multiply kernel.
+// Window tables, one per device and width, built by the square-and-multiply
+// kernel: T[w][d] = t^(d 2^(WB w)) mod phi.  WB = 8: 16 x 256 rows (1.6 MB,
+// L2-resident).  WB = 16: 8 x 65536 rows (203 MB), for bulk jumps, where it
+// halves the number of applications.
 // ---------------------------------------------------------------------------
-const uint32_t* window_table() {
-  static std::mutex mu;
-  static std::map<int, uint32_t*> tabs;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> g(mu);
-  auto it = tabs.find(dev);
-  if (it != tabs.end()) return it->second;
-  const uint64_t n = (uint64_t)kWindows * kWinDigits;
+static const uint32_t* build_window_table(int wb) {
+  const int windows = 128 / wb;
+  const uint64_t digits = 1ull << wb;
+  const uint64_t n = (uint64_t)windows * digits;
   std::vector<ranmar_u128> Jh(n);
-  for (int w = 0; w < kWindows; ++w)
-    for (int d = 0; d < kWinDigits; ++d) {
-      const unsigned __int128 v = (unsigned __int128)d << (kWinBits * w);
-      Jh[w * kWinDigits + d].lo = (uint64_t)v;
-      Jh[w * kWinDigits + d].hi = (uint64_t)(v >> 64);
+  for (int w = 0; w < windows; ++w)
+    for (uint64_t d = 0; d < digits; ++d) {
+      const unsigned __int128 v = (unsigned __int128)d << (wb * w);
+      Jh[w * digits + d].lo = (uint64_t)v;
+      Jh[w * digits + d].hi = (uint64_t)(v >> 64);
     }
   uint32_t* T = nullptr;
   ranmar_u128* dJ = nullptr;
@@ -250,11 +248,27 @@ const uint32_t* window_table() {
   hipFree(dJ);
   if (!ok) {
     hipFree(T);
+    (void)hipGetLastError();  // a failed allocation is reported by the nullptr, not left for the next call
     return nullptr;
   }
-  tabs[dev] = T;
   return T;
 }
+
+static const uint32_t* cached_window_table(int wb) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, const uint32_t*> tabs;  // (device, width) -> table; failures cached too
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = tabs.find({dev, wb});
+  if (it != tabs.end()) return it->second;
+  const uint32_t* T = build_window_table(wb);
+  tabs[{dev, wb}] = T;
+  return T;
+}
+
+const uint32_t* window_table() { return cached_window_table(8); }
+const uint32_t* window16_table() { return cached_window_table(16); }
 
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                             hipStream_t st) {
@@ -269,26 +283,31 @@ hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar
   return hipGetLastError();
 }
 
-template <int G>
+template <int G, int WB>
 static hipError_t launch_jump_grp(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                                   hipStream_t st) {
   constexpr uint64_t kPerWg = 256 / G;
   if (!n) return hipSuccess;
   if ((n + kPerWg - 1) / kPerWg > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  const uint32_t* T = window_table();
+  const uint32_t* T = WB == 16 ? window16_table() : window_table();
   if (!T) return hipErrorOutOfMemory;
   const dim3 grid((unsigned)((n + kPerWg - 1) / kPerWg));
   if (seeds)
-    hipLaunchKernelGGL((k_jump_grp<G, true>), grid, dim3(256), 0, st, states, seeds, J, n, T);
+    hipLaunchKernelGGL((k_jump_grp<G, WB, true>), grid, dim3(256), 0, st, states, seeds, J, n, T);
   else
-    hipLaunchKernelGGL((k_jump_grp<G, false>), grid, dim3(256), 0, st, states, seeds, J, n, T);
+    hipLaunchKernelGGL((k_jump_grp<G, WB, false>), grid, dim3(256), 0, st, states, seeds, J, n, T);
   return hipGetLastError();
 }
 
 hipError_t launch_jump_variant(int v, uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                                hipStream_t st) {
-  if (v == JUMP_QUARTER_WINDOW) return launch_jump_grp<16>(states, seeds, J, n, st);
-  if (v == JUMP_EIGHTH_WINDOW) return launch_jump_grp<8>(states, seeds, J, n, st);
+  if (v == JUMP_QUARTER_WINDOW) return launch_jump_grp<16, 8>(states, seeds, J, n, st);
+  if (v == JUMP_EIGHTH_WINDOW) return launch_jump_grp<8, 8>(states, seeds, J, n, st);
+  if (v == JUMP_EIGHTH_WINDOW16) {
+    // The 16-bit table is large; without it the 8-bit windows do the same job.
+    if (window16_table()) return launch_jump_grp<8, 16>(states, seeds, J, n, st);
+    return launch_jump_grp<8, 8>(states, seeds, J, n, st);
+  }
   if (v == JUMP_HALF_WINDOW) return launch_jump_coop(states, seeds, J, n, st);
   return launch_jump(states, seeds, J, n, st);
 }

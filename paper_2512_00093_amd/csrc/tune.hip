@@ -39,9 +39,11 @@ int jump_variant_for(uint64_t n) {
   if (g_forced[RANMAR_K_JUMP] >= 0) return g_forced[RANMAR_K_JUMP];
   auto it = g_table.find({RANMAR_K_JUMP, ilog2(n), 0});
   if (it != g_table.end()) return it->second;
-  // Many requests: 8 lanes each (most useful multiply-adds per issue); few:
-  // 32 lanes each (a third of the latency per request, more workgroups).
-  return n >= 16384 ? JUMP_EIGHTH_WINDOW : JUMP_HALF_WINDOW;
+  // Many requests: 8 lanes each (most useful multiply-adds per issue) and
+  // 16-bit windows (half the applications, 203 MB table); few: 32 lanes each
+  // (a third of the latency per request, more workgroups) and the 1.6 MB
+  // table.
+  return n >= 16384 ? JUMP_EIGHTH_WINDOW16 : JUMP_HALF_WINDOW;
 }
 
 int gen_variant_for(uint64_t n, uint64_t count) {
@@ -135,6 +137,7 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_JUMP && variant == JUMP_HALF_WINDOW) return "halfwave_window8";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_QUARTER_WINDOW) return "lanes16_window8";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW) return "lanes8_window8";
+  if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW16) return "lanes8_window16";
   return nullptr;
 }
 

@@ -311,7 +311,8 @@ def test_repeatable(orc):
 
 
 # --- jump variants: per-lane square-and-multiply, half- and quarter-wave windowed ---
-@pytest.fixture(params=[0, 1, 2, 3], ids=["lane_sqmul", "half_window", "lanes16_window", "lanes8_window"])
+@pytest.fixture(params=[0, 1, 2, 3, 4], ids=["lane_sqmul", "half_window", "lanes16_window", "lanes8_window",
+                                             "lanes8_window16"])
 def jump_variant(request):
     R.ranmar_tune_set(R.RANMAR_K_JUMP, request.param)
     yield request.param
