@@ -111,6 +111,8 @@ struct ranmar_batch {
   bool launched = false;
   size_t prepared_bytes = 0;  // descriptor bytes staged by prepare, 0 = none
   BatchBuffers B{};
+  std::vector<BReq> tmp;      // prepare: slices with draws, before the final layout
+  bool tried_wtab16 = false;  // the 16-bit window table was asked for
   uint8_t* kdesc = nullptr;   // kernel argument storage for the graph node
   void* kargs[2] = {nullptr, nullptr};
 };
@@ -186,6 +188,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
     b->B.queue = b->d_queue;
     b->B.err = b->h_err;
     b->B.wtab = window_table();
+    b->B.wtab16 = nullptr;  // set by the first batch with many requests without draws
     b->B.spare = (uint32_t)b->max_slices;
     ok = b->B.wtab != nullptr;
   }
@@ -215,18 +218,26 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   b->prepared_bytes = 0;
   if (n > b->max_req) return RANMAR_ENOMEM;
   if (n == 0) return RANMAR_OK;
-  uint64_t total = 0;
+  uint64_t total = 0, n_jo = 0;  // chunks; requests without draws
   for (uint64_t r = 0; r < n; ++r) {
     uint64_t nq = 0;
     int rc = check_request(reqs[r], b->L, &nq);
     if (rc) return rc;
     total += nq;
+    n_jo += nq == 0;
   }
   if (total > b->max_chunks) return RANMAR_ENOMEM;
+  // Many requests without draws: jump them with 16-bit windows (the 203 MB
+  // table is built once per device, on first use; if it cannot be, the 8-bit
+  // table serves).  The kernel node takes the new pointer at the next launch.
+  if (n_jo >= 16384 && !b->B.wtab16 && !b->tried_wtab16) {
+    b->tried_wtab16 = true;
+    b->B.wtab16 = window16_table();
+    b->grid_node = 0;  // forces the kernel node's arguments to be set again
+  }
   // Bins: about 4 units of work (jumps + chunks) per bin at least, at most 64.
   const uint64_t cost = n + total;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(kMaxBins, std::max<uint64_t>(1, cost / 4));
-  const uint64_t T = (cost + nb - 1) / nb;  // work per bin; >= 4 when nb > 1
   const uint64_t req_off = req_offset(nb), chunk_off = chunk_offset(n, nb);
   // The staging buffer may still be read by the previous run's copy.
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
@@ -236,69 +247,87 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   BChunk* ch = (BChunk*)(b->h_desc + chunk_off);
   std::memset(b->h_desc, 0, req_off);
   const uint64_t L = b->L;
-  uint64_t ns = 0, nc = 0, fill = 0;
+
+  // Requests with draws, in order, fill the bins one after the other with
+  // about Tc units (one per slice jump, one per chunk) each; a request that
+  // does not fit is cut at a chunk boundary and continues in the next bin.
+  // Their slices are collected in b->tmp, in bin order.
+  const uint64_t Tc = std::max<uint64_t>(2, (n - n_jo + total + nb - 1) / nb);
+  std::vector<BReq>& tmp = b->tmp;
+  tmp.clear();
+  std::vector<uint32_t> nsc(nb, 0), nkb(nb, 0);
+  uint64_t nc = 0, fill = 0;
   uint32_t x = 0;
   for (uint64_t r = 0; r < n; ++r) {
     const ranmar_request& q = reqs[r];
     const uint64_t nq = (q.count + L - 1) / L;
+    if (nq == 0) continue;
     uint64_t first = 0;  // chunks of request r placed so far
-    for (;;) {
-      const uint64_t left = nq - first;
-      uint64_t take = left;
+    while (first < nq) {
+      uint64_t take = nq - first;
       if (x + 1 < nb) {
-        // Chunks that still fit beside this slice's jump.
-        const uint64_t room = fill + 1 < T ? T - fill - 1 : 0;
-        if (fill > 0 && (fill + 1 > T || (left > 0 && room == 0))) {
-          bins[x].ns = (uint32_t)(ns - bins[x].s0);
-          bins[x].nk = (uint32_t)(nc - bins[x].k0);
+        const uint64_t room = fill + 1 < Tc ? Tc - fill - 1 : 0;  // chunks that fit beside this slice's jump
+        if (fill > 0 && room == 0) {
           ++x;
-          bins[x].s0 = (uint32_t)ns;
-          bins[x].k0 = (uint32_t)nc;
           fill = 0;
           continue;
         }
-        if (take > room) take = room;
+        if (take > room) take = room;  // >= 1: room >= Tc - 1 >= 1 in an empty bin
       }
       const uint64_t d0 = first * L;
-      BReq& s = sl[ns];
-      s = to_breq(q);
+      BReq s = to_breq(q);
       const unsigned __int128 off = ((unsigned __int128)q.offset.hi << 64 | q.offset.lo) + d0;
       s.off_lo = (uint64_t)off;
       s.off_hi = (uint64_t)(off >> 64);
       s.count = std::min<uint64_t>(q.count - d0, take * L);
-      s.out = q.count ? s.out + 4 * d0 : s.out;
+      s.out += 4 * d0;
       s.state = (first + take == nq) ? s.state : 0;
+      const uint32_t local = nsc[x]++;
       for (uint64_t k = 0; k < take; ++k, ++nc) {
-        ch[nc].req = (uint32_t)ns;
+        ch[nc].req = local;
         ch[nc].q = (uint32_t)k;
         const uint64_t rem = s.count - k * L;
         ch[nc].draws = (uint32_t)(rem < L ? rem : L);
         ch[nc].last = (k + 1 == take) ? 1u : 0u;
       }
-      ++ns;
+      nkb[x] += (uint32_t)take;
+      tmp.push_back(s);
       fill += 1 + take;
       first += take;
-      if (first == nq) break;
     }
   }
-  bins[x].ns = (uint32_t)(ns - bins[x].s0);
-  bins[x].nk = (uint32_t)(nc - bins[x].k0);
-  const uint32_t nbu = x + 1;
-  // Workgroups per bin: as many as the fullest bin has items, within the
-  // device.  Jump pairs are taken g at a time when a bin has many.
-  const uint32_t wpb_max = b->workers_max / nbu;
+  // Slice table: per bin, its slices with draws, then its share of the
+  // requests without draws (an equal split, in order).
+  const bool octets = b->B.wtab16 != nullptr;
+  const uint32_t wpb_max = std::max<uint32_t>(1, b->workers_max / nb);
+  uint64_t ns = 0, ti = 0, k0 = 0, jr = 0;
   uint32_t wpb = 1;
-  for (uint32_t i = 0; i < nbu; ++i) {
-    const uint32_t n_jg = (bins[i].ns + 1) / 2;
-    uint32_t g = n_jg / (2u * wpb_max);
-    g = g < 1u ? 1u : (g > 8u ? 8u : g);
-    bins[i].g = g;
-    bins[i].n_ju = (n_jg + g - 1) / g;
-    bins[i].n_cg = (bins[i].nk + 1) / 2;
-    wpb = std::max(wpb, std::min(wpb_max, bins[i].n_ju + bins[i].n_cg));
+  for (uint32_t i = 0; i < nb; ++i) {
+    BBin& bn = bins[i];
+    bn.s0 = (uint32_t)ns;
+    for (uint32_t k = 0; k < nsc[i]; ++k) sl[ns++] = tmp[ti++];
+    const uint64_t njo = n_jo * (i + 1) / nb - n_jo * i / nb;
+    for (uint64_t k = 0; k < njo; ++k) {
+      while (reqs[jr].count != 0) ++jr;
+      sl[ns++] = to_breq(reqs[jr++]);
+    }
+    bn.ns = (uint32_t)(ns - bn.s0);
+    bn.nsc = octets ? nsc[i] : bn.ns;  // without the 16-bit table, pair items take every slice
+    bn.k0 = (uint32_t)k0;
+    bn.nk = nkb[i];
+    k0 += nkb[i];
+    // Jump pairs and octets are taken several at a time when a bin has many.
+    const uint32_t n_jg = (bn.nsc + 1) / 2, n_jq = (bn.ns - bn.nsc + 7) / 8;
+    bn.g = std::min<uint32_t>(8, std::max<uint32_t>(1, n_jg / (2 * wpb_max)));
+    bn.n_ju = (n_jg + bn.g - 1) / bn.g;
+    bn.n_cg = (bn.nk + 1) / 2;
+    bn.gq = std::min<uint32_t>(8, std::max<uint32_t>(1, n_jq / (2 * wpb_max)));
+    bn.n_qi = (n_jq + bn.gq - 1) / bn.gq;
+    // Workgroups per bin: as many as the fullest bin has items, within the device.
+    wpb = std::max(wpb, std::min(wpb_max, bn.n_ju + bn.n_cg + bn.n_qi));
   }
-  h->n_bins = nbu;
-  h->n_workers = nbu * wpb;
+  h->n_bins = nb;
+  h->n_workers = nb * wpb;
   h->epoch = ++b->epoch;
   h->L = b->L;
   h->req_off = req_off;
@@ -415,7 +444,7 @@ extern "C" int ranmar_run_unbatched(const ranmar_request* reqs, uint64_t n, void
     d.r0 = to_breq(reqs[r]);
     d.L = kDefaultChunk;
     d.epoch = ++c.epoch;
-    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), c.queue, c.err, 1u};
+    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), nullptr, c.queue, c.err, 1u};
     if (!B.wtab) return RANMAR_ENOMEM;
     const uint64_t items = 1 + (nq + 1) / 2;
     const unsigned grid = (unsigned)(items < maxgrid ? items : maxgrid);

@@ -13,14 +13,19 @@
 // its own seed + jump) and of their chunks, and has its own queue counter on
 // its own 256-byte line: one counter shared by the whole grid serialises
 // every dequeue at one memory channel.  Workgroup w serves bin w mod n_bins.
-// Items of a bin, taken in order from its counter by one-wave workgroups:
-//   [0, n_ju)            jump groups: g jump pairs; each half-wave seeds one
-//                        slice and jumps it to its offset (parallel seeding
-//                        and the windowed jump of coop_dev.hpp), then raises
-//                        the slice's flag;
-//   [n_ju, n_ju + n_cg)  chunk pairs: each half-wave places one chunk start
-//                        (P_{qL} applied to the slice's start state, in LDS)
-//                        and generates the chunk's draws.
+// A bin's slices with draws come first, then its slices without (jumps
+// only).  Items of a bin, taken in order from its counter by one-wave
+// workgroups:
+//   [0, n_ju)                   pair items: g jump pairs; each half-wave seeds
+//                               one slice with draws and jumps it to its
+//                               offset (parallel seeding and the windowed jump
+//                               of coop_dev.hpp), then raises its flag;
+//   [n_ju, n_ju + n_cg)         chunk pairs: each half-wave places one chunk
+//                               start (P_{qL} applied to the slice's start
+//                               state, in LDS) and generates the chunk's draws;
+//   [.., .. + n_qi)             octet items: gq jump octets; each 8-lane group
+//                               seeds and jumps one slice without draws
+//                               (nothing waits for these, so they come last).
 // A chunk waits for its slice's flag (flag == run epoch, so flags never need
 // clearing).  A chunk's slice is in the chunk's own bin and every jump item of
 // a bin precedes its chunk items, so the jump a chunk waits for has already
@@ -42,10 +47,12 @@ struct BHeader {        // 64 bytes
 };
 struct BBin {           // 256 bytes: the counter alone on its line
   uint32_t ctr;         // next item (0 at launch: the descriptor copy resets it)
-  uint32_t s0, ns;      // slices [s0, s0 + ns)
+  uint32_t s0, ns, nsc; // slices [s0, s0 + ns): the first nsc by pair items, the rest (no draws) by octet items
   uint32_t k0, nk;      // chunks [k0, k0 + nk)
-  uint32_t g, n_ju, n_cg;  // jump pairs per jump item, jump items, chunk pairs
-  uint32_t pad[56];
+  uint32_t g, n_ju;     // jump pairs (slices with draws) per pair item, pair items
+  uint32_t n_cg;        // chunk pairs
+  uint32_t gq, n_qi;    // jump octets (slices without draws) per octet item, octet items
+  uint32_t pad[53];
 };
 struct BReq {           // 48 bytes
   int32_t seed;
@@ -56,7 +63,7 @@ struct BReq {           // 48 bytes
   uint64_t state;
 };
 struct BChunk {         // 16 bytes
-  uint32_t req, q, draws, last;  // slice, chunk index in the slice, draws, last of the slice
+  uint32_t req, q, draws, last;  // slice (index within its bin), chunk index in the slice, draws, last of the slice
 };
 static_assert(sizeof(BHeader) == 64 && sizeof(BBin) == 256 && sizeof(BReq) == 48 && sizeof(BChunk) == 16,
               "descriptor layout");
@@ -64,7 +71,7 @@ constexpr uint32_t kMaxBins = 64;
 
 // A bin's ranges, as held in registers (the counter is only touched atomically).
 struct BinInfo {
-  uint32_t s0, ns, k0, nk, g, n_ju, n_cg;
+  uint32_t s0, ns, nsc, k0, nk, g, n_ju, n_cg, gq, n_qi;
 };
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // x ~100 cycles per sleep: about 0.2 s
@@ -76,7 +83,7 @@ struct TableDesc {
   __device__ __forceinline__ BHeader header() const { return *(const BHeader*)desc; }
   __device__ __forceinline__ BinInfo bin(uint32_t x) const {
     const BBin* b = (const BBin*)(desc + 64) + x;
-    return BinInfo{b->s0, b->ns, b->k0, b->nk, b->g, b->n_ju, b->n_cg};
+    return BinInfo{b->s0, b->ns, b->nsc, b->k0, b->nk, b->g, b->n_ju, b->n_cg, b->gq, b->n_qi};
   }
   __device__ __forceinline__ uint32_t* counter(uint32_t x, uint32_t*) const { return &((BBin*)(desc + 64))[x].ctr; }
   __device__ __forceinline__ BReq req(const BHeader& h, uint32_t r) const {
@@ -104,11 +111,14 @@ struct SingleDesc {
     const uint64_t nq = (r0.count + L - 1) / L;
     b.s0 = 0;
     b.ns = 1;  // one jump pair, its second half idle
+    b.nsc = 1;
     b.k0 = 0;
     b.nk = (uint32_t)nq;
     b.g = 1;
     b.n_ju = 1;
     b.n_cg = (uint32_t)((nq + 1) / 2);
+    b.gq = 1;
+    b.n_qi = 0;
     return b;
   }
   __device__ __forceinline__ uint32_t* counter(uint32_t, uint32_t* queue) const { return queue; }
@@ -139,7 +149,8 @@ struct BatchBuffers {
   uint32_t* req_states;    // 98 words per slice
   uint32_t* done;          // one flag per slice, plus one spare written by idle halves
   const uint32_t* ptab;    // 97 words per q: P_{qL}
-  const uint32_t* wtab;    // window table T[w][d]
+  const uint32_t* wtab;    // window table T[w][d], 8-bit digits
+  const uint32_t* wtab16;  // window table with 16-bit digits, or nullptr
   uint32_t* queue;         // single-request launches: [0] next item, [1] finished workgroups
   int* err;                // host-visible error word
   uint32_t spare;          // index of the spare flag
@@ -147,6 +158,9 @@ struct BatchBuffers {
 
 // LDS per half-wave: the extended window X (193 words) and a polynomial (97).
 constexpr int kHalfLds = 193 + 97;
+// LDS per 8-lane group of a jump octet (stride 1 mod 4: see k_jump_grp).
+constexpr int kOctStride = 193 + 97 + 3;
+constexpr int kWaveLds = 8 * kOctStride > 2 * kHalfLds ? 8 * kOctStride : 2 * kHalfLds;
 
 // Hand-off of a slice's start state from the wave that jumped it to the waves
 // that generate its chunks, which may run on other XCDs (each XCD has its own
@@ -175,7 +189,7 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   const uint32_t lane = threadIdx.x;
   const uint32_t half = lane >> 5, l = lane & 31u;
   const uint32_t rl = 2u * p + half;
-  const bool active = rl < bn.ns;
+  const bool active = rl < bn.nsc;
   const uint32_t r = bn.s0 + rl;
   uint32_t* X = lds + half * kHalfLds;
   uint32_t* Bp = X + 193;
@@ -226,13 +240,14 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   BChunk ch{};
   BReq rq{};
   if (active) ch = D.chunk(h, j);
+  const uint32_t r = bn.s0 + ch.req;  // the chunk's slice
   // P_{qL} does not depend on the slice: fetch it before waiting.
   const uint32_t* P = B.ptab + (uint64_t)ch.q * 97u;
   const uint32_t p0 = P[l], p1 = P[l + 32], p2 = P[l + 64], p3 = P[96];
   if (active) {
-    rq = D.req(h, ch.req);
+    rq = D.req(h, r);
     uint32_t it = 0;
-    while (__hip_atomic_load(&B.done[ch.req], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != h.epoch) {
+    while (__hip_atomic_load(&B.done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != h.epoch) {
       __builtin_amdgcn_s_sleep(2);
       if (++it > kSpinLimit) {
         __hip_atomic_store(B.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -244,7 +259,7 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   // this scope; the words are read with device-scope loads).
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   // Chunk start: the slice's start state times P_{qL}(A), c by qL steps.
-  uint32_t* src = B.req_states + (uint64_t)ch.req * kWords;
+  uint32_t* src = B.req_states + (uint64_t)r * kWords;
   X[l] = active ? dev_load(src + l) : 0u;
   X[l + 32] = active ? dev_load(src + l + 32) : 0u;
   X[l + 64] = active ? dev_load(src + l + 64) : 0u;
@@ -268,18 +283,57 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   wave_sync();
 }
 
+// Eight slices without draws per wave, 8 lanes each (seed_group / jump_group
+// of coop_dev.hpp, 16-bit windows; the host makes octet items only when that
+// table exists).  Nothing waits for them: the state goes straight to the
+// caller's record, if it asked for one.
+template <class Desc>
+__device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, const BatchBuffers& B,
+                                               const BinInfo& bn, uint32_t qi, uint32_t* lds) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t grp = lane >> 3, l = lane & 7u;
+  const uint32_t rl = bn.nsc + 8u * qi + grp;
+  const bool active = rl < bn.ns;
+  uint32_t* X = lds + grp * kOctStride;
+  uint32_t* Bp = X + 193;
+  BReq q{};
+  if (active) q = D.req(h, bn.s0 + rl);
+  const bool valid = active && seed_group<8>(q.seed, X, l);
+  if (!valid) {
+#pragma unroll
+    for (int k = 0; k < 96; k += 8) X[l + k] = 0;
+    if (l == 0) X[96] = X[97] = 0;
+  }
+  wave_sync();
+  const uint32_t c = X[97];
+  const uint32_t j0 = valid ? (uint32_t)q.off_lo : 0u, j1 = valid ? (uint32_t)(q.off_lo >> 32) : 0u;
+  const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
+  jump_group<8, 16>(X, Bp, B.wtab16, j0, j1, j2, j3, wave_windows<16>(j0, j1, j2, j3), l);
+  if (active && q.state) {
+    uint32_t* dst = (uint32_t*)q.state;
+#pragma unroll
+    for (int k = 0; k < 96; k += 8) dst[l + k] = valid ? X[l + k] : 0u;
+    if (l == 0) {
+      dst[96] = valid ? X[96] : 0u;
+      dst[97] = valid ? c_jump(c, u128_mod_m(j0, j1, j2, j3)) : kInvalidC;
+    }
+  }
+  wave_sync();
+}
+
 // One-wave workgroups; workgroup w serves bin w mod n_bins.  The bin index
 // and everything derived from it stay wave-uniform (scalar registers).
 template <class Desc>
 __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B) {
   const BHeader h = D.header();
   const uint32_t lane = threadIdx.x;
-  __shared__ uint32_t lds[2 * kHalfLds];
+  __shared__ uint32_t lds[kWaveLds];
   if (blockIdx.x >= h.n_workers) return;
   const uint32_t x = blockIdx.x % h.n_bins;
   const BinInfo bn = D.bin(x);
   uint32_t* ctr = D.counter(x, B.queue);
-  const uint32_t n_jg = (bn.ns + 1) / 2;
+  const uint32_t n_jg = (bn.nsc + 1) / 2;           // jump pairs
+  const uint32_t n_jq = (bn.ns - bn.nsc + 7) / 8;   // jump octets
   for (;;) {
     // Dequeue without a lane-conditional branch: every lane executes the
     // atomic, lane 0 adding 1 and the others 0, and lane 0's result is taken.
@@ -293,6 +347,10 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
       for (uint32_t p = item * bn.g; p < p1; ++p) batch_jump_pair(D, h, B, bn, p, lds);
     } else if (item < bn.n_ju + bn.n_cg) {
       batch_chunk_pair(D, h, B, bn, item - bn.n_ju, lds);
+    } else if (item < bn.n_ju + bn.n_cg + bn.n_qi) {
+      const uint32_t it = item - bn.n_ju - bn.n_cg;
+      const uint32_t p1 = (it + 1) * bn.gq < n_jq ? (it + 1) * bn.gq : n_jq;
+      for (uint32_t p = it * bn.gq; p < p1; ++p) batch_jump_oct(D, h, B, bn, p, lds);
     } else {
       break;
     }

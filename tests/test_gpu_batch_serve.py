@@ -317,3 +317,32 @@ def test_batch_splits_requests_across_bins(orc):
             _check(orc, items)
     finally:
         R.ranmar_batch_destroy(b)
+
+
+def test_batch_jump_octets_and_pairs(orc):
+    """From 16384 requests without draws the batch jumps them eight per wave
+    with 16-bit windows (octet items), after the slices with draws.  Same bits
+    as ranmar_seed_jump and the oracle; the requests with draws in the same
+    batch match too."""
+    n = 20000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=23)
+    states = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+    items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                  state=states[i]) for i in range(n)]
+    drawn = _alloc(_mixed_requests(6, 60, max_count=70_000, with_zero=False))
+    mixed = items[:10000] + drawn + items[10000:]
+    b = R.ranmar_batch_create(len(mixed), 64)
+    try:
+        say(f"batch octets n={len(mixed)}")
+        R.ranmar_batch_run(b, R.make_requests(mixed))
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+    w = u32(states)
+    direct = u32(R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                    torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev())))
+    assert np.array_equal(w, direct)
+    idx = [0, 1, 4999, 10000, n - 1]
+    ref = orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx]))
+    assert np.array_equal(w[idx], ref)
+    _check(orc, drawn)
