@@ -260,9 +260,9 @@ def run_bulk1m(R, torch, steps, warmup):
                                "1,024 float32 draws each", "streams": n, "draws_per_stream": cnt},
         "output_write_GBps": 4 * draws / (ms * 1e-3) / 1e9,
         "output_write_frac": 4 * draws / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": algo / (ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "k_gen32_wide<f32>", "achieved": algo / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_gen32<1, true>", n // 8 * 256),
+                     "traffic": profiled_traffic("k_gen32_wide<1, true>", n // 8 * 256),
                      "bytes_per_launch": algo, "launch_ms": ms},
     }
 

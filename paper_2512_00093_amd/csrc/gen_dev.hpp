@@ -49,17 +49,39 @@ __device__ __forceinline__ void emit(void* row, uint64_t idx, uint32_t k, bool i
     *p = w;
 }
 
+// A stream's state as the 32 lanes of a half-wave hold it: lane l has words
+// l, 32+l, 64+l of the window; every lane has word 96 and c.
+struct StreamRegs {
+  uint32_t s97, s65, s33, rprev, c0;
+};
+
+__device__ __forceinline__ StreamRegs load_stream(const uint32_t* W, uint32_t l) {
+  return StreamRegs{W[l], W[32 + l], W[64 + l], W[96], W[97]};
+}
+
 // `count` draws of one stream by the 32 lanes of a half-wave (l = lane within
 // the half, lane = lane within the wave).  W: the stream's state record;
 // dst: where the state after the draws goes (may equal W; nullptr: nowhere);
 // row: the stream's first output element.  All lanes of the half must call it
 // with the same arguments; the other half may run a different stream.
 template <int FMT, bool NT>
+__device__ __forceinline__ void gen_regs32(uint32_t l, uint32_t lane, StreamRegs st, const uint32_t* W,
+                                           uint32_t* dst, uint64_t count, bool is_f32, void* out_row);
+
+template <int FMT, bool NT>
 __device__ __forceinline__ void gen_stream32(uint32_t l, uint32_t lane, const uint32_t* W, uint32_t* dst,
                                              uint64_t count, bool is_f32, void* out_row) {
-  uint32_t s97 = W[l], s65 = W[32 + l], s33 = W[64 + l];
-  uint32_t rprev = W[96];  // x_{T-1} for lane 0 of the first block
-  const uint32_t c0 = W[97];
+  gen_regs32<FMT, NT>(l, lane, load_stream(W, l), W, dst, count, is_f32, out_row);
+}
+
+// The same from a state already in registers (W: its record, compared with
+// dst only).
+template <int FMT, bool NT>
+__device__ __forceinline__ void gen_regs32(uint32_t l, uint32_t lane, StreamRegs st, const uint32_t* W,
+                                           uint32_t* dst, uint64_t count, bool is_f32, void* out_row) {
+  uint32_t s97 = st.s97, s65 = st.s65, s33 = st.s33;
+  uint32_t rprev = st.rprev;  // x_{T-1} for lane 0 of the first block
+  const uint32_t c0 = st.c0;
 
   if (count == 0) {
     if (dst && dst != W) {

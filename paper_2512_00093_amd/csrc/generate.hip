@@ -1,5 +1,7 @@
 // Bulk generation over many independent streams: one stream per half-wave,
 // two per wave64, eight per workgroup (see gen_dev.hpp for the mapping).
+#include <algorithm>
+
 #include "common.hpp"
 #include "gen_dev.hpp"
 #include "internal.hpp"
@@ -15,6 +17,27 @@ __global__ __launch_bounds__(256) void k_gen32(const uint32_t* __restrict__ sin,
   if (s >= n) return;  // a whole half-wave leaves together; shifts stay inside a half
   gen_stream32<FMT, NT>(l, lane, sin + s * kWords, sout ? sout + s * kWords : nullptr, count, FMT == RANMAR_F32,
                         (char*)out + s * ld * 4u);
+}
+
+// Several streams per half-wave: half-wave h takes streams h, h + H, h + 2H,
+// ... (H half-waves in the grid) and loads the next stream's state while it
+// generates the current one, so short streams do not wait for their state.
+template <int FMT, bool NT>
+__global__ __launch_bounds__(256) void k_gen32_pipe(const uint32_t* __restrict__ sin, uint32_t* sout, uint64_t n,
+                                                    uint64_t count, void* __restrict__ out, uint64_t ld, uint64_t H) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t l = lane & 31u;
+  const uint64_t h = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2u + (lane >> 5);
+  if (h >= n) return;  // a whole half-wave leaves together
+  StreamRegs cur = load_stream(sin + h * kWords, l);
+  for (uint64_t s = h; s < n; s += H) {
+    const uint64_t sn = s + H;
+    StreamRegs nxt = cur;
+    if (sn < n) nxt = load_stream(sin + sn * kWords, l);  // in flight during the draws below
+    gen_regs32<FMT, NT>(l, lane, cur, sin + s * kWords, sout ? sout + s * kWords : nullptr, count,
+                        FMT == RANMAR_F32, (char*)out + s * ld * 4u);
+    cur = nxt;
+  }
 }
 
 // Wide-store variant: eight half-waves per workgroup, each with a 512-byte LDS
@@ -37,6 +60,7 @@ const char* gen_variant_name(int v) {
     case GEN_LANES32_NT: return "lanes32_nt";
     case GEN_WIDE4: return "lanes32_wide4";
     case GEN_WIDE4_NT: return "lanes32_wide4_nt";
+    case GEN_PIPE_NT: return "lanes32_pipe_nt";
     default: return "?";
   }
 }
@@ -51,6 +75,21 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   const bool wide_ok = (((uintptr_t)out & 15) == 0) && (ld % 4 == 0);
   if (!wide_ok && variant == GEN_WIDE4) variant = GEN_LANES32;
   if (!wide_ok && variant == GEN_WIDE4_NT) variant = GEN_LANES32_NT;
+  if (variant == GEN_PIPE_NT) {
+    // Enough half-waves for about four times what the device holds at once;
+    // each then takes about n / H streams.
+    int dev = 0, cus = 256, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gen32_pipe<FMT, true>, wg, 0) !=
+            hipSuccess || per_cu <= 0)
+      per_cu = 8;
+    const uint64_t cap = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)per_cu * per_wg;  // resident half-waves
+    uint64_t H = std::min<uint64_t>(n, 4 * cap);
+    const dim3 g((unsigned)((H + per_wg - 1) / per_wg));
+    H = (uint64_t)g.x * per_wg;  // every half-wave of the grid takes part in the stride
+    hipLaunchKernelGGL((k_gen32_pipe<FMT, true>), g, dim3(wg), 0, st, sin, sout, n, count, out, ld, H);
+    return hipGetLastError();
+  }
   switch (variant) {
     case GEN_WIDE4:
       hipLaunchKernelGGL((k_gen32_wide<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);

@@ -45,7 +45,8 @@ enum GenVariant : int {
   GEN_LANES32_NT = 1,  // same, non-temporal output stores
   GEN_WIDE4 = 2,       // four blocks per step, LDS transpose, 16-byte stores
   GEN_WIDE4_NT = 3,    // same, non-temporal
-  GEN_NUM_VARIANTS = 4
+  GEN_PIPE_NT = 4,     // 32 lanes per stream, several streams per half-wave with the next state prefetched
+  GEN_NUM_VARIANTS = 5
 };
 const char* gen_variant_name(int v);
 hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uint64_t n, uint64_t count, int fmt,

@@ -51,7 +51,10 @@ int gen_variant_for(uint64_t n, uint64_t count) {
   if (g_forced[RANMAR_K_GENERATE] >= 0) return g_forced[RANMAR_K_GENERATE];
   auto it = g_table.find({RANMAR_K_GENERATE, ilog2(n), ilog2(count)});
   if (it != g_table.end()) return it->second;
-  return GEN_LANES32_NT;
+  // Short rows: 16-byte stores of four blocks at a time write them faster
+  // (measured on 2^20 streams x 1,024 draws); long rows: 4-byte stores do as
+  // well.  The wide form falls back to 4-byte stores for unaligned rows.
+  return count <= 2048 ? GEN_WIDE4_NT : GEN_LANES32_NT;
 }
 
 // Times the jump variants on n seed+jump requests with `bits`-bit offsets.
