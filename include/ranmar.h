@@ -75,8 +75,9 @@ typedef enum ranmar_status {
 
 /* Output format of generated draws. */
 typedef enum ranmar_fmt {
-    RANMAR_U24 = 0, /* uint32 k, 0 <= k < 2^24 (the value is k * 2^-24) */
-    RANMAR_F32 = 1  /* float k * 2^-24, exact in binary32 */
+    RANMAR_U24 = 0,     /* uint32 k, 0 <= k < 2^24 (the value is k * 2^-24) */
+    RANMAR_F32 = 1,     /* float k * 2^-24, exact in binary32 */
+    RANMAR_U24_F32 = 2  /* both, in two planes (ranmar_generate only) */
 } ranmar_fmt;
 
 /* ------------------------------------------------------------------------ */
@@ -161,6 +162,9 @@ int ranmar_jump_family(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n
 /* For each stream r < n: `count` consecutive draws of Algorithm 2 starting
  * from d_in[r], written to row r of d_out (row stride `ld` elements,
  * ld >= count; element type uint32 for RANMAR_U24, float for RANMAR_F32).
+ * RANMAR_U24_F32 writes every draw in both forms in one pass: uint32 k in
+ * plane 0 (d_out, as for RANMAR_U24) and float k * 2^-24 in plane 1 (starting
+ * n * ld elements after d_out, same row layout).
  * If d_state_out is not NULL the state after the draws is written there
  * (d_state_out may equal d_in: in-place advance; otherwise it must not
  * overlap d_in).  d_out must be 4-byte aligned and must not overlap the
@@ -180,7 +184,7 @@ int ranmar_generate(const ranmar_state *d_in, ranmar_state *d_state_out, uint64_
  * followed by ranmar_generate(count) for the request alone. */
 typedef struct ranmar_request {
     int32_t seed;
-    uint32_t fmt;       /* ranmar_fmt */
+    uint32_t fmt;       /* ranmar_fmt: RANMAR_U24 or RANMAR_F32 */
     ranmar_u128 offset; /* J of the first draw's predecessor state */
     uint64_t count;     /* draws */
     void *d_out;        /* device, count elements */

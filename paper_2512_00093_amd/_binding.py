@@ -11,7 +11,8 @@ raw words travel in int32/int64 tensors of the same width):
   jumps    int64  [n, 2]    ranmar_u128 records (lo, hi) as raw 64-bit limbs
   polys    int32  [n, 97]   coefficients b_0..b_96 of t^J mod phi
   seeds    int32  [n]
-  draws    int32 (RANMAR_U24) or float32 (RANMAR_F32), [n, ld]
+  draws    int32 (RANMAR_U24) or float32 (RANMAR_F32), [n, ld]; RANMAR_U24_F32: int32 [2, n, ld]
+           (plane 1 holds float32 bit patterns: view it as float32)
 """
 from __future__ import annotations
 
@@ -33,6 +34,7 @@ RANMAR_ETIMEDOUT = -6
 RANMAR_ENODEV = -7
 RANMAR_U24 = 0
 RANMAR_F32 = 1
+RANMAR_U24_F32 = 2
 RANMAR_K_GENERATE = 0
 RANMAR_K_JUMP = 1
 STATE_WORDS = 98
@@ -230,11 +232,14 @@ def ranmar_jump_family(base, delta: int, n: int, out=None, stream=None):
 def ranmar_generate(states_in, count: int, fmt: int = RANMAR_U24, out=None, states_out=None, ld=None,
                     stream=None):
     n = states_in.shape[0]
+    planes = 2 if fmt == RANMAR_U24_F32 else 1
     if ld is None:
         ld = count if out is None else out.shape[-1]
     if out is None:
         dt = torch.float32 if fmt == RANMAR_F32 else torch.int32
-        out = torch.empty((n, ld), dtype=dt, device=states_in.device)
+        out = torch.empty((planes, n, ld) if planes == 2 else (n, ld), dtype=dt, device=states_in.device)
+    elif count and (not out.is_contiguous() or out.numel() < planes * n * ld or out.element_size() != 4):
+        raise ValueError("out must be a contiguous 4-byte tensor of at least planes * n * ld elements")
     _check(lib().ranmar_generate(_ptr(states_in), _ptr(states_out), n, count, fmt, _ptr(out) if count else None,
                                  ld, _stream(stream)), "ranmar_generate")
     return out

@@ -161,14 +161,15 @@ int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n
 int ranmar_generate(const ranmar_state* d_in, ranmar_state* d_state_out, uint64_t n, uint64_t count, int fmt,
                     void* d_out, uint64_t ld, void* stream) {
   if (n == 0) return RANMAR_OK;
-  if (fmt != RANMAR_U24 && fmt != RANMAR_F32) return RANMAR_EINVAL;
+  if (fmt != RANMAR_U24 && fmt != RANMAR_F32 && fmt != RANMAR_U24_F32) return RANMAR_EINVAL;
   if (!d_in || !aligned(d_in, 4) || (d_state_out && !aligned(d_state_out, 4))) return RANMAR_EINVAL;
   if (count > 0 && (!d_out || !aligned(d_out, 4) || ld < count)) return RANMAR_EINVAL;
-  if (ld > (UINT64_MAX / 4) / n) return RANMAR_EINVAL;
+  if (ld > (UINT64_MAX / 8) / n) return RANMAR_EINVAL;
   const uint64_t sb = sizeof(ranmar_state) * n;
   if (d_state_out && d_state_out != d_in && overlap(d_in, sb, d_state_out, sb)) return RANMAR_EINVAL;
   if (count > 0) {
-    const uint64_t ob = 4 * (ld * (n - 1) + count);
+    const uint64_t planes = fmt == RANMAR_U24_F32 ? 2 : 1;
+    const uint64_t ob = 4 * (ld * n * (planes - 1) + ld * (n - 1) + count);
     if (overlap(d_out, ob, d_in, sb) || (d_state_out && overlap(d_out, ob, d_state_out, sb))) return RANMAR_EINVAL;
   }
   int rc = ensure_init();

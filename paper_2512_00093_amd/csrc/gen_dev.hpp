@@ -26,23 +26,27 @@ namespace ranmar {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) u32x4 gu32x4;
 
-// Runtime-format variant of the output stage (FMT_RUNTIME): both encodings
-// are formed and the word for the stream's format is stored, so two half-waves
-// of one wave may write different formats without diverging.
-constexpr int FMT_RUNTIME = 2;
+// Output stage.  FMT is RANMAR_U24, RANMAR_F32, RANMAR_U24_F32 (both: k to
+// plane 0, the float to plane 1, `plane` elements further on) or FMT_RUNTIME:
+// both encodings are formed and the one for the stream's format is stored, so
+// two half-waves of one wave may write different formats without diverging.
+constexpr int FMT_RUNTIME = 16;
 
 template <int FMT, bool NT>
-__device__ __forceinline__ void emit(void* row, uint64_t idx, uint32_t k, bool is_f32) {
-  uint32_t w;
-  if (FMT == RANMAR_F32) {
-    w = __float_as_uint((float)k * 0x1p-24f);
-  } else if (FMT == RANMAR_U24) {
-    w = k;
-  } else {
-    const uint32_t fw = __float_as_uint((float)k * 0x1p-24f);
-    w = is_f32 ? fw : k;
-  }
+__device__ __forceinline__ void emit(void* row, uint64_t idx, uint32_t k, bool is_f32, uint64_t plane = 0) {
   gu32* p = gptr(row) + idx;
+  const uint32_t fw = __float_as_uint((float)k * 0x1p-24f);
+  if (FMT == RANMAR_U24_F32) {
+    if (NT) {
+      __builtin_nontemporal_store(k, p);
+      __builtin_nontemporal_store(fw, p + plane);
+    } else {
+      p[0] = k;
+      p[plane] = fw;
+    }
+    return;
+  }
+  const uint32_t w = FMT == RANMAR_F32 ? fw : FMT == RANMAR_U24 ? k : (is_f32 ? fw : k);
   if (NT)
     __builtin_nontemporal_store(w, p);
   else
@@ -66,19 +70,21 @@ __device__ __forceinline__ StreamRegs load_stream(const uint32_t* W, uint32_t l)
 // with the same arguments; the other half may run a different stream.
 template <int FMT, bool NT>
 __device__ __forceinline__ void gen_regs32(uint32_t l, uint32_t lane, StreamRegs st, const uint32_t* W,
-                                           uint32_t* dst, uint64_t count, bool is_f32, void* out_row);
+                                           uint32_t* dst, uint64_t count, bool is_f32, void* out_row,
+                                           uint64_t plane = 0);
 
 template <int FMT, bool NT>
 __device__ __forceinline__ void gen_stream32(uint32_t l, uint32_t lane, const uint32_t* W, uint32_t* dst,
-                                             uint64_t count, bool is_f32, void* out_row) {
-  gen_regs32<FMT, NT>(l, lane, load_stream(W, l), W, dst, count, is_f32, out_row);
+                                             uint64_t count, bool is_f32, void* out_row, uint64_t plane = 0) {
+  gen_regs32<FMT, NT>(l, lane, load_stream(W, l), W, dst, count, is_f32, out_row, plane);
 }
 
 // The same from a state already in registers (W: its record, compared with
 // dst only).
 template <int FMT, bool NT>
 __device__ __forceinline__ void gen_regs32(uint32_t l, uint32_t lane, StreamRegs st, const uint32_t* W,
-                                           uint32_t* dst, uint64_t count, bool is_f32, void* out_row) {
+                                           uint32_t* dst, uint64_t count, bool is_f32, void* out_row,
+                                           uint64_t plane) {
   uint32_t s97 = st.s97, s65 = st.s65, s33 = st.s33;
   uint32_t rprev = st.rprev;  // x_{T-1} for lane 0 of the first block
   const uint32_t c0 = st.c0;
@@ -112,7 +118,7 @@ __device__ __forceinline__ void gen_regs32(uint32_t l, uint32_t lane, StreamRegs
 #define RANMAR_GEN_STEP(S97, S33, Q)                                       \
   {                                                                        \
     const uint32_t v_ = S97 - S33;                                         \
-    emit<FMT, NT>(row, (Q) * 32u, (v_ - c) & kMask, is_f32);               \
+    emit<FMT, NT>(row, (Q) * 32u, (v_ - c) & kMask, is_f32, plane);        \
     c = c_add(c, kStep);                                                   \
     const uint32_t rot_ = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)v_); \
     S97 = lead ? rprev : rot_;                                             \
@@ -139,7 +145,7 @@ __device__ __forceinline__ void gen_regs32(uint32_t l, uint32_t lane, StreamRegs
   // Last (possibly partial) block: rr = count - 32q draws in 1..32.
   const uint32_t v = s97 - s33;
   const uint32_t rr = (uint32_t)(count - 32u * q);
-  if (l < rr) emit<FMT, NT>(row, q * 32u, (v - c) & kMask, is_f32);
+  if (l < rr) emit<FMT, NT>(row, q * 32u, (v - c) & kMask, is_f32, plane);
 
   if (dst) {
     // The new window x_{count+1..count+97} is covered by what the lanes hold:

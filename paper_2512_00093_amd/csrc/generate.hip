@@ -10,13 +10,13 @@ namespace ranmar {
 
 template <int FMT, bool NT>
 __global__ __launch_bounds__(256) void k_gen32(const uint32_t* __restrict__ sin, uint32_t* sout, uint64_t n,
-                                               uint64_t count, void* __restrict__ out, uint64_t ld) {
+                                               uint64_t count, void* __restrict__ out, uint64_t ld, uint64_t plane) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t l = lane & 31u;
   const uint64_t s = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2u + (lane >> 5);
   if (s >= n) return;  // a whole half-wave leaves together; shifts stay inside a half
   gen_stream32<FMT, NT>(l, lane, sin + s * kWords, sout ? sout + s * kWords : nullptr, count, FMT == RANMAR_F32,
-                        (char*)out + s * ld * 4u);
+                        (char*)out + s * ld * 4u, plane);
 }
 
 // Several streams per half-wave: half-wave h takes streams h, h + H, h + 2H,
@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_gen32(const uint32_t* __restrict__ sin,
 // generates the current one, so short streams do not wait for their state.
 template <int FMT, bool NT>
 __global__ __launch_bounds__(256) void k_gen32_pipe(const uint32_t* __restrict__ sin, uint32_t* sout, uint64_t n,
-                                                    uint64_t count, void* __restrict__ out, uint64_t ld, uint64_t H) {
+                                                    uint64_t count, void* __restrict__ out, uint64_t ld, uint64_t H,
+                                                    uint64_t plane) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t l = lane & 31u;
   const uint64_t h = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2u + (lane >> 5);
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_gen32_pipe(const uint32_t* __restrict__
     StreamRegs nxt = cur;
     if (sn < n) nxt = load_stream(sin + sn * kWords, l);  // in flight during the draws below
     gen_regs32<FMT, NT>(l, lane, cur, sin + s * kWords, sout ? sout + s * kWords : nullptr, count,
-                        FMT == RANMAR_F32, (char*)out + s * ld * 4u);
+                        FMT == RANMAR_F32, (char*)out + s * ld * 4u, plane);
     cur = nxt;
   }
 }
@@ -71,8 +72,9 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   const unsigned wg = 256;
   const uint64_t per_wg = wg / 32;
   const dim3 grid((unsigned)((n + per_wg - 1) / per_wg));
-  // The wide stores need 16-byte aligned rows.
-  const bool wide_ok = (((uintptr_t)out & 15) == 0) && (ld % 4 == 0);
+  // The wide stores need 16-byte aligned rows, and write one format.
+  const bool wide_ok = (((uintptr_t)out & 15) == 0) && (ld % 4 == 0) && FMT != RANMAR_U24_F32;
+  const uint64_t plane = n * ld;  // second plane of RANMAR_U24_F32
   if (!wide_ok && variant == GEN_WIDE4) variant = GEN_LANES32;
   if (!wide_ok && variant == GEN_WIDE4_NT) variant = GEN_LANES32_NT;
   if (variant == GEN_PIPE_NT) {
@@ -87,21 +89,23 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
     uint64_t H = std::min<uint64_t>(n, 4 * cap);
     const dim3 g((unsigned)((H + per_wg - 1) / per_wg));
     H = (uint64_t)g.x * per_wg;  // every half-wave of the grid takes part in the stride
-    hipLaunchKernelGGL((k_gen32_pipe<FMT, true>), g, dim3(wg), 0, st, sin, sout, n, count, out, ld, H);
+    hipLaunchKernelGGL((k_gen32_pipe<FMT, true>), g, dim3(wg), 0, st, sin, sout, n, count, out, ld, H, plane);
     return hipGetLastError();
   }
   switch (variant) {
     case GEN_WIDE4:
-      hipLaunchKernelGGL((k_gen32_wide<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+      if constexpr (FMT != RANMAR_U24_F32)
+        hipLaunchKernelGGL((k_gen32_wide<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
       break;
     case GEN_WIDE4_NT:
-      hipLaunchKernelGGL((k_gen32_wide<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+      if constexpr (FMT != RANMAR_U24_F32)
+        hipLaunchKernelGGL((k_gen32_wide<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
       break;
     case GEN_LANES32_NT:
-      hipLaunchKernelGGL((k_gen32<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+      hipLaunchKernelGGL((k_gen32<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld, plane);
       break;
     default:
-      hipLaunchKernelGGL((k_gen32<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+      hipLaunchKernelGGL((k_gen32<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld, plane);
       break;
   }
   return hipGetLastError();
@@ -111,6 +115,7 @@ hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uin
                            void* out, uint64_t ld, hipStream_t st) {
   if (!n) return hipSuccess;
   if (fmt == RANMAR_F32) return launch_fmt<RANMAR_F32>(variant, sin, sout, n, count, out, ld, st);
+  if (fmt == RANMAR_U24_F32) return launch_fmt<RANMAR_U24_F32>(variant, sin, sout, n, count, out, ld, st);
   return launch_fmt<RANMAR_U24>(variant, sin, sout, n, count, out, ld, st);
 }
 

@@ -149,22 +149,24 @@ __global__ __launch_bounds__(256) void k_seed_coop(const int32_t* __restrict__ s
 }
 
 // One radix-256 round of a stream family: with the first M starts in place,
-// start s in [M, min(n, 256 M)) is start s mod M jumped by (s div M) M delta.
+// start s in [first, min(n, 256 M)) is start s mod M jumped by (s div M) M
+// delta, the sources read from src (the family itself, or the base record in
+// the first round, where M = 1 and start 0 is the base jumped by 0).
 // MD = M delta (< 2^128), MDmod = MD mod m.  The factors are the table rows
 // of the exponent's nonzero 8-bit digits; for delta = 2^40 and M = 256^i the
 // exponent has one digit, so every start costs one application.
-__global__ __launch_bounds__(256) void k_family_radix(uint32_t* __restrict__ out, const uint32_t* __restrict__ T,
-                                                      uint64_t M, uint64_t cnt, uint64_t md_lo, uint64_t md_hi,
-                                                      uint32_t md_mod) {
+__global__ __launch_bounds__(256) void k_family_radix(uint32_t* __restrict__ out, const uint32_t* src_tab,
+                                                      const uint32_t* __restrict__ T, uint64_t M, uint64_t first,
+                                                      uint64_t cnt, uint64_t md_lo, uint64_t md_hi, uint32_t md_mod) {
   __shared__ uint32_t lds[8 * kHalfWords];
   const uint32_t hw = threadIdx.x >> 5, l = threadIdx.x & 31u;
   const uint64_t g = (uint64_t)blockIdx.x * 8u + hw;
   const bool active = g < cnt;
-  const uint64_t s = M + (active ? g : 0);
+  const uint64_t s = first + (active ? g : 0);
   const uint64_t jdig = s / M, src_i = s - jdig * M;
   uint32_t* X = lds + hw * kHalfWords;
   uint32_t* B = X + 193;
-  const uint32_t* src = out + src_i * kWords;
+  const uint32_t* src = src_tab + src_i * kWords;
   X[l] = src[l];
   X[l + 32] = src[l + 32];
   X[l + 64] = src[l + 64];
@@ -203,18 +205,17 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
   if (n > 1 && D > kMax / (n - 1)) return hipErrorInvalidValue;
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
-  if (base != out) {
-    hipError_t e = hipMemcpyAsync(out, base, 4 * kWords, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
-  }
-  for (uint64_t M = 1; M < n;) {
-    const uint64_t top = (M <= n / 256) ? 256 * M : n;  // starts [M, top) this round
-    const uint64_t cnt = top - M;
+  // Round 1 reads the base record and also writes start 0 (the base itself)
+  // unless the family is built in place.
+  for (uint64_t M = 1, first = (base != out) ? 0 : 1; M < n || first < M; first = M) {
+    const uint64_t top = (M <= n / 256) ? 256 * M : n;  // starts [first, top) this round
+    const uint64_t cnt = top - first;
     if ((cnt + 7) / 8 > 0x7FFFFFFFull) return hipErrorInvalidValue;
     const unsigned __int128 MD = D * M;  // <= (n - 1) delta
     const uint32_t md_mod = (uint32_t)(MD % kMod);
-    hipLaunchKernelGGL(k_family_radix, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out, T, M, cnt,
-                       (uint64_t)MD, (uint64_t)(MD >> 64), md_mod);
+    hipLaunchKernelGGL(k_family_radix, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out,
+                       M == 1 ? base : (const uint32_t*)out, T, M, first, cnt, (uint64_t)MD, (uint64_t)(MD >> 64),
+                       md_mod);
     M = top;
   }
   return hipGetLastError();

@@ -194,6 +194,42 @@ def test_generate_count_zero_copies():
     assert np.array_equal(u32(d_out), st)
 
 
+@pytest.mark.parametrize("n,count,ld", [(1, 1, 1), (3, 33, 40), (17, 1000, 1000), (64, 4097, 4100)])
+def test_generate_both_formats(orc, n, count, ld):
+    """RANMAR_U24_F32: every draw as uint32 k in plane 0 and as the float
+    k * 2^-24 in plane 1, in one pass, with every generation variant; the
+    state after the draws as with one format."""
+    st = np.stack([orc.state_from_seed(40 + k) for k in range(n)])
+    ref, ref_st = orc.draws_many(st, count)
+    nv = R.ranmar_tune_variants(R.RANMAR_K_GENERATE)
+    try:
+        for v in range(nv):
+            R.ranmar_tune_set(R.RANMAR_K_GENERATE, v)
+            say(f"generate both n={n} count={count} ld={ld} variant={v}")
+            out = torch.full((2, n, ld), -5, dtype=torch.int32, device=dev())
+            so = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+            R.ranmar_generate(states_t(st), count, R.RANMAR_U24_F32, out=out, states_out=so, ld=ld)
+            w = u32(out)
+            assert np.array_equal(w[0, :, :count], ref), v
+            assert np.array_equal(w[1, :, :count], f32_words(ref)), v
+            assert (w[:, :, count:] == np.uint32(0xFFFFFFFB)).all(), v   # padding untouched
+            assert np.array_equal(u32(so), ref_st), v
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_GENERATE, -1)
+
+
+def test_family_in_place(orc):
+    """d_base == d_out: the family is built around its own first record."""
+    delta, n = (1 << 40) + 7, 600
+    base = orc.state_from_seed(31)
+    fam = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+    fam[0] = states_t(base)[0]
+    say("jump_family in place n=600")
+    R.ranmar_jump_family(fam[:1], delta, n, out=fam)
+    ind = R.ranmar_seed_jump(seeds_t([31] * n), jumps_t([k * delta for k in range(n)]))
+    assert torch.equal(fam, ind)
+
+
 def test_generate_variants_bit_identical(orc):
     n, count = 64, 777
     st = np.stack([orc.state_from_seed(5 + k) for k in range(n)])
