@@ -15,7 +15,8 @@
 // run alone: the jumps are exact and compose (Sec. 3).
 //
 // With cfg.unbatched every admitted request is launched on its own (one launch
-// per request, no graph, no packing): the baseline.
+// per request, no graph, no packing): the baseline.  A batched tick that holds
+// a single request is launched the same way.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -232,8 +233,11 @@ struct ranmar_server {
         // submissions and releases go on meanwhile (only this thread uses the
         // lane).
         lk.unlock();
-        int rc = cfg.unbatched ? ranmar_run_unbatched(ln.reqbuf.data(), ln.reqbuf.size(), ln.st)
-                               : ranmar_batch_run(ln.b, ln.reqbuf.data(), ln.reqbuf.size(), ln.st);
+        // A tick of one request is launched with the request passed by value
+        // (no descriptor copy); the draws are the same either way.
+        int rc = (cfg.unbatched || ln.reqbuf.size() == 1)
+                     ? ranmar_run_unbatched(ln.reqbuf.data(), ln.reqbuf.size(), ln.st)
+                     : ranmar_batch_run(ln.b, ln.reqbuf.data(), ln.reqbuf.size(), ln.st);
         if (rc == RANMAR_OK && hipEventRecord(ln.ev, ln.st) != hipSuccess) rc = RANMAR_EHIP;
         lk.lock();
         if (rc != RANMAR_OK) err = rc;
