@@ -190,6 +190,43 @@ __global__ __launch_bounds__(256) void k_family_radix(uint32_t* __restrict__ out
   }
 }
 
+// The same round with G lanes per start (the grouped jump of k_jump_grp), for
+// rounds with many starts.
+template <int G>
+__global__ __launch_bounds__(256) void k_family_radix_grp(uint32_t* __restrict__ out, const uint32_t* src_tab,
+                                                          const uint32_t* __restrict__ T, uint64_t M, uint64_t first,
+                                                          uint64_t cnt, uint64_t md_lo, uint64_t md_hi,
+                                                          uint32_t md_mod) {
+  constexpr uint32_t kPerWg = 256 / G;
+  __shared__ uint32_t lds[kPerWg * kGroupStride];
+  const uint32_t q = threadIdx.x / G, l = threadIdx.x % G;
+  const uint64_t g = (uint64_t)blockIdx.x * kPerWg + q;
+  const bool active = g < cnt;
+  const uint64_t s = first + (active ? g : 0);
+  const uint64_t jdig = s / M, src_i = s - jdig * M;
+  uint32_t* X = lds + q * kGroupStride;
+  uint32_t* B = X + 193;
+  const uint32_t* src = src_tab + src_i * kWords;
+#pragma unroll
+  for (int k = 0; k < 96; k += G) X[l + k] = src[l + k];
+  if (l == 0) X[96] = src[96];
+  const uint32_t c = src[97];
+  const unsigned __int128 E = (unsigned __int128)jdig * (((unsigned __int128)md_hi << 64) | md_lo);
+  const uint64_t elo = active ? (uint64_t)E : 0, ehi = active ? (uint64_t)(E >> 64) : 0;
+  const uint32_t j0 = (uint32_t)elo, j1 = (uint32_t)(elo >> 32), j2 = (uint32_t)ehi, j3 = (uint32_t)(ehi >> 32);
+  wave_sync();
+  jump_group<G, 8>(X, B, T, j0, j1, j2, j3, wave_windows<8>(j0, j1, j2, j3), l);
+  if (active) {
+    uint32_t* dst = out + s * kWords;
+#pragma unroll
+    for (int k = 0; k < 96; k += G) dst[l + k] = X[l + k];
+    if (l == 0) {
+      dst[96] = X[96];
+      dst[97] = c_jump(c, (uint32_t)(jdig * md_mod % kMod));
+    }
+  }
+}
+
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_seed_coop, dim3((unsigned)((n + 7) / 8)), dim3(256), 0, st, seeds, n, out);
@@ -213,9 +250,13 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
     if ((cnt + 7) / 8 > 0x7FFFFFFFull) return hipErrorInvalidValue;
     const unsigned __int128 MD = D * M;  // <= (n - 1) delta
     const uint32_t md_mod = (uint32_t)(MD % kMod);
-    hipLaunchKernelGGL(k_family_radix, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out,
-                       M == 1 ? base : (const uint32_t*)out, T, M, first, cnt, (uint64_t)MD, (uint64_t)(MD >> 64),
-                       md_mod);
+    const uint32_t* src = M == 1 ? base : (const uint32_t*)out;
+    if (cnt >= 16384)  // many starts: 8 lanes each (more useful multiply-adds per issue)
+      hipLaunchKernelGGL((k_family_radix_grp<8>), dim3((unsigned)((cnt + 31) / 32)), dim3(256), 0, st, out, src, T,
+                         M, first, cnt, (uint64_t)MD, (uint64_t)(MD >> 64), md_mod);
+    else  // few: 32 lanes each (lower latency)
+      hipLaunchKernelGGL(k_family_radix, dim3((unsigned)((cnt + 7) / 8)), dim3(256), 0, st, out, src, T, M, first,
+                         cnt, (uint64_t)MD, (uint64_t)(MD >> 64), md_mod);
     M = top;
   }
   return hipGetLastError();
