@@ -304,7 +304,9 @@ int ranmar_serve_replay(ranmar_server *s, uint64_t n, const double *t_arrival_s,
  * bits; the tuner only picks the fastest for a shape. */
 typedef enum ranmar_kernel {
     RANMAR_K_GENERATE = 0,
-    RANMAR_K_JUMP = 1
+    RANMAR_K_JUMP = 1,
+    RANMAR_K_FAMILY = 2   /* ranmar_jump_family: radix rounds on the VALU, or
+                             a matrix product on the matrix cores (MFMA) */
 } ranmar_kernel;
 
 /* Number of variants of a kernel, and a short name for each. */
@@ -315,7 +317,8 @@ const char *ranmar_tune_variant_name(int kernel, int variant);
 int ranmar_tune_set(int kernel, int variant);
 
 /* Times every variant of `kernel` on synthetic data of the given shape
- * (n streams/requests, count draws or jump bits) on `stream`, stores the
+ * (n streams/requests; count = draws, jump bits, or for RANMAR_K_FAMILY
+ * log2 of the spacing delta) on `stream`, stores the
  * winner for the shape bucket and writes the per-variant mean time (ms) to
  * ms_out[variant] (host, ranmar_tune_variants() entries, may be NULL).
  * Returns the winning variant index, or a negative status. */

@@ -37,6 +37,7 @@ RANMAR_F32 = 1
 RANMAR_U24_F32 = 2
 RANMAR_K_GENERATE = 0
 RANMAR_K_JUMP = 1
+RANMAR_K_FAMILY = 2
 STATE_WORDS = 98
 
 

@@ -64,6 +64,15 @@ static int seed_host(int64_t seed, ranmar_state* out) {
   return RANMAR_OK;
 }
 
+hipError_t launch_family_variant(int v, const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out,
+                                 hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  if (v == FAMILY_GEMM) e = launch_family_gemm(base, delta, n, out, st);
+  if (e == hipErrorInvalidValue) e = launch_family_window(base, delta, n, out, st);
+  if (e == hipErrorInvalidValue) e = launch_family(base, delta, n, out, st);
+  return e;
+}
+
 }  // namespace ranmar
 
 using namespace ranmar;
@@ -153,9 +162,8 @@ int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n
     return RANMAR_EINVAL;
   int rc = ensure_init();
   if (rc) return rc;
-  const hipError_t e = launch_family_window((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, (hipStream_t)stream);
-  if (e != hipErrorInvalidValue) return hip_status(e);
-  return hip_status(launch_family((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, (hipStream_t)stream));
+  return hip_status(launch_family_variant(family_variant_for(n), (const uint32_t*)d_base, delta, n, (uint32_t*)d_out,
+                                          (hipStream_t)stream));
 }
 
 int ranmar_generate(const ranmar_state* d_in, ranmar_state* d_state_out, uint64_t n, uint64_t count, int fmt,

@@ -25,6 +25,19 @@ const uint32_t* window16_table();  // T[w][d] = t^(d 2^(16w)) mod phi, per devic
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
 // Family by table factors; hipErrorInvalidValue if an exponent needs > 128 bits.
 hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
+// Family as a matrix product on the matrix cores; hipErrorInvalidValue if
+// the family is too small for it or an exponent needs > 128 bits.
+hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
+enum FamilyVariant : int {
+  FAMILY_RADIX = 0,  // radix-256 rounds, one table application per start (VALU)
+  FAMILY_GEMM = 1,   // ~sqrt(97 n) direct starts, the rest as int8 MFMA products
+  FAMILY_NUM_VARIANTS = 2
+};
+int family_variant_for(uint64_t n);
+// A family with the given variant, falling back (radix rounds, then the
+// polynomial path) where the variant does not apply.
+hipError_t launch_family_variant(int v, const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out,
+                                 hipStream_t st);
 
 enum JumpVariant : int {
   JUMP_LANE_SQMUL = 0,      // one request per lane, square-and-multiply in VGPRs

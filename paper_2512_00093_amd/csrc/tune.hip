@@ -19,7 +19,7 @@ namespace ranmar {
 
 namespace {
 std::mutex g_mu;
-int g_forced[2] = {-1, -1};
+int g_forced[3] = {-1, -1, -1};
 std::map<std::tuple<int, int, int>, int> g_table;  // (kernel, log2 n, log2 count) -> variant
 
 int ilog2(uint64_t v) {
@@ -44,6 +44,16 @@ int jump_variant_for(uint64_t n) {
   // (a third of the latency per request, more workgroups) and the 1.6 MB
   // table.
   return n >= 16384 ? JUMP_EIGHTH_WINDOW16 : JUMP_HALF_WINDOW;
+}
+
+int family_variant_for(uint64_t n) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (g_forced[RANMAR_K_FAMILY] >= 0) return g_forced[RANMAR_K_FAMILY];
+  auto it = g_table.find({RANMAR_K_FAMILY, ilog2(n), 0});
+  if (it != g_table.end()) return it->second;
+  // Measured: the product form wins on 2^20 starts (0.25 ms against 0.39 ms)
+  // and loses on 65,536 (0.039 ms against 0.036 ms).
+  return n >= 131072 ? FAMILY_GEMM : FAMILY_RADIX;
 }
 
 int gen_variant_for(uint64_t n, uint64_t count) {
@@ -122,6 +132,54 @@ done:
   return rc;
 }
 
+// Times the family variants on n starts at spacing 2^lg from seed 1.
+static int tune_family(uint64_t n, int lg, double* ms_out, hipStream_t st) {
+  if (n < 2 || n > (1ull << 24) || lg < 0 || lg > 100) return RANMAR_EINVAL;
+  ranmar_state h{};
+  if (ranmar_seed(1, &h) != RANMAR_OK) return RANMAR_EINVAL;
+  const unsigned __int128 d = (unsigned __int128)1 << lg;
+  const ranmar_u128 delta{(uint64_t)d, (uint64_t)(d >> 64)};
+  uint32_t *d_base = nullptr, *d_out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = RANMAR_EHIP;
+  double best = 1e30;
+  int best_v = 0;
+  if (hipMalloc(&d_base, sizeof(ranmar_state)) != hipSuccess ||
+      hipMalloc(&d_out, sizeof(ranmar_state) * n) != hipSuccess)
+    goto done;
+  if (hipMemcpyAsync(d_base, &h, sizeof h, hipMemcpyHostToDevice, st) != hipSuccess) goto done;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+  for (int v = 0; v < FAMILY_NUM_VARIANTS; ++v) {
+    if (launch_family_variant(v, d_base, delta, n, d_out, st) != hipSuccess) goto done;
+    hipEventRecord(e0, st);
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r)
+      if (launch_family_variant(v, d_base, delta, n, d_out, st) != hipSuccess) goto done;
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) goto done;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / reps;
+    if (ms_out) ms_out[v] = per;
+    if (per < best) {
+      best = per;
+      best_v = v;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table[{RANMAR_K_FAMILY, ilog2(n), 0}] = best_v;
+  }
+  rc = best_v;
+done:
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  hipFree(d_out);
+  hipFree(d_base);
+  return rc;
+}
+
 }  // namespace ranmar
 
 using namespace ranmar;
@@ -131,6 +189,7 @@ extern "C" {
 int ranmar_tune_variants(int kernel) {
   if (kernel == RANMAR_K_GENERATE) return GEN_NUM_VARIANTS;
   if (kernel == RANMAR_K_JUMP) return kJumpVariants;
+  if (kernel == RANMAR_K_FAMILY) return FAMILY_NUM_VARIANTS;
   return RANMAR_EINVAL;
 }
 
@@ -141,6 +200,8 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_JUMP && variant == JUMP_QUARTER_WINDOW) return "lanes16_window8";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW) return "lanes8_window8";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW16) return "lanes8_window16";
+  if (kernel == RANMAR_K_FAMILY && variant == FAMILY_RADIX) return "radix256_valu";
+  if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM) return "product_mfma_i8";
   return nullptr;
 }
 
@@ -159,6 +220,7 @@ int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if (kernel == RANMAR_K_JUMP) return tune_jump(n, count ? (int)count : 120, ms_out, st);
+  if (kernel == RANMAR_K_FAMILY) return tune_family(n, count ? (int)count : 40, ms_out, st);
   if (count == 0 || n > (1ull << 24) || count > (1ull << 24) || n * count > (1ull << 31)) return RANMAR_EINVAL;
   // Synthetic states: seeds 1..n at offset 0.
   int32_t* d_seeds = nullptr;

@@ -218,6 +218,28 @@ def test_generate_both_formats(orc, n, count, ld):
         R.ranmar_tune_set(R.RANMAR_K_GENERATE, -1)
 
 
+@pytest.mark.parametrize("variant", [0, 1], ids=["radix_valu", "product_mfma"])
+@pytest.mark.parametrize("n,delta", [(8192, 1 << 40), (9999, (1 << 40) + 12345), (70_001, 1 << 40),
+                                     (5000, (1 << 115) + 12345), (300, 1 << 40)])
+def test_family_variants(orc, variant, n, delta):
+    """Both family variants against independent jumps: radix rounds on the
+    VALU, and the matrix product (about sqrt(97 n) direct starts, the rest as
+    int8 MFMA products with limb splitting).  The product form also covers a
+    ragged last block (70,001) and 15-digit factors (2^115 spacing); n = 300 is
+    below its minimum and falls back."""
+    base = orc.state_from_seed(4711)
+    R.ranmar_tune_set(R.RANMAR_K_FAMILY, variant)
+    try:
+        say(f"jump_family variant={variant} n={n} delta={delta}")
+        fam = R.ranmar_jump_family(states_t(base), delta, n)
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_FAMILY, -1)
+    ind = R.ranmar_seed_jump(seeds_t([4711] * n), jumps_t([k * delta for k in range(n)]))
+    assert torch.equal(fam, ind)
+    for k in sorted({0, 1, n // 3, n - 1}):
+        assert np.array_equal(u32(fam[k]), orc.jump(base, k * delta)), k
+
+
 def test_family_in_place(orc):
     """d_base == d_out: the family is built around its own first record."""
     delta, n = (1 << 40) + 7, 600
@@ -405,6 +427,8 @@ def test_tune_run_jump_and_generate():
     assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_JUMP) and all(m > 0 for m in ms)
     best, ms = R.ranmar_tune_run(R.RANMAR_K_GENERATE, 4096, 4096)
     assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_GENERATE) and all(m > 0 for m in ms)
+    best, ms = R.ranmar_tune_run(R.RANMAR_K_FAMILY, 20000, 40)
+    assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_FAMILY) and all(m > 0 for m in ms)
 
 
 def test_seed_batch_both_paths(orc):
