@@ -207,16 +207,21 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step(True)
+        step(False)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    # Per-phase times from a second, instrumented pass: event records between
+    # the phases add idle time on the stream, so the timed steps carry none.
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
     draws = n * cnt
     gen_ms = tm.mean_ms("gen_f32")
     gen_bytes = 4 * draws + 2 * 392 * n          # float32 output + state read + state write-back
     res = {
         "metric": "draws/s", "value": draws / dt, "unit": "draws/s", "ms_per_step": dt * 1e3,
         "dtype": "u24", "config": {"workload": f"family65k: 65,536 streams from seed 4711 at offsets k*2^40 "
-                                   f"({'radix-256 family rounds' if jump_mode == 'family' else 'one jump per stream'}"
+                                   f"({'family jump: int8 MFMA product of shared factors' if jump_mode == 'family' else 'one jump per stream'}"
                                    "), 4,096 draws each written as uint32 and as float32",
                                    "streams": n, "draws_per_stream": cnt, "jump": jump_mode},
         "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},

@@ -1,31 +1,39 @@
 // Stream families as a matrix product on the matrix cores (MFMA int8).
 //
 // Starts k * delta, k < n, from a base state.  Write n = A * B (A a multiple
-// of 16, B = ceil(n / A)) and start s = j A + i (i < A, j < B).  Then
+// of 16, A ~ sqrt(n), B = ceil(n / A)) and start s = j A + i (i < A, j < B).
+// Then
 //     x_s = x_i  P_j(A_c)        with P_j = t^(j A delta) mod phi
 // (Sec. 3.1: the jump is the matrix P(A_c) of the companion matrix A_c acting
 // on the row vector x), and c_s is c_i jumped by j A delta (Sec. 3.2).  So the
 // x-parts of all starts with the same j are one product
 //     Y_j [A x 97] = W [A x 97] * Q_j [97 x 97],   Q_j = P_j(A_c) mod 2^24,
-// where row r of Q_j is the unit window e_r jumped by j A delta.  Every
-// factor is shared by A starts: a dense contraction, unlike a jump of one
-// state by its own polynomial.
+// a dense contraction: every factor is shared by A starts, unlike a jump of
+// one state by its own polynomial.
+//
+// Row r of Q_j is the unit window e_r jumped by J = j A delta, i.e. terms
+// J .. J+96 of the sequence g_r that starts from e_r.  The recurrence
+// x_n = x_(n-97) - x_(n-33) gives g_r(n) = g_(r+1)(n+1) for r != 63 and
+// g_63(n) = g_64(n+1) + g_96(n), so with h = terms J .. J+192 of g_96 (e_96
+// jumped by J, then extended by 96 steps):
+//     Q_j[r][l] = h[l + 96 - r] + (r <= 63 ? h[l + 63 - r] : 0)   (mod 2^24).
+// One jump per factor instead of 97.
 //
 // Launch 1 (VALU, 32 lanes per job, the windowed jump of coop_dev.hpp):
 //   jobs [0, A):          x_i = base jumped by i delta (with c), into out;
-//   jobs [A, A + 128(B-1)): job (j, r): row r of Q_j (e_r jumped by j A delta),
-//                         written as three signed 8-bit limbs, transposed
-//                         (k = r contiguous) and zero-padded to 112 x 128,
-//                         the layout the MFMA B operand reads.
-// Launch 2 (MFMA): a workgroup per (j, 8 tiles of 16 sources) stages Q_j in
-// LDS once; each wave takes two tiles: the 16 x 97 block of W is split into
-// limbs in registers, and for each of seven 16-column tiles
+//   jobs [A, A + B - 1):  h of factor j = job - A + 1, 193 words.
+// Launch 2 (MFMA): a workgroup per (j, 4 x tpw tiles of 16 sources) turns h
+// into the limb sequences from which every B operand is read (Q_j is two
+// Toeplitz bands, see below); each wave loads its tiles' 16 x 97 blocks of W
+// into registers, splits them into limbs, and for each of seven 16-column
+// tiles computes
 //     Y = W0 Q0 + 2^8 (W0 Q1 + W1 Q0) + 2^16 (W0 Q2 + W1 Q1 + W2 Q0)  (mod 2^24)
 // with v_mfma_i32_16x16x64_i8 (K = 97 padded to 128: two steps), 12 MFMAs
-// per tile.  Exactness: a 24-bit word is w0 + 2^8 w1 + 2^16 w2 (mod 2^24)
+// per column tile.  Exactness: a 24-bit word is w0 + 2^8 w1 + 2^16 w2 (mod 2^24)
 // with signed limbs in [-128, 127]; limb products with weight >= 2^24 vanish
-// mod 2^24; each accumulator sums at most 3 x 97 products of magnitude <= 2^14,
-// far inside int32, and the final combination wraps mod 2^32, then is masked.
+// mod 2^24; each of the six accumulators (one per limb product) sums at most
+// 97 products of magnitude <= 2^14, far inside int32, and the final
+// combination wraps mod 2^32, then is masked.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,9 +47,8 @@ namespace ranmar {
 namespace {
 
 constexpr int kQN = 112;  // output columns, padded to 7 tiles of 16
-constexpr int kQK = 128;  // source words, padded to 2 K-steps of 64
-constexpr uint64_t kQBytes = 3ull * kQN * kQK;  // one Q_j: three limb planes of [kQN][kQK] int8
-constexpr int kL1Words = 193 + 97;             // LDS per half-wave: extended window + polynomial
+constexpr int kHWords = 196;  // one factor's h (193 words), rows 16-byte aligned
+constexpr int kL1Words = 193 + 97;  // LDS per half-wave: extended window + polynomial
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -55,7 +62,7 @@ __device__ __forceinline__ void limbs3(uint32_t v, int& w0, int& w1, int& w2) {
   w2 = (int)(int8_t)(t & 0xFF);  // the top carry (2^24) is dropped: mod 2^24
 }
 
-__global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_t* out, int8_t* __restrict__ Qg,
+__global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_t* out, uint32_t* __restrict__ H,
                                                    const uint32_t* __restrict__ T, uint64_t A, uint64_t njobs,
                                                    uint64_t d_lo, uint64_t d_hi, uint64_t ad_lo, uint64_t ad_hi,
                                                    uint32_t in_place) {
@@ -68,7 +75,6 @@ __global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_
   uint32_t* Bp = X + 193;
   unsigned __int128 E = 0;
   uint32_t c = 0;
-  uint64_t jq = 0, r = 0;
   if (is_start) {
     X[l] = base[l];
     X[l + 32] = base[l + 32];
@@ -77,14 +83,9 @@ __global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_
     c = base[97];
     E = (unsigned __int128)t * (((unsigned __int128)d_hi << 64) | d_lo);  // t delta <= (n - 1) delta
   } else {
-    const uint64_t u = active ? t - A : 0;
-    jq = u / kQK;  // j - 1
-    r = u % kQK;
-    X[l] = X[l + 32] = X[l + 64] = 0;
-    if (l == 0) X[96] = 0;
-    wave_sync();
-    if (l == 0 && r < 97) X[r] = 1u;
-    if (active && r < 97) E = (unsigned __int128)(jq + 1) * (((unsigned __int128)ad_hi << 64) | ad_lo);
+    X[l] = X[l + 32] = X[l + 64] = 0;  // e_96
+    if (l == 0) X[96] = 1u;
+    if (active) E = (unsigned __int128)(t - A + 1) * (((unsigned __int128)ad_hi << 64) | ad_lo);
   }
   wave_sync();
   const uint32_t j0 = (uint32_t)E, j1 = (uint32_t)(E >> 32), j2 = (uint32_t)(E >> 64), j3 = (uint32_t)(E >> 96);
@@ -101,147 +102,190 @@ __global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_
       dst[97] = c_jump(c, u128_mod_m(j0, j1, j2, j3));
     }
   } else {
-    // Column r of the transposed limb planes: Qg[jq][b][o][r], o < kQN.
-    int8_t* q = Qg + jq * kQBytes + r;
+    // h: the jumped window extended by 96 steps, X_(97+i) = X_i - X_(i+64).
 #pragma unroll
-    for (uint32_t o = l; o < (uint32_t)kQN; o += 32) {
-      int w0 = 0, w1 = 0, w2 = 0;
-      if (o < 97 && r < 97) limbs3(X[o], w0, w1, w2);
-      q[(0 * kQN + o) * kQK] = (int8_t)w0;
-      q[(1 * kQN + o) * kQK] = (int8_t)w1;
-      q[(2 * kQN + o) * kQK] = (int8_t)w2;
+    for (uint32_t s0 = 0; s0 < 96; s0 += 32) {
+      X[97 + s0 + l] = X[s0 + l] - X[s0 + l + 64];
+      wave_sync();
     }
+    uint32_t* h = H + (t - A) * kHWords;
+#pragma unroll
+    for (uint32_t o = l; o < 193; o += 32) h[o] = X[o] & kMask;
   }
 }
 
-// 16 int8 limbs (plane b) of words w[0..15] packed for an MFMA operand.
-__device__ __forceinline__ v4i pack_limbs(const int (&w)[16]) {
-  v4i v;
+// Signed 8-bit digits of v < 2^24 in bytes 0..2: with e = v + 0x808080,
+// digit k = byte k of e minus 128 lies in [-128, 127], and their weighted sum
+// is v + 2^24 (byte 3 of e), i.e. v mod 2^24; byte k of e xor 0x80 is that
+// digit in two's complement.
+__device__ __forceinline__ uint32_t limb_bytes(uint32_t v) { return (v + 0x808080u) ^ 0x808080u; }
+
+// Q_j in LDS without expanding it.  Q_j[r][o] depends only on d = o - r and
+// on whether r <= 63 (two Toeplitz bands), and the MFMA B operand of column
+// o, K-step kk and lane group kg is the 16 limbs of rows r = 64 kk + 16 kg
+// .. +15: with m = 112 - o + r these are 16 consecutive entries of
+//     L_kk,b[m] = limb b of (kk == 0 ? h[208 - m] + h[175 - m] : h[208 - m])
+// (h index out of [0, 192]: 0), since K-step 0 holds exactly the rows
+// r <= 63 and K-step 1 the rest.  The six sequences (kk, b) of 240 bytes are
+// kept in 16 copies, copy c shifted left by c bytes, so that every operand
+// is one aligned 16-byte read: entries m0 .. m0+15 sit at byte m0 - c of copy
+// c = m0 mod 16.  Entries for o >= 97 or r >= 97 are never used: those output
+// columns are not stored, and the A operand is zero for r >= 97.
+constexpr int kSeqLen = 240;                   // m in [0, 240): m0 + 15 <= 112 + 64 + 48 + 15
+constexpr int kCopyStride = 6 * kSeqLen + 16;  // 364 words = 4 x 91: copies start on distinct bank groups
+constexpr int kBaseLen = 256;                  // unshifted sequences, zero-padded
+
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));  // records are only 8-byte aligned
+
+// One tile's sources in the A-operand layout: lane (mrow, kg) holds words
+// kk*64 + kg*16 + e (e < 16) of record i0 + mrow, zero for words >= 97, and
+// lanes 0..15 (kg = 0) the record's c.
+struct SrcTile {
+  uint32_t w[2][16];
+  uint32_t c;
+};
+
+// Reads stay inside the output buffer: the last source record is A - 1 and
+// the furthest word read is 127 of it, below row A + 1 <= n.  Words >= 97
+// are loaded but replaced by zero (they are c or the next record).
+__device__ __forceinline__ void load_tile(const uint32_t* rec, uint32_t kg, SrcTile& s) {
 #pragma unroll
-  for (int d = 0; d < 4; ++d)
-    v[d] = (w[4 * d] & 0xFF) | ((w[4 * d + 1] & 0xFF) << 8) | ((w[4 * d + 2] & 0xFF) << 16) |
-           ((uint32_t)(w[4 * d + 3] & 0xFF) << 24);
-  return v;
+  for (int kk = 0; kk < 2; ++kk) {
+    const u32x4a* p = (const u32x4a*)(rec + kk * 64 + kg * 16);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const u32x4a v = p[d];
+      s.w[kk][4 * d] = v.x;
+      s.w[kk][4 * d + 1] = v.y;
+      s.w[kk][4 * d + 2] = v.z;
+      s.w[kk][4 * d + 3] = v.w;
+    }
+  }
+  s.c = rec[97];
 }
 
-// LDS layout of Q_j: 336 rows (3 limb planes x 112 columns) of 128 bytes,
-// padded to 144 so that the 16 lanes reading one 16-byte piece of 16
-// consecutive rows fall on different banks.
-constexpr int kQRow = 144;
-constexpr int kTilesPerWave = 2;
-
-__global__ __launch_bounds__(256) void k_family_gemm(uint32_t* out, const int8_t* __restrict__ Qg, uint64_t A,
-                                                     uint64_t n, uint32_t ad_mod) {
-  __shared__ __attribute__((aligned(16))) int8_t q_lds[3 * kQN * kQRow];
-  // Per wave: the 16 source records of a tile, then its 16 output records
-  // (both contiguous in memory, so they are read and written whole).
-  __shared__ uint32_t blk_all[4][16 * kWords];
+// The product kernel.  Workgroup (x, jq): factor j = jq + 1, source tiles
+// (4 x + wave) tpw + tt.  Every wave first loads its first tile, then the
+// workgroup expands h_j into Q_j in LDS; tiles are multiplied from
+// registers and written straight from the accumulators (16 consecutive words
+// of 4 records per store; the L2 merges a tile's 6272 bytes).
+__global__ __launch_bounds__(256, 3) void k_family_gemm(uint32_t* out, const uint32_t* __restrict__ H, uint64_t A,
+                                                     uint64_t n, uint32_t ad_mod, uint32_t tpw) {
+  __shared__ __attribute__((aligned(16))) uint8_t tq[16 * kCopyStride];
+  __shared__ __attribute__((aligned(16))) uint8_t tb[6 * kBaseLen];
+  __shared__ uint32_t hl[196];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t mrow = lane & 15u, kg = lane >> 4;
   const uint64_t jq = blockIdx.y, j = jq + 1;
   const uint64_t tiles = A / 16;
-  // Q_j, staged once for the workgroup's tiles: every load is issued before
-  // the first LDS write, so the round trips overlap.
-  {
-    constexpr uint32_t kChunks = kQBytes / 16, kIt = (kChunks + 255) / 256;
-    const v4i* src = (const v4i*)(Qg + jq * kQBytes);
-    v4i tmp[kIt];
-#pragma unroll
-    for (uint32_t it = 0; it < kIt; ++it) {
-      const uint32_t x = threadIdx.x + 256 * it;
-      if (x < kChunks) tmp[it] = src[x];
-    }
-#pragma unroll
-    for (uint32_t it = 0; it < kIt; ++it) {
-      const uint32_t x = threadIdx.x + 256 * it;
-      if (x < kChunks) *(v4i*)(q_lds + (x >> 3) * kQRow + (x & 7) * 16) = tmp[it];
-    }
-  }
-  __syncthreads();  // the only workgroup barrier: every wave reaches it
-  uint32_t* blk = blk_all[wave];
-  const uint32_t mrow = lane & 15u, kg = lane >> 4;
-  // Source records of a tile: 16 contiguous records, loaded into registers
-  // (all loads in flight together); the next tile's are loaded while the
-  // current tile is multiplied.
-  constexpr uint32_t kIt = (16 * kWords + 63) / 64;
-  auto tile_ok = [&](int tt) {
-    const uint64_t tile = ((uint64_t)blockIdx.x * 4 + wave) * kTilesPerWave + tt;
+  const uint64_t tile0 = ((uint64_t)blockIdx.x * 4 + wave) * tpw;
+  auto tile_ok = [&](uint64_t tile) {
     return tile < tiles && j * A + tile * 16 < n;  // blocks of the last factor may lie beyond n
   };
-  auto load_src = [&](int tt, uint32_t (&tmp)[kIt]) {
-    const uint64_t i0 = (((uint64_t)blockIdx.x * 4 + wave) * kTilesPerWave + tt) * 16;
-    const uint32_t* wsrc = out + i0 * kWords;
+  SrcTile cur;
+  if (tile_ok(tile0)) load_tile(out + (tile0 * 16 + mrow) * kWords, kg, cur);
+  if (threadIdx.x < 193) hl[threadIdx.x] = H[jq * kHWords + threadIdx.x];
+  __syncthreads();
+  {  // the six limb sequences, entry m = threadIdx.x
+    const int m = (int)threadIdx.x, i1 = 208 - m, i2 = 175 - m;
+    const uint32_t va = (i1 >= 0 && i1 <= 192) ? hl[i1] : 0u;
+    const uint32_t vb = (va + ((i2 >= 0 && i2 <= 192) ? hl[i2] : 0u)) & kMask;
+    int a0, a1, a2, b0, b1, b2;
+    limbs3(vb, b0, b1, b2);  // K-step 0: rows r <= 63
+    limbs3(va, a0, a1, a2);  // K-step 1
+    tb[0 * kBaseLen + m] = (uint8_t)b0;
+    tb[1 * kBaseLen + m] = (uint8_t)b1;
+    tb[2 * kBaseLen + m] = (uint8_t)b2;
+    tb[3 * kBaseLen + m] = (uint8_t)a0;
+    tb[4 * kBaseLen + m] = (uint8_t)a1;
+    tb[5 * kBaseLen + m] = (uint8_t)a2;
+  }
+  __syncthreads();
+  // Shifted copies: wave w fills rows it = w, w + 4, ... of the 96 (copy c,
+  // sequence cb) rows, lane p < 60 the word at bytes 4 p .. 4 p + 3, which
+  // are base bytes 4 p + c .. 4 p + c + 3 (<= cb * 256 + 254).
+  {
+    const uint32_t* tb32 = (const uint32_t*)tb;
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane(wave);  // uniform: scalar loop control
 #pragma unroll
-    for (uint32_t it = 0; it < kIt; ++it) {
-      const uint32_t w = lane + 64 * it;
-      if (w < 16 * kWords) tmp[it] = wsrc[w];
+    for (uint32_t k = 0; k < 24; ++k) {
+      const uint32_t it = w0 + 4 * k, c = it / 6, cb = it % 6;
+      if (lane < kSeqLen / 4) {
+        const uint32_t wi = cb * (kBaseLen / 4) + (c >> 2) + lane;
+        const uint32_t w = __builtin_amdgcn_alignbyte(tb32[wi + 1], tb32[wi], c & 3u);
+        *(uint32_t*)(tq + c * kCopyStride + cb * kSeqLen + 4 * lane) = w;
+      }
     }
-  };
-  uint32_t nxt[kIt];
-  if (tile_ok(0)) load_src(0, nxt);
-  for (int tt = 0; tt < kTilesPerWave; ++tt) {
-    if (!tile_ok(tt)) break;  // and so are the later tiles
-    const uint64_t tile = ((uint64_t)blockIdx.x * 4 + wave) * kTilesPerWave + tt;
-    const uint64_t i0 = tile * 16, s0 = j * A + i0;
-#pragma unroll
-    for (uint32_t it = 0; it < kIt; ++it) {
-      const uint32_t w = lane + 64 * it;
-      if (w < 16 * kWords) blk[w] = nxt[it];
-    }
-    if (tt + 1 < kTilesPerWave && tile_ok(tt + 1)) load_src(tt + 1, nxt);
-    wave_sync();
-    // A operand: rows mrow, words k = kk*64 + kg*16 + 0..15 (k >= 97: zero).
+  }
+  __syncthreads();  // every wave reaches the three barriers
+  const uint32_t jm = (uint32_t)(j * ad_mod % kMod);
+  // B operands: column o = nt*16 + mrow, K-step kk, lane group kg reads
+  // entries m0 = 112 - o + 64 kk + 16 kg of copy c = m0 mod 16 = (16 - mrow)
+  // mod 16, at byte m0 - c = (mrow == 0 ? 16 : 0) + 16 kg + 16 (6 - nt) + 64 kk
+  // of that copy's sequence (kk, b): one base per lane, constant offsets.
+  const uint32_t cq = (16u - mrow) & 15u;
+  const uint8_t* qb = tq + cq * kCopyStride + (mrow == 0 ? 16u : 0u) + kg * 16;
+  for (uint32_t tt = 0; tt < tpw; ++tt) {
+    const uint64_t tile = tile0 + tt;
+    if (!tile_ok(tile)) break;  // and so are the later tiles
+    const uint64_t s0 = j * A + tile * 16;
+    // A operand from the registers: limbs of words k = kk*64 + kg*16 + e.
     v4i a[3][2];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      int l0[16], l1[16], l2[16];
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const uint32_t k = kk * 64 + kg * 16 + e;
-        const uint32_t v = k < 97 ? blk[mrow * kWords + k] : 0u;
-        limbs3(v, l0[e], l1[e], l2[e]);
+      for (int d = 0; d < 4; ++d) {
+        uint32_t x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t k = kk * 64 + kg * 16 + 4 * d + e;
+          x[e] = limb_bytes(k < 97 ? cur.w[kk][4 * d + e] : 0u);
+        }
+        // Byte transpose: plane b takes byte b of the four words, in order.
+        const uint32_t lo01 = __builtin_amdgcn_perm(x[1], x[0], 0x05010400u);  // x0.0 x1.0 x0.1 x1.1
+        const uint32_t lo23 = __builtin_amdgcn_perm(x[3], x[2], 0x05010400u);
+        const uint32_t hi01 = __builtin_amdgcn_perm(x[1], x[0], 0x0C0C0602u);  // x0.2 x1.2 0 0
+        const uint32_t hi23 = __builtin_amdgcn_perm(x[3], x[2], 0x0C0C0602u);
+        a[0][kk][d] = (int)__builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+        a[1][kk][d] = (int)__builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+        a[2][kk][d] = (int)__builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
       }
-      a[0][kk] = pack_limbs(l0);
-      a[1][kk] = pack_limbs(l1);
-      a[2][kk] = pack_limbs(l2);
-    }
-    const uint32_t c_src = lane < 16 ? blk[lane * kWords + 97] : 0u;
-    wave_sync();  // blk now takes the outputs
+    const uint32_t c_src = cur.c;
+    if (tt + 1 < tpw && tile_ok(tile + 1)) load_tile(out + ((tile + 1) * 16 + mrow) * kWords, kg, cur);
+    const uint32_t rows = (uint32_t)(n - s0 < 16 ? n - s0 : 16);  // s0 < n: checked above
+    uint32_t* dst = out + s0 * kWords;
+    uint32_t* lp = dst + kg * 4 * kWords + mrow;  // row kg*4, column mrow; the rest are constant offsets
 #pragma unroll
     for (int nt = 0; nt < kQN / 16; ++nt) {
-      const uint32_t o = nt * 16 + mrow;
       v4i q[3][2];
 #pragma unroll
-      for (int b = 0; b < 3; ++b)
+      for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) q[b][kk] = *(const v4i*)(q_lds + (b * kQN + o) * kQRow + kk * 64 + kg * 16);
-      v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
+        for (int b = 0; b < 3; ++b)
+          q[b][kk] = *(const v4i*)(qb + (6 - nt) * 16 + kk * (3 * kSeqLen + 64) + b * kSeqLen);
+      // Six accumulators, one per limb product, so that no MFMA waits for
+      // more than the one of the previous K-step.
+      v4i acc0 = {0, 0, 0, 0}, acc1a = acc0, acc1b = acc0, acc2a = acc0, acc2b = acc0, acc2c = acc0;
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
         acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][kk], q[0][kk], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][kk], q[1][kk], acc1, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][kk], q[2][kk], acc2, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1][kk], q[0][kk], acc1, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1][kk], q[1][kk], acc2, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[2][kk], q[0][kk], acc2, 0, 0, 0);
+        acc1a = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][kk], q[1][kk], acc1a, 0, 0, 0);
+        acc2a = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][kk], q[2][kk], acc2a, 0, 0, 0);
+        acc1b = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1][kk], q[0][kk], acc1b, 0, 0, 0);
+        acc2b = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1][kk], q[1][kk], acc2b, 0, 0, 0);
+        acc2c = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[2][kk], q[0][kk], acc2c, 0, 0, 0);
       }
-      // D layout: lane holds rows kg*4 + i, column mrow of the tile.
+      const v4i acc1 = acc1a + acc1b, acc2 = acc2a + acc2b + acc2c;
+      // D layout: lane holds rows kg*4 + i, column nt*16 + mrow (< 97 unless
+      // nt = 6 and mrow > 0).
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t y = ((uint32_t)acc0[i] + ((uint32_t)acc1[i] << 8) + ((uint32_t)acc2[i] << 16)) & kMask;
-        if (o < 97) blk[(kg * 4 + i) * kWords + o] = y;
+        if ((nt < 6 || mrow == 0) && kg * 4 + i < rows) lp[i * kWords + nt * 16] = y;
       }
     }
     // c of the block's starts (Sec. 3.2): c_i jumped by j A delta.
-    if (lane < 16) blk[lane * kWords + 97] = c_jump(c_src, (uint32_t)(j * ad_mod % kMod));
-    wave_sync();
-    const uint64_t rows = n - s0 < 16 ? n - s0 : 16;  // s0 < n: checked above
-    uint32_t* dst = out + s0 * kWords;
-#pragma unroll
-    for (uint32_t it = 0; it < (16 * kWords + 63) / 64; ++it) {
-      const uint32_t w = lane + 64 * it;
-      if (w < rows * kWords) dst[w] = blk[w];
-    }
-    wave_sync();  // blk is reused by the next tile
+    if (lane < rows) dst[lane * kWords + 97] = c_jump(c_src, jm);
   }
 }
 
@@ -253,31 +297,42 @@ hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t 
   const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
   const unsigned __int128 kMax = ~(unsigned __int128)0;
   if (n < 2 || D > kMax / (n - 1)) return hipErrorInvalidValue;
-  // A ~ sqrt(97 n): A direct jumps plus 97 (B - 1) factor rows.
-  uint64_t A = (uint64_t)std::ceil(std::sqrt(97.0 * (double)n) / 16.0) * 16;
+  // A ~ sqrt(n): A direct jumps plus B - 1 factor jumps.
+  uint64_t A = (uint64_t)std::ceil(std::sqrt((double)n) / 16.0) * 16;
   if (A < 16) A = 16;
   if (2 * A > n) return hipErrorInvalidValue;
   const uint64_t B = (n + A - 1) / A;
-  const uint64_t njobs = A + kQK * (B - 1);
-  const uint64_t wg_tiles = 4 * kTilesPerWave;  // source tiles per workgroup
+  const uint64_t njobs = A + (B - 1);
+  // Tiles per wave: enough that the workgroups fit on the device at once,
+  // at most eight (a workgroup builds its factor's sequences once).
+  int dev = 0, cus = 256, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_family_gemm, 256, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 2;
+  const uint64_t slots = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)per_cu;  // resident workgroups
+  const uint64_t all_tiles = (B - 1) * (A / 16);
+  const uint64_t want = (all_tiles + 4 * slots - 1) / (4 * slots);
+  const uint32_t tpw = (uint32_t)(want < 1 ? 1 : (want > 8 ? 8 : want));
+  const uint64_t wg_tiles = 4 * (uint64_t)tpw;  // source tiles per workgroup
   const uint64_t gx = (A / 16 + wg_tiles - 1) / wg_tiles;
   if ((njobs + 7) / 8 > 0x7FFFFFFFull || gx > 0x7FFFFFFFull || B - 1 > 65535) return hipErrorInvalidValue;
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
   const unsigned __int128 AD = D * A;  // < n delta, and A <= n - 1
-  int8_t* Qg = nullptr;
-  hipError_t e = hipMallocAsync((void**)&Qg, kQBytes * (B - 1), st);
+  uint32_t* H = nullptr;
+  hipError_t e = hipMallocAsync((void**)&H, sizeof(uint32_t) * kHWords * (B - 1), st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_family_l1, dim3((unsigned)((njobs + 7) / 8)), dim3(256), 0, st, base, out, Qg, T, A, njobs,
+  hipLaunchKernelGGL(k_family_l1, dim3((unsigned)((njobs + 7) / 8)), dim3(256), 0, st, base, out, H, T, A, njobs,
                      (uint64_t)D, (uint64_t)(D >> 64), (uint64_t)AD, (uint64_t)(AD >> 64),
                      (uint32_t)(base == out ? 1 : 0));
   e = hipGetLastError();
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_family_gemm, dim3((unsigned)gx, (unsigned)(B - 1)), dim3(256), 0, st, out, Qg, A, n,
-                       (uint32_t)(AD % kMod));
+    hipLaunchKernelGGL(k_family_gemm, dim3((unsigned)gx, (unsigned)(B - 1)), dim3(256), 0, st, out, H, A, n,
+                       (uint32_t)(AD % kMod), tpw);
     e = hipGetLastError();
   }
-  const hipError_t f = hipFreeAsync(Qg, st);
+  const hipError_t f = hipFreeAsync(H, st);
   return e != hipSuccess ? e : f;
 }
 

@@ -51,9 +51,10 @@ int family_variant_for(uint64_t n) {
   if (g_forced[RANMAR_K_FAMILY] >= 0) return g_forced[RANMAR_K_FAMILY];
   auto it = g_table.find({RANMAR_K_FAMILY, ilog2(n), 0});
   if (it != g_table.end()) return it->second;
-  // Measured: the product form wins on 2^20 starts (0.25 ms against 0.39 ms)
-  // and loses on 65,536 (0.039 ms against 0.036 ms).
-  return n >= 131072 ? FAMILY_GEMM : FAMILY_RADIX;
+  // Measured: the product form wins on 65,536 starts (0.023 ms against
+  // 0.036 ms) and 2^20 (0.15 ms against 0.39 ms), and loses on 16,384
+  // (0.020 ms against 0.018 ms).
+  return n >= 32768 ? FAMILY_GEMM : FAMILY_RADIX;
 }
 
 int gen_variant_for(uint64_t n, uint64_t count) {
