@@ -172,8 +172,8 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     n, cnt = p["streams"], p["draws"]
     dev = torch.device("cuda:0")
     seed1 = torch.tensor([p["seed"]], dtype=torch.int32, device=dev)
-    base = torch.empty((1, 98), dtype=torch.int32, device=dev)
-    states = torch.empty((n, 98), dtype=torch.int32, device=dev)
+    base = [torch.empty((1, 98), dtype=torch.int32, device=dev) for _ in range(2)]
+    states = [torch.empty((n, 98), dtype=torch.int32, device=dev) for _ in range(2)]
     out_u = torch.empty((n, cnt), dtype=torch.int32, device=dev)
     out_f = torch.empty((n, cnt), dtype=torch.float32, device=dev)
     seeds_n = torch.full((n,), p["seed"], dtype=torch.int32, device=dev)
@@ -181,42 +181,76 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     lo, hi = synth.family_offsets(n, p["spacing"])
     offs = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
     tm = Timer(torch)
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream(device=dev)  # default priority
 
-    def step(timed):
-        a, b = tm.span("starts") if timed else (None, None)
+    def starts(b, timed=False):
+        a, e = tm.span("starts") if timed else (None, None)
         if a: a.record()
         if jump_mode == "family":
-            R.ranmar_seed_batch(seed1, out=base)
-            R.ranmar_jump_family(base, p["spacing"], n, out=states)
+            R.ranmar_seed_batch(seed1, out=base[b])
+            R.ranmar_jump_family(base[b], p["spacing"], n, out=states[b])
         else:
-            R.ranmar_seed_jump(seeds_n, offs, out=states)
-        if b: b.record()
+            R.ranmar_seed_jump(seeds_n, offs, out=states[b])
+        if e: e.record()
+
+    def gen(b, timed=False, f32_span=None):
         # Two passes (uint32, then float32 with the state written back): on
         # this shape they write faster than the one-pass RANMAR_U24_F32 form.
-        a, b = tm.span("gen_u24") if timed else (None, None)
+        a, e = tm.span("gen_u24") if timed else (None, None)
         if a: a.record()
-        R.ranmar_generate(states, cnt, R.RANMAR_U24, out=out_u)
-        if b: b.record()
-        a, b = tm.span("gen_f32") if timed else (None, None)
+        R.ranmar_generate(states[b], cnt, R.RANMAR_U24, out=out_u)
+        if e: e.record()
+        a, e = tm.span(f32_span or "gen_f32") if (timed or f32_span) else (None, None)
         if a: a.record()
-        R.ranmar_generate(states, cnt, R.RANMAR_F32, out=out_f, states_out=states)
-        if b: b.record()
+        R.ranmar_generate(states[b], cnt, R.RANMAR_F32, out=out_f, states_out=states[b])
+        if e: e.record()
 
-    for _ in range(warmup):
-        step(False)
+    # Pipelined steps: batch k+1's starts run on a second stream while batch
+    # k is generated (the start kernels fill few CUs; generation is bound by
+    # HBM writes).  Two state buffers; events order each buffer's reuse.
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    free = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def pipelined(k_steps, f32_span=None):
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            starts(0)
+        ready[0].record(side)
+        for k in range(k_steps):
+            b = k % 2
+            if k + 1 < k_steps:
+                if k >= 1:
+                    side.wait_event(free[1 - b])  # generation of batch k-1 read that buffer
+                with torch.cuda.stream(side):
+                    starts(1 - b)
+                ready[1 - b].record(side)
+            main.wait_event(ready[b])
+            gen(b, f32_span=f32_span)
+            free[b].record(main)
+
+    pipelined(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        step(False)
+    pipelined(steps, f32_span="gen_f32_timed")  # the roofline's launch time, in the timed steps
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    # Per-phase times from a second, instrumented pass: event records between
-    # the phases add idle time on the stream, so the timed steps carry none.
+    # The same steps one after another on one stream, for reference.
+    t0 = time.perf_counter()
     for _ in range(steps):
-        step(True)
+        starts(0)
+        gen(0)
+    torch.cuda.synchronize()
+    dt_serial = (time.perf_counter() - t0) / steps
+    # Per-phase times from a third, instrumented pass: event records between
+    # the phases add idle time on the stream, so the timed steps carry only
+    # the two around the float32 launch.
+    for _ in range(steps):
+        starts(0, True)
+        gen(0, True)
     torch.cuda.synchronize()
     draws = n * cnt
-    gen_ms = tm.mean_ms("gen_f32")
+    gen_ms = tm.mean_ms("gen_f32_timed")
     gen_bytes = 4 * draws + 2 * 392 * n          # float32 output + state read + state write-back
     res = {
         "metric": "draws/s", "value": draws / dt, "unit": "draws/s", "ms_per_step": dt * 1e3,
@@ -225,6 +259,8 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
                                    "), 4,096 draws each written as uint32 and as float32",
                                    "streams": n, "draws_per_stream": cnt, "jump": jump_mode},
         "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},
+        "pipelined": "batch k+1's starts on a second stream during batch k's generation",
+        "serial_ms_per_step": dt_serial * 1e3,
         "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": gen_bytes / (gen_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gen_bytes / (gen_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -424,7 +460,7 @@ def main():
             "warmup": a.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": res["dtype"], "data": "synthetic", "config": res["config"],
             "roofline": res["roofline"]}
-    for k in ("breakdown_ms", "output_write_GBps", "output_write_frac"):
+    for k in ("breakdown_ms", "pipelined", "serial_ms_per_step", "output_write_GBps", "output_write_frac"):
         if k in res:
             line[k] = res[k]
     if not a.no_extras and a.workload == "family65k":
