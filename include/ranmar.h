@@ -147,13 +147,29 @@ int ranmar_seed_jump(const int32_t *d_seeds, const ranmar_u128 *d_offsets, uint6
 
 /* Stream family (Sec. 1, block splitting): d_out[k] = f^(k*delta)(*d_base)
  * for k < n, i.e. unit k starts at state s_{k*delta}.  Computed on the GPU
- * by prefix doubling with the exact jump: the starts of units [2^b, 2^(b+1))
- * are those of [0, 2^b) jumped by 2^b*delta; bit-identical to n separate
- * jumps.  The exponent k*delta is used exactly (it may exceed 2^128, unlike the
- * J of ranmar_jump).  d_base: 1 record (may lie inside d_out only as
- * d_out[0]). */
+ * and bit-identical to n separate jumps: from 32,768 starts (by default) as
+ * int8 matrix-core products of ~sqrt(n) direct starts with ~sqrt(n) shared
+ * factor matrices (the jump is the matrix P(A_c), Sec. 3.1), otherwise in
+ * radix-256 rounds of table factors.  The exponent k*delta is used exactly
+ * (it may exceed 2^128, unlike the J of ranmar_jump; then by prefix doubling
+ * of polynomials).  d_base: 1 record (may lie inside d_out only as d_out[0]).
+ * Scratch: the product form takes (n / ~sqrt(n)) * 784 bytes of
+ * stream-ordered device memory for the duration of the call. */
 int ranmar_jump_family(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n,
                        ranmar_state *d_out, void *stream);
+
+/* Per-rank streams of one seed (Sec. 1, block splitting, as a parallel code
+ * uses it: rank p draws the block that starts at s_{p*J}): d_out[k] = state
+ * of `seed` at offset (first_rank + k) * J + discard_first, for k < n_ranks.
+ * discard_first = 1 drops one draw after seeding before the split, for codes
+ * whose generator consumes one uniform when it is constructed; the paper
+ * describes no such warm-up, and 0 is its own convention.  seed must be in
+ * [1, 9e8], discard_first 0 or 1, and first_rank * J + discard_first below
+ * 2^128, else RANMAR_EINVAL (nothing launched).  Seeding and every jump run on
+ * the GPU (one seed-and-jump record, then ranmar_jump_family around it).
+ * d_out: n_ranks records, 4-byte aligned. */
+int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64_t n_ranks, int discard_first,
+                        ranmar_state *d_out, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* a5: generation (Algorithm 2)                                              */

@@ -92,6 +92,7 @@ _SIGS = {
     "ranmar_jump": (_int, [_vp, _vp, _u64, _vp]),
     "ranmar_seed_jump": (_int, [_vp, _vp, _u64, _vp, _vp]),
     "ranmar_jump_family": (_int, [_vp, ranmar_u128, _u64, _vp, _vp]),
+    "ranmar_rank_streams": (_int, [_i32, ranmar_u128, _u64, _u64, _int, _vp, _vp]),
     "ranmar_generate": (_int, [_vp, _vp, _u64, _u64, _int, _vp, _u64, _vp]),
     "ranmar_batch_create": (_int, [_u64, _u64, _u64, ctypes.POINTER(_vp)]),
     "ranmar_batch_run": (_int, [_vp, ctypes.POINTER(ranmar_request), _u64, _vp]),
@@ -227,6 +228,15 @@ def ranmar_jump_family(base, delta: int, n: int, out=None, stream=None):
         out = new_states(n, base.device)
     _check(lib().ranmar_jump_family(_ptr(base), _u128(delta), n, _ptr(out), _stream(stream)),
            "ranmar_jump_family")
+    return out
+
+
+def ranmar_rank_streams(seed: int, J: int, first_rank: int, n_ranks: int, discard_first: bool = False, out=None,
+                        device=None, stream=None):
+    if out is None:
+        out = new_states(n_ranks, device if device is not None else torch.device("cuda"))
+    _check(lib().ranmar_rank_streams(int(seed), _u128(J), int(first_rank), int(n_ranks), int(bool(discard_first)),
+                                     _ptr(out), _stream(stream)), "ranmar_rank_streams")
     return out
 
 

@@ -166,6 +166,25 @@ int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n
                                           (hipStream_t)stream));
 }
 
+int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64_t n_ranks, int discard_first,
+                        ranmar_state* d_out, void* stream) {
+  if (n_ranks == 0) return RANMAR_OK;
+  if (!d_out || !aligned(d_out, 4) || seed < 1 || seed > 900000000 || (discard_first != 0 && discard_first != 1))
+    return RANMAR_EINVAL;
+  // Offset of the first rank, first_rank * J + discard_first, must fit in 128 bits.
+  const unsigned __int128 Jv = ((unsigned __int128)J.hi << 64) | J.lo;
+  const unsigned __int128 kMax = ~(unsigned __int128)0;
+  if (first_rank && Jv > (kMax - (unsigned)discard_first) / first_rank) return RANMAR_EINVAL;
+  const unsigned __int128 E0 = Jv * first_rank + (unsigned)discard_first;
+  int rc = ensure_init();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_seed_jump_one((uint32_t*)d_out, seed, ranmar_u128{(uint64_t)E0, (uint64_t)(E0 >> 64)}, st);
+  if (e == hipSuccess && n_ranks > 1)  // the rest as a family around d_out[0]
+    e = launch_family_variant(family_variant_for(n_ranks), (const uint32_t*)d_out, J, n_ranks, (uint32_t*)d_out, st);
+  return hip_status(e);
+}
+
 int ranmar_generate(const ranmar_state* d_in, ranmar_state* d_state_out, uint64_t n, uint64_t count, int fmt,
                     void* d_out, uint64_t ld, void* stream) {
   if (n == 0) return RANMAR_OK;

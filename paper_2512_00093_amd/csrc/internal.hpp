@@ -23,6 +23,8 @@ hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar
 const uint32_t* window_table();    // T[w][d] = t^(d 2^(8w)) mod phi, per device
 const uint32_t* window16_table();  // T[w][d] = t^(d 2^(16w)) mod phi, per device (nullptr if it cannot be built)
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
+// One record: the state of a (checked) seed at offset E, values by argument.
+hipError_t launch_seed_jump_one(uint32_t* out, int32_t seed, ranmar_u128 E, hipStream_t st);
 // Family by table factors; hipErrorInvalidValue if an exponent needs > 128 bits.
 hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
 // Family as a matrix product on the matrix cores; hipErrorInvalidValue if
@@ -30,7 +32,7 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
 hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
 enum FamilyVariant : int {
   FAMILY_RADIX = 0,  // radix-256 rounds, one table application per start (VALU)
-  FAMILY_GEMM = 1,   // ~sqrt(97 n) direct starts, the rest as int8 MFMA products
+  FAMILY_GEMM = 1,   // ~sqrt(n) direct starts and factors, the rest as int8 MFMA products
   FAMILY_NUM_VARIANTS = 2
 };
 int family_variant_for(uint64_t n);

@@ -227,6 +227,36 @@ __global__ __launch_bounds__(256) void k_family_radix_grp(uint32_t* __restrict__
   }
 }
 
+// One request with its values passed by argument: the state of `seed` at
+// offset E (Algorithm 3, then the windowed jump with c by its closed form).
+// One half-wave; the caller has checked the seed.
+__global__ __launch_bounds__(32) void k_seed_jump_one(uint32_t* __restrict__ out, int32_t seed, uint64_t e_lo,
+                                                      uint64_t e_hi, const uint32_t* __restrict__ T) {
+  __shared__ uint32_t lds[kHalfWords];
+  const uint32_t l = threadIdx.x & 31u;
+  uint32_t* X = lds;
+  uint32_t* B = X + 193;
+  seed_half(seed, X, l);
+  wave_sync();
+  const uint32_t c = X[97];
+  const uint32_t j0 = (uint32_t)e_lo, j1 = (uint32_t)(e_lo >> 32), j2 = (uint32_t)e_hi, j3 = (uint32_t)(e_hi >> 32);
+  jump_half(X, B, T, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
+  out[l] = X[l];
+  out[l + 32] = X[l + 32];
+  out[l + 64] = X[l + 64];
+  if (l == 0) {
+    out[96] = X[96];
+    out[97] = c_jump(c, u128_mod_m(j0, j1, j2, j3));
+  }
+}
+
+hipError_t launch_seed_jump_one(uint32_t* out, int32_t seed, ranmar_u128 E, hipStream_t st) {
+  const uint32_t* T = window_table();
+  if (!T) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(k_seed_jump_one, dim3(1), dim3(32), 0, st, out, seed, E.lo, E.hi, T);
+  return hipGetLastError();
+}
+
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_seed_coop, dim3((unsigned)((n + 7) / 8)), dim3(256), 0, st, seeds, n, out);

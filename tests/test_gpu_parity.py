@@ -284,6 +284,45 @@ def test_family_equals_independent_jumps(orc, n, delta):
         assert np.array_equal(u32(fam[k]), orc.jump(base, k * delta)), k
 
 
+# --- per-rank streams -------------------------------------------------------------
+@pytest.mark.parametrize("seed,J,first,n,discard", [
+    (4711, 1 << 40, 0, 1, 0), (4711, 1 << 40, 0, 7, 1), (12345, (1 << 100) + 77, 3, 130, 0),
+    (900000000, 999_999, 1000, 5000, 1), (1, 1 << 60, 0, 40_000, 0)])
+def test_rank_streams(orc, seed, J, first, n, discard):
+    """Rank first+k starts at offset (first+k) J (+1 with the warm-up discard);
+    the last case takes the matrix-core family path."""
+    say(f"rank_streams seed={seed} J={J} first={first} n={n} discard={discard}")
+    got = R.ranmar_rank_streams(seed, J, first, n, discard_first=bool(discard), device=dev())
+    torch.cuda.synchronize()
+    base = orc.state_from_seed(seed)
+    for k in sorted({0, 1 % n, n // 2, n - 1}):
+        assert np.array_equal(u32(got[k]), orc.jump(base, (first + k) * J + discard)), k
+    if n <= 200:
+        ind = R.ranmar_seed_jump(seeds_t([seed] * n), jumps_t([(first + k) * J + discard for k in range(n)]))
+        assert torch.equal(got, ind)
+
+
+def test_rank_streams_discard_is_one_draw(orc):
+    """With the discard, rank 0's first draw is the undiscarded stream's second."""
+    say("rank_streams discard = one draw")
+    a = R.ranmar_rank_streams(4711, 1 << 30, 0, 2, discard_first=False, device=dev())
+    b = R.ranmar_rank_streams(4711, 1 << 30, 0, 2, discard_first=True, device=dev())
+    da = u32(R.ranmar_generate(a, 8, 0))
+    db = u32(R.ranmar_generate(b, 7, 0))
+    assert np.array_equal(da[0, 1:], db[0]) and np.array_equal(da[1, 1:], db[1])
+
+
+def test_rank_streams_rejects_bad_arguments():
+    """Bad seeds, an offset beyond 2^128 and a discard flag other than 0/1
+    are refused on the host (RANMAR_EINVAL, nothing launched)."""
+    say("rank_streams invalid arguments")
+    out = torch.empty((4, 98), dtype=torch.int32, device=dev())
+    st = torch.cuda.current_stream().cuda_stream
+    for seed, J, first, discard in ((0, 1, 0, 0), (900000001, 1, 0, 0), (5, 1 << 127, 2, 0), (5, 1, 0, 2)):
+        rc = R.lib().ranmar_rank_streams(seed, R._binding._u128(J), first, 4, discard, out.data_ptr(), st)
+        assert rc == -1, (seed, J, first, discard)
+
+
 # --- configurations at full size -------------------------------------------------
 def test_config1_single_stream(orc):
     p = synth.SINGLE_STREAM
