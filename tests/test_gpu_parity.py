@@ -220,13 +220,16 @@ def test_generate_both_formats(orc, n, count, ld):
 
 @pytest.mark.parametrize("variant", [0, 1], ids=["radix_valu", "product_mfma"])
 @pytest.mark.parametrize("n,delta", [(8192, 1 << 40), (9999, (1 << 40) + 12345), (70_001, 1 << 40),
-                                     (5000, (1 << 115) + 12345), (300, 1 << 40)])
+                                     (5000, (1 << 115) + 12345), (300, 1 << 40), (33, (1 << 40) + 5),
+                                     (31, 12345), (32_768, 1 << 40), (131_071, 3)])
 def test_family_variants(orc, variant, n, delta):
     """Both family variants against independent jumps: radix rounds on the
-    VALU, and the matrix product (about sqrt(97 n) direct starts, the rest as
-    int8 MFMA products with limb splitting).  The product form also covers a
-    ragged last block (70,001) and 15-digit factors (2^115 spacing); n = 300 is
-    below its minimum and falls back."""
+    VALU, and the matrix product (about sqrt(n) direct starts and as many
+    shared factors, the rest as int8 MFMA products of signed digits).  The
+    product form covers ragged last blocks (70,001; 131,071; 33, whose last
+    factor holds one start), 15-digit factors (2^115 spacing) and the
+    default switch-over size (32,768); n = 31 is below its minimum (two
+    blocks of 16) and falls back to the radix rounds."""
     base = orc.state_from_seed(4711)
     R.ranmar_tune_set(R.RANMAR_K_FAMILY, variant)
     try:
@@ -240,14 +243,19 @@ def test_family_variants(orc, variant, n, delta):
         assert np.array_equal(u32(fam[k]), orc.jump(base, k * delta)), k
 
 
-def test_family_in_place(orc):
+@pytest.mark.parametrize("variant,n", [(0, 600), (1, 600), (1, 40_000)])
+def test_family_in_place(orc, variant, n):
     """d_base == d_out: the family is built around its own first record."""
-    delta, n = (1 << 40) + 7, 600
+    delta = (1 << 40) + 7
     base = orc.state_from_seed(31)
     fam = torch.zeros((n, 98), dtype=torch.int32, device=dev())
     fam[0] = states_t(base)[0]
-    say("jump_family in place n=600")
-    R.ranmar_jump_family(fam[:1], delta, n, out=fam)
+    say(f"jump_family in place variant={variant} n={n}")
+    R.ranmar_tune_set(R.RANMAR_K_FAMILY, variant)
+    try:
+        R.ranmar_jump_family(fam[:1], delta, n, out=fam)
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_FAMILY, -1)
     ind = R.ranmar_seed_jump(seeds_t([31] * n), jumps_t([k * delta for k in range(n)]))
     assert torch.equal(fam, ind)
 
