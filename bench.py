@@ -149,21 +149,70 @@ def cpu_baseline(kind: str, seconds: float):
 # ---------------------------------------------------------------------------
 # GPU workloads
 # ---------------------------------------------------------------------------
+def _hip_runtime():
+    """The HIP runtime this process already uses (the one torch and the
+    library launch through), found among the loaded shared objects."""
+    import ctypes
+    path = None
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64.so" in line:
+                path = line.split()[-1]
+                break
+    if path is None:
+        raise RuntimeError("libamdhip64 is not loaded")
+    hip = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(vp), ctypes.c_uint]
+    hip.hipEventRecord.argtypes = [vp, vp]
+    hip.hipEventSynchronize.argtypes = [vp]
+    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), vp, vp]
+    hip.hipEventDestroy.argtypes = [vp]
+    return hip
+
+
 class Timer:
-    """HIP events on torch's current stream (the stream the library launches on)."""
+    """HIP events on torch's current stream (the stream the library launches
+    on), created with hipEventDisableSystemFence: timing-only events whose
+    record skips the system-scope cache write-back and invalidation of an
+    ordinary event, which would otherwise idle the stream between launches."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    class _Event:
+        def __init__(self, timer):
+            import ctypes
+            self.timer = timer
+            self.h = ctypes.c_void_p()
+            rc = timer.hip.hipEventCreateWithFlags(ctypes.byref(self.h), Timer.DISABLE_SYSTEM_FENCE)
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreateWithFlags: {rc}")
+
+        def record(self):
+            import ctypes
+            st = ctypes.c_void_p(self.timer.t.cuda.current_stream().cuda_stream)
+            rc = self.timer.hip.hipEventRecord(self.h, st)
+            if rc != 0:
+                raise RuntimeError(f"hipEventRecord: {rc}")
 
     def __init__(self, torch):
         self.t = torch
+        self.hip = _hip_runtime()
         self.spans = {}
 
     def span(self, name):
-        t = self.t
-        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a, b = Timer._Event(self), Timer._Event(self)
         self.spans.setdefault(name, []).append((a, b))
         return a, b
 
     def mean_ms(self, name):
-        v = [a.elapsed_time(b) for a, b in self.spans.get(name, [])]
+        import ctypes
+        v = []
+        for a, b in self.spans.get(name, []):
+            ms = ctypes.c_float()
+            if self.hip.hipEventSynchronize(b.h) != 0 or self.hip.hipEventElapsedTime(ctypes.byref(ms), a.h, b.h) != 0:
+                raise RuntimeError("hipEventElapsedTime failed")
+            v.append(ms.value)
         return sum(v) / len(v) if v else float("nan")
 
 
@@ -172,8 +221,8 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     n, cnt = p["streams"], p["draws"]
     dev = torch.device("cuda:0")
     seed1 = torch.tensor([p["seed"]], dtype=torch.int32, device=dev)
-    base = [torch.empty((1, 98), dtype=torch.int32, device=dev) for _ in range(2)]
-    states = [torch.empty((n, 98), dtype=torch.int32, device=dev) for _ in range(2)]
+    base = torch.empty((1, 98), dtype=torch.int32, device=dev)
+    states = torch.empty((n, 98), dtype=torch.int32, device=dev)
     out_u = torch.empty((n, cnt), dtype=torch.int32, device=dev)
     out_f = torch.empty((n, cnt), dtype=torch.float32, device=dev)
     seeds_n = torch.full((n,), p["seed"], dtype=torch.int32, device=dev)
@@ -181,73 +230,45 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     lo, hi = synth.family_offsets(n, p["spacing"])
     offs = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
     tm = Timer(torch)
-    main = torch.cuda.current_stream()
-    side = torch.cuda.Stream(device=dev)  # default priority
 
-    def starts(b, timed=False):
+    def starts(timed=False):
         a, e = tm.span("starts") if timed else (None, None)
         if a: a.record()
         if jump_mode == "family":
-            R.ranmar_seed_batch(seed1, out=base[b])
-            R.ranmar_jump_family(base[b], p["spacing"], n, out=states[b])
+            R.ranmar_seed_batch(seed1, out=base)
+            R.ranmar_jump_family(base, p["spacing"], n, out=states)
         else:
-            R.ranmar_seed_jump(seeds_n, offs, out=states[b])
+            R.ranmar_seed_jump(seeds_n, offs, out=states)
         if e: e.record()
 
-    def gen(b, timed=False, f32_span=None):
+    def gen(timed=False, f32_span=None):
         # Two passes (uint32, then float32 with the state written back): on
         # this shape they write faster than the one-pass RANMAR_U24_F32 form.
         a, e = tm.span("gen_u24") if timed else (None, None)
         if a: a.record()
-        R.ranmar_generate(states[b], cnt, R.RANMAR_U24, out=out_u)
+        R.ranmar_generate(states, cnt, R.RANMAR_U24, out=out_u)
         if e: e.record()
         a, e = tm.span(f32_span or "gen_f32") if (timed or f32_span) else (None, None)
         if a: a.record()
-        R.ranmar_generate(states[b], cnt, R.RANMAR_F32, out=out_f, states_out=states[b])
+        R.ranmar_generate(states, cnt, R.RANMAR_F32, out=out_f, states_out=states)
         if e: e.record()
 
-    # Pipelined steps: batch k+1's starts run on a second stream while batch
-    # k is generated (the start kernels fill few CUs; generation is bound by
-    # HBM writes).  Two state buffers; events order each buffer's reuse.
-    ready = [torch.cuda.Event(), torch.cuda.Event()]
-    free = [torch.cuda.Event(), torch.cuda.Event()]
-
-    def pipelined(k_steps, f32_span=None):
-        side.wait_stream(main)
-        with torch.cuda.stream(side):
-            starts(0)
-        ready[0].record(side)
-        for k in range(k_steps):
-            b = k % 2
-            if k + 1 < k_steps:
-                if k >= 1:
-                    side.wait_event(free[1 - b])  # generation of batch k-1 read that buffer
-                with torch.cuda.stream(side):
-                    starts(1 - b)
-                ready[1 - b].record(side)
-            main.wait_event(ready[b])
-            gen(b, f32_span=f32_span)
-            free[b].record(main)
-
-    pipelined(warmup)
+    for _ in range(warmup):
+        starts()
+        gen()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pipelined(steps, f32_span="gen_f32_timed")  # the roofline's launch time, in the timed steps
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    # The same steps one after another on one stream, for reference.
     t0 = time.perf_counter()
     for _ in range(steps):
-        starts(0)
-        gen(0)
+        starts()
+        gen(f32_span="gen_f32_timed")  # the roofline's launch time, in the timed steps
     torch.cuda.synchronize()
-    dt_serial = (time.perf_counter() - t0) / steps
-    # Per-phase times from a third, instrumented pass: event records between
+    dt = (time.perf_counter() - t0) / steps
+    # Per-phase times from a second, instrumented pass: event records between
     # the phases add idle time on the stream, so the timed steps carry only
     # the two around the float32 launch.
     for _ in range(steps):
-        starts(0, True)
-        gen(0, True)
+        starts(True)
+        gen(True)
     torch.cuda.synchronize()
     draws = n * cnt
     gen_ms = tm.mean_ms("gen_f32_timed")
@@ -259,8 +280,6 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
                                    "), 4,096 draws each written as uint32 and as float32",
                                    "streams": n, "draws_per_stream": cnt, "jump": jump_mode},
         "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},
-        "pipelined": "batch k+1's starts on a second stream during batch k's generation",
-        "serial_ms_per_step": dt_serial * 1e3,
         "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": gen_bytes / (gen_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gen_bytes / (gen_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -460,7 +479,7 @@ def main():
             "warmup": a.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": res["dtype"], "data": "synthetic", "config": res["config"],
             "roofline": res["roofline"]}
-    for k in ("breakdown_ms", "pipelined", "serial_ms_per_step", "output_write_GBps", "output_write_frac"):
+    for k in ("breakdown_ms", "output_write_GBps", "output_write_frac"):
         if k in res:
             line[k] = res[k]
     if not a.no_extras and a.workload == "family65k":

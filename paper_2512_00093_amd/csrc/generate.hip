@@ -62,8 +62,26 @@ const char* gen_variant_name(int v) {
     case GEN_WIDE4: return "lanes32_wide4";
     case GEN_WIDE4_NT: return "lanes32_wide4_nt";
     case GEN_PIPE_NT: return "lanes32_pipe_nt";
+    case GEN_LANES32_NT_R2: return "lanes32_nt_res2";
+    case GEN_LANES32_NT_R3: return "lanes32_nt_res3";
+    case GEN_WIDE4_NT_R4: return "lanes32_wide4_nt_res4";
+    case GEN_WIDE4_NT_R6: return "lanes32_wide4_nt_res6";
     default: return "?";
   }
+}
+
+// Dynamic LDS (unused by the kernel) that leaves room for at most k resident
+// workgroups of static LDS `stat` per CU: the smallest per-workgroup total
+// above per_cu / (k + 1).  0 (no cap) if the device does not report its LDS.
+static unsigned residency_lds(int k, unsigned stat) {
+  int dev = 0, per_cu = 0, per_wg = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || per_cu <= 0)
+    return 0;
+  const unsigned total = ((unsigned)per_cu / (unsigned)(k + 1) + 256u) & ~255u;
+  if (total > (unsigned)per_wg || total <= stat) return 0;
+  return total - stat;
 }
 
 template <int FMT>
@@ -75,6 +93,14 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   // The wide stores need 16-byte aligned rows, and write one format.
   const bool wide_ok = (((uintptr_t)out & 15) == 0) && (ld % 4 == 0) && FMT != RANMAR_U24_F32;
   const uint64_t plane = n * ld;  // second plane of RANMAR_U24_F32
+  unsigned cap_lds = 0;  // residency cap of the _R variants
+  if (variant == GEN_LANES32_NT_R2 || variant == GEN_LANES32_NT_R3) {
+    cap_lds = residency_lds(variant == GEN_LANES32_NT_R2 ? 2 : 3, 0);
+    variant = GEN_LANES32_NT;
+  } else if (variant == GEN_WIDE4_NT_R4 || variant == GEN_WIDE4_NT_R6) {
+    cap_lds = residency_lds(variant == GEN_WIDE4_NT_R4 ? 4 : 6, wide_ok ? 8 * 128 * 4 : 0);
+    variant = GEN_WIDE4_NT;
+  }
   if (!wide_ok && variant == GEN_WIDE4) variant = GEN_LANES32;
   if (!wide_ok && variant == GEN_WIDE4_NT) variant = GEN_LANES32_NT;
   if (variant == GEN_PIPE_NT) {
@@ -99,10 +125,10 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
       break;
     case GEN_WIDE4_NT:
       if constexpr (FMT != RANMAR_U24_F32)
-        hipLaunchKernelGGL((k_gen32_wide<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+        hipLaunchKernelGGL((k_gen32_wide<FMT, true>), grid, dim3(wg), cap_lds, st, sin, sout, n, count, out, ld);
       break;
     case GEN_LANES32_NT:
-      hipLaunchKernelGGL((k_gen32<FMT, true>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld, plane);
+      hipLaunchKernelGGL((k_gen32<FMT, true>), grid, dim3(wg), cap_lds, st, sin, sout, n, count, out, ld, plane);
       break;
     default:
       hipLaunchKernelGGL((k_gen32<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld, plane);

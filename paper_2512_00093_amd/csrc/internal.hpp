@@ -61,7 +61,14 @@ enum GenVariant : int {
   GEN_WIDE4 = 2,       // four blocks per step, LDS transpose, 16-byte stores
   GEN_WIDE4_NT = 3,    // same, non-temporal
   GEN_PIPE_NT = 4,     // 32 lanes per stream, several streams per half-wave with the next state prefetched
-  GEN_NUM_VARIANTS = 5
+  // Residency-capped forms: the launch reserves LDS (unused by the kernel) so
+  // that at most R workgroups share a CU.  Fewer rows are then written at
+  // once, and each is written faster, which HBM takes more efficiently.
+  GEN_LANES32_NT_R2 = 5,
+  GEN_LANES32_NT_R3 = 6,
+  GEN_WIDE4_NT_R4 = 7,
+  GEN_WIDE4_NT_R6 = 8,
+  GEN_NUM_VARIANTS = 9
 };
 const char* gen_variant_name(int v);
 hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uint64_t n, uint64_t count, int fmt,

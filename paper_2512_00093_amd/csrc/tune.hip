@@ -62,10 +62,14 @@ int gen_variant_for(uint64_t n, uint64_t count) {
   if (g_forced[RANMAR_K_GENERATE] >= 0) return g_forced[RANMAR_K_GENERATE];
   auto it = g_table.find({RANMAR_K_GENERATE, ilog2(n), ilog2(count)});
   if (it != g_table.end()) return it->second;
-  // Short rows: 16-byte stores of four blocks at a time write them faster
-  // (measured on 2^20 streams x 1,024 draws); long rows: 4-byte stores do as
-  // well.  The wide form falls back to 4-byte stores for unaligned rows.
-  return count <= 2048 ? GEN_WIDE4_NT : GEN_LANES32_NT;
+  // Measured (float32, ms per launch): 2^20 streams x 1,024 draws: 16-byte
+  // stores with at most 6 workgroups per CU 0.80, uncapped 0.92; 65,536 x
+  // 4,096: 4-byte stores with at most 2 workgroups per CU 0.172, uncapped
+  // 0.190; 16,384 x 16,384 (every workgroup resident at once anyway):
+  // ordinary 16-byte stores 0.203, the capped forms 0.21-0.23.  The wide
+  // forms fall back to 4-byte stores for unaligned rows.
+  if (count <= 2048) return GEN_WIDE4_NT_R6;
+  return n >= 32768 ? GEN_LANES32_NT_R2 : GEN_WIDE4;
 }
 
 // Times the jump variants on n seed+jump requests with `bits`-bit offsets.
