@@ -228,7 +228,8 @@ int ranmar_batch_run(ranmar_batch *b, const ranmar_request *reqs, uint64_t n, vo
  * work only, same errors as ranmar_batch_run); ranmar_batch_launch launches
  * the graph for the prepared batch on `stream` (RANMAR_EINVAL if nothing is
  * prepared).  prepare waits for the batch's previous launch to have read the
- * staging buffer. */
+ * staging buffer; from 65,536 requests it validates and stages them on up to
+ * eight host threads (it returns after all have finished). */
 int ranmar_batch_prepare(ranmar_batch *b, const ranmar_request *reqs, uint64_t n);
 int ranmar_batch_launch(ranmar_batch *b, void *stream);
 

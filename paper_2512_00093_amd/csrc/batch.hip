@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -74,6 +75,28 @@ static int check_request(const ranmar_request& q, uint32_t L, uint64_t* nq) {
   if (q.d_state && ((uintptr_t)q.d_state & 3)) return RANMAR_EINVAL;
   *nq = (q.count + L - 1) / L;
   return RANMAR_OK;
+}
+
+// body(lo, hi, part) over a split of [0, n) into parts: on up to eight
+// threads for large n, else on the calling thread.  The split depends only on
+// n, so two calls with the same n see the same parts.
+template <class F>
+static void parallel_parts(uint64_t n, uint32_t parts, F&& body) {
+  if (parts <= 1) {
+    body(0, n, 0u);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(parts - 1);
+  for (uint32_t t = 1; t < parts; ++t) th.emplace_back([&, t] { body(n * t / parts, n * (t + 1) / parts, t); });
+  body(0, n / parts, 0u);
+  for (auto& x : th) x.join();
+}
+
+static uint32_t host_parts(uint64_t n) {
+  if (n < 65536) return 1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  return std::max(1u, std::min(8u, hw ? hw : 1u));
 }
 
 static BReq to_breq(const ranmar_request& q) {
@@ -218,13 +241,30 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   b->prepared_bytes = 0;
   if (n > b->max_req) return RANMAR_ENOMEM;
   if (n == 0) return RANMAR_OK;
+  // Validation and counts, in parts (large batches on several threads).
+  const uint32_t parts = host_parts(n);
+  std::vector<uint64_t> p_total(parts, 0), p_jo(parts, 0);
+  std::vector<int> p_rc(parts, RANMAR_OK);
+  parallel_parts(n, parts, [&](uint64_t lo, uint64_t hi, uint32_t t) {
+    uint64_t tot = 0, jo = 0;
+    for (uint64_t r = lo; r < hi; ++r) {
+      uint64_t nq = 0;
+      const int rc = check_request(reqs[r], b->L, &nq);
+      if (rc) {
+        p_rc[t] = rc;
+        return;
+      }
+      tot += nq;
+      jo += nq == 0;
+    }
+    p_total[t] = tot;
+    p_jo[t] = jo;
+  });
   uint64_t total = 0, n_jo = 0;  // chunks; requests without draws
-  for (uint64_t r = 0; r < n; ++r) {
-    uint64_t nq = 0;
-    int rc = check_request(reqs[r], b->L, &nq);
-    if (rc) return rc;
-    total += nq;
-    n_jo += nq == 0;
+  for (uint32_t t = 0; t < parts; ++t) {
+    if (p_rc[t]) return p_rc[t];
+    total += p_total[t];
+    n_jo += p_jo[t];
   }
   if (total > b->max_chunks) return RANMAR_ENOMEM;
   // Many requests without draws: jump them with 16-bit windows (the 203 MB
@@ -300,17 +340,13 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   // requests without draws (an equal split, in order).
   const bool octets = b->B.wtab16 != nullptr;
   const uint32_t wpb_max = std::max<uint32_t>(1, b->workers_max / nb);
-  uint64_t ns = 0, ti = 0, k0 = 0, jr = 0;
+  uint64_t ns = 0, ti = 0, k0 = 0;
   uint32_t wpb = 1;
   for (uint32_t i = 0; i < nb; ++i) {
     BBin& bn = bins[i];
     bn.s0 = (uint32_t)ns;
     for (uint32_t k = 0; k < nsc[i]; ++k) sl[ns++] = tmp[ti++];
-    const uint64_t njo = n_jo * (i + 1) / nb - n_jo * i / nb;
-    for (uint64_t k = 0; k < njo; ++k) {
-      while (reqs[jr].count != 0) ++jr;
-      sl[ns++] = to_breq(reqs[jr++]);
-    }
+    ns += n_jo * (i + 1) / nb - n_jo * i / nb;  // filled below
     bn.ns = (uint32_t)(ns - bn.s0);
     bn.nsc = octets ? nsc[i] : bn.ns;  // without the 16-bit table, pair items take every slice
     bn.k0 = (uint32_t)k0;
@@ -325,6 +361,26 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     bn.n_qi = (n_jq + bn.gq - 1) / bn.gq;
     // Workgroups per bin: as many as the fullest bin has items, within the device.
     wpb = std::max(wpb, std::min(wpb_max, bn.n_ju + bn.n_cg + bn.n_qi));
+  }
+  // Requests without draws, k-th of them (in order) into bin i with
+  // n_jo i / nb <= k < n_jo (i + 1) / nb, after that bin's other slices.
+  if (n_jo) {
+    std::vector<uint64_t> jo_before(parts, 0);
+    for (uint32_t t = 1; t < parts; ++t) jo_before[t] = jo_before[t - 1] + p_jo[t - 1];
+    parallel_parts(n, parts, [&](uint64_t lo, uint64_t hi, uint32_t t) {
+      uint64_t k = jo_before[t];
+      if (k >= n_jo) return;
+      auto start = [&](uint32_t i) { return n_jo * i / nb; };
+      uint32_t i = (uint32_t)std::min<uint64_t>(nb - 1, k * nb / n_jo);
+      while (i > 0 && start(i) > k) --i;
+      while (i + 1 < nb && start(i + 1) <= k) ++i;
+      for (uint64_t r = lo; r < hi; ++r) {
+        if (reqs[r].count != 0) continue;
+        while (i + 1 < nb && start(i + 1) <= k) ++i;
+        sl[bins[i].s0 + nsc[i] + (k - start(i))] = to_breq(reqs[r]);
+        ++k;
+      }
+    });
   }
   h->n_bins = nb;
   h->n_workers = nb * wpb;

@@ -346,3 +346,32 @@ def test_batch_jump_octets_and_pairs(orc):
     ref = orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx]))
     assert np.array_equal(w[idx], ref)
     _check(orc, drawn)
+
+
+def test_batch_large_prepare_in_parts(orc):
+    """From 65,536 requests the host validates and places them on several
+    threads; requests with draws scattered among 100,000 jumps keep their
+    order and bits."""
+    n = 100_000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=29)
+    states = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+    items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                  state=states[i]) for i in range(n)]
+    drawn = _alloc(_mixed_requests(4, 61, max_count=50_000, with_zero=False))
+    mixed = [drawn[0]] + items[:30_000] + [drawn[1]] + items[30_000:70_001] + [drawn[2]] + items[70_001:] + [drawn[3]]
+    b = R.ranmar_batch_create(len(mixed), 64)
+    try:
+        for rep in range(2):
+            states.zero_()
+            say(f"batch prepare in parts n={len(mixed)} rep={rep}")
+            R.ranmar_batch_run(b, R.make_requests(mixed))
+            torch.cuda.synchronize()
+            w = u32(states)
+            direct = u32(R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                            torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev())))
+            assert np.array_equal(w, direct)
+    finally:
+        R.ranmar_batch_destroy(b)
+    idx = [0, 29_999, 30_000, 70_000, 70_001, n - 1]
+    assert np.array_equal(w[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
+    _check(orc, drawn)
