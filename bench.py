@@ -220,8 +220,6 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     p = synth.FAMILY_65K
     n, cnt = p["streams"], p["draws"]
     dev = torch.device("cuda:0")
-    seed1 = torch.tensor([p["seed"]], dtype=torch.int32, device=dev)
-    base = torch.empty((1, 98), dtype=torch.int32, device=dev)
     states = torch.empty((n, 98), dtype=torch.int32, device=dev)
     out_u = torch.empty((n, cnt), dtype=torch.int32, device=dev)
     out_f = torch.empty((n, cnt), dtype=torch.float32, device=dev)
@@ -235,8 +233,7 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
         a, e = tm.span("starts") if timed else (None, None)
         if a: a.record()
         if jump_mode == "family":
-            R.ranmar_seed_batch(seed1, out=base)
-            R.ranmar_jump_family(base, p["spacing"], n, out=states)
+            R.ranmar_rank_streams(p["seed"], p["spacing"], 0, n, out=states)
         else:
             R.ranmar_seed_jump(seeds_n, offs, out=states)
         if e: e.record()
@@ -276,7 +273,7 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     res = {
         "metric": "draws/s", "value": draws / dt, "unit": "draws/s", "ms_per_step": dt * 1e3,
         "dtype": "u24", "config": {"workload": f"family65k: 65,536 streams from seed 4711 at offsets k*2^40 "
-                                   f"({'family jump: int8 MFMA product of shared factors' if jump_mode == 'family' else 'one jump per stream'}"
+                                   f"({'per-rank streams: seeding and 65,536 starts as int8 MFMA products of shared factors, two launches' if jump_mode == 'family' else 'one jump per stream'}"
                                    "), 4,096 draws each written as uint32 and as float32",
                                    "streams": n, "draws_per_stream": cnt, "jump": jump_mode},
         "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},

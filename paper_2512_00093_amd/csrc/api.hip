@@ -179,7 +179,13 @@ int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64
   int rc = ensure_init();
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_seed_jump_one((uint32_t*)d_out, seed, ranmar_u128{(uint64_t)E0, (uint64_t)(E0 >> 64)}, st);
+  const ranmar_u128 e0{(uint64_t)E0, (uint64_t)(E0 >> 64)};
+  if (n_ranks > 1 && family_variant_for(n_ranks) == FAMILY_GEMM) {
+    // Seeding inside the product form's first launch (one launch fewer).
+    const hipError_t g = launch_family_gemm_seeded(seed, e0, J, n_ranks, (uint32_t*)d_out, st);
+    if (g != hipErrorInvalidValue) return hip_status(g);
+  }
+  hipError_t e = launch_seed_jump_one((uint32_t*)d_out, seed, e0, st);
   if (e == hipSuccess && n_ranks > 1)  // the rest as a family around d_out[0]
     e = launch_family_variant(family_variant_for(n_ranks), (const uint32_t*)d_out, J, n_ranks, (uint32_t*)d_out, st);
   return hip_status(e);

@@ -62,10 +62,13 @@ __device__ __forceinline__ void limbs3(uint32_t v, int& w0, int& w1, int& w2) {
   w2 = (int)(int8_t)(t & 0xFF);  // the top carry (2^24) is dropped: mod 2^24
 }
 
+// Start jobs begin from the base record, or (seed > 0) from the seeded state
+// of `seed` (Algorithm 3, by the half-wave); start t is then jumped by
+// E0 + t delta.
 __global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_t* out, uint32_t* __restrict__ H,
                                                    const uint32_t* __restrict__ T, uint64_t A, uint64_t njobs,
                                                    uint64_t d_lo, uint64_t d_hi, uint64_t ad_lo, uint64_t ad_hi,
-                                                   uint32_t in_place) {
+                                                   uint32_t in_place, int32_t seed, uint64_t e0_lo, uint64_t e0_hi) {
   __shared__ uint32_t lds[8 * kL1Words];
   const uint32_t hw = threadIdx.x >> 5, l = threadIdx.x & 31u;
   const uint64_t t = (uint64_t)blockIdx.x * 8u + hw;
@@ -76,12 +79,19 @@ __global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_
   unsigned __int128 E = 0;
   uint32_t c = 0;
   if (is_start) {
-    X[l] = base[l];
-    X[l + 32] = base[l + 32];
-    X[l + 64] = base[l + 64];
-    if (l == 0) X[96] = base[96];
-    c = base[97];
-    E = (unsigned __int128)t * (((unsigned __int128)d_hi << 64) | d_lo);  // t delta <= (n - 1) delta
+    if (seed > 0) {
+      seed_half(seed, X, l);  // the host checked the seed
+      wave_sync();
+      c = X[97];
+    } else {
+      X[l] = base[l];
+      X[l + 32] = base[l + 32];
+      X[l + 64] = base[l + 64];
+      if (l == 0) X[96] = base[96];
+      c = base[97];
+    }
+    // E0 + t delta <= E0 + (n - 1) delta < 2^128: checked on the host.
+    E = (((unsigned __int128)e0_hi << 64) | e0_lo) + (unsigned __int128)t * (((unsigned __int128)d_hi << 64) | d_lo);
   } else {
     X[l] = X[l + 32] = X[l + 64] = 0;  // e_96
     if (l == 0) X[96] = 1u;
@@ -292,11 +302,15 @@ __global__ __launch_bounds__(256, 3) void k_family_gemm(uint32_t* out, const uin
 }  // namespace
 
 // Returns hipErrorInvalidValue (nothing launched) when the family is too small
-// for the product form (n < 2 A), or (n - 1) delta needs more than 128 bits.
-hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st) {
+// for the product form (n < 2 A), or E0 + (n - 1) delta needs more than 128
+// bits.  Starts from `base` (seed == 0, E0 == 0) or from the state of `seed`
+// at offset E0.
+static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n,
+                              uint32_t* out, hipStream_t st) {
   const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
+  const unsigned __int128 E0 = ((unsigned __int128)e0.hi << 64) | e0.lo;
   const unsigned __int128 kMax = ~(unsigned __int128)0;
-  if (n < 2 || D > kMax / (n - 1)) return hipErrorInvalidValue;
+  if (n < 2 || D > (kMax - E0) / (n - 1)) return hipErrorInvalidValue;
   // A ~ sqrt(n): A direct jumps plus B - 1 factor jumps.
   uint64_t A = (uint64_t)std::ceil(std::sqrt((double)n) / 16.0) * 16;
   if (A < 16) A = 16;
@@ -325,7 +339,7 @@ hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_family_l1, dim3((unsigned)((njobs + 7) / 8)), dim3(256), 0, st, base, out, H, T, A, njobs,
                      (uint64_t)D, (uint64_t)(D >> 64), (uint64_t)AD, (uint64_t)(AD >> 64),
-                     (uint32_t)(base == out ? 1 : 0));
+                     (uint32_t)(seed == 0 && base == out ? 1 : 0), seed, e0.lo, e0.hi);
   e = hipGetLastError();
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_family_gemm, dim3((unsigned)gx, (unsigned)(B - 1)), dim3(256), 0, st, out, H, A, n,
@@ -334,6 +348,15 @@ hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t 
   }
   const hipError_t f = hipFreeAsync(H, st);
   return e != hipSuccess ? e : f;
+}
+
+hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st) {
+  return family_gemm(base, 0, ranmar_u128{0, 0}, delta, n, out, st);
+}
+
+hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,
+                                     hipStream_t st) {
+  return family_gemm(nullptr, seed, e0, delta, n, out, st);
 }
 
 }  // namespace ranmar

@@ -30,6 +30,10 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
 // Family as a matrix product on the matrix cores; hipErrorInvalidValue if
 // the family is too small for it or an exponent needs > 128 bits.
 hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
+// The same family around the state of a (checked) seed at offset e0: the
+// seeding happens inside the first launch.
+hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,
+                                     hipStream_t st);
 enum FamilyVariant : int {
   FAMILY_RADIX = 0,  // radix-256 rounds, one table application per start (VALU)
   FAMILY_GEMM = 1,   // ~sqrt(n) direct starts and factors, the rest as int8 MFMA products

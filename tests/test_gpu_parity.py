@@ -295,10 +295,11 @@ def test_family_equals_independent_jumps(orc, n, delta):
 # --- per-rank streams -------------------------------------------------------------
 @pytest.mark.parametrize("seed,J,first,n,discard", [
     (4711, 1 << 40, 0, 1, 0), (4711, 1 << 40, 0, 7, 1), (12345, (1 << 100) + 77, 3, 130, 0),
-    (900000000, 999_999, 1000, 5000, 1), (1, 1 << 60, 0, 40_000, 0)])
+    (900000000, 999_999, 1000, 5000, 1), (1, 1 << 60, 0, 40_000, 0), (77, (1 << 50) + 3, 5, 33_000, 1)])
 def test_rank_streams(orc, seed, J, first, n, discard):
     """Rank first+k starts at offset (first+k) J (+1 with the warm-up discard);
-    the last case takes the matrix-core family path."""
+    the last two cases take the matrix-core family path with the seeding
+    inside its first launch."""
     say(f"rank_streams seed={seed} J={J} first={first} n={n} discard={discard}")
     got = R.ranmar_rank_streams(seed, J, first, n, discard_first=bool(discard), device=dev())
     torch.cuda.synchronize()
