@@ -118,15 +118,22 @@ __device__ __forceinline__ uint32_t seed_word_at(int ii, uint32_t a0, uint32_t b
 // The 32 lanes of a half-wave (lane index l) write the seeded state to
 // X[0..96] and c to X[97].  Returns false (and writes nothing) for a seed out
 // of [1, 9e8]; the result is uniform over the half.
-__device__ __forceinline__ bool seed_half(int32_t seed, uint32_t* X, uint32_t l) {
-  if (seed < 1 || seed > 900000000) return false;
+// Algorithm 3's starting values (i, j, k as discrete logs base 2 mod 179,
+// and l) for a seed in [1, 9e8].
+__device__ __forceinline__ void seed_start(int32_t seed, uint32_t& a0, uint32_t& b0, uint32_t& c0, uint32_t& l0) {
   const uint32_t s1 = (uint32_t)seed - 1u;
   const uint32_t ij = s1 / 30082u;
   const uint32_t kl = s1 - 30082u * ij;
-  const uint32_t a0 = kSeedTab.log2[(ij / 177u) % 177u + 2u];
-  const uint32_t b0 = kSeedTab.log2[ij % 177u + 2u];
-  const uint32_t c0 = kSeedTab.log2[(kl / 169u) % 178u + 1u];
-  const uint32_t l0 = kl % 169u;
+  a0 = kSeedTab.log2[(ij / 177u) % 177u + 2u];
+  b0 = kSeedTab.log2[ij % 177u + 2u];
+  c0 = kSeedTab.log2[(kl / 169u) % 178u + 1u];
+  l0 = kl % 169u;
+}
+
+__device__ __forceinline__ bool seed_half(int32_t seed, uint32_t* X, uint32_t l) {
+  if (seed < 1 || seed > 900000000) return false;
+  uint32_t a0, b0, c0, l0;
+  seed_start(seed, a0, b0, c0, l0);
   // u_(ii+1) goes to x[96 - ii].
   X[96 - l] = seed_word_at(l, a0, b0, c0, l0);
   X[64 - l] = seed_word_at(l + 32, a0, b0, c0, l0);

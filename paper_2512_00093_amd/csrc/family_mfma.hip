@@ -70,16 +70,32 @@ __global__ __launch_bounds__(256) void k_family_l1(const uint32_t* base, uint32_
                                                    uint64_t d_lo, uint64_t d_hi, uint64_t ad_lo, uint64_t ad_hi,
                                                    uint32_t in_place, int32_t seed, uint64_t e0_lo, uint64_t e0_hi) {
   __shared__ uint32_t lds[8 * kL1Words];
+  __shared__ uint32_t seeded[97];
   const uint32_t hw = threadIdx.x >> 5, l = threadIdx.x & 31u;
   const uint64_t t = (uint64_t)blockIdx.x * 8u + hw;
   const bool active = t < njobs;
   const bool is_start = t < A;
+  // Workgroups of start jobs only (A is a multiple of 8) seed together: one
+  // word per thread instead of three per lane.
+  const bool wg_seeds = seed > 0 && ((uint64_t)blockIdx.x + 1) * 8u <= A;
+  if (wg_seeds) {
+    uint32_t a0, b0, c0, l0;
+    seed_start(seed, a0, b0, c0, l0);
+    if (threadIdx.x < 97) seeded[96 - threadIdx.x] = seed_word_at((int)threadIdx.x, a0, b0, c0, l0);
+    __syncthreads();  // uniform over the workgroup
+  }
   uint32_t* X = lds + hw * kL1Words;
   uint32_t* Bp = X + 193;
   unsigned __int128 E = 0;
   uint32_t c = 0;
   if (is_start) {
-    if (seed > 0) {
+    if (wg_seeds) {
+      X[l] = seeded[l];
+      X[l + 32] = seeded[l + 32];
+      X[l + 64] = seeded[l + 64];
+      if (l == 0) X[96] = seeded[96];
+      c = kC0;
+    } else if (seed > 0) {
       seed_half(seed, X, l);  // the host checked the seed
       wave_sync();
       c = X[97];
