@@ -134,8 +134,9 @@ int ranmar_apply_poly(ranmar_state *d_states, const uint32_t *d_P, uint64_t n, v
  * Memory: P_J is formed as a product of precomputed powers of t, one per
  * nonzero digit of J.  The library keeps, per device and until the process
  * ends, a 1.6 MB table of 8-bit digits and, from the first call with at
- * least 16384 requests, a 203 MB table of 16-bit digits (if that allocation
- * fails, the 8-bit table serves; results are the same either way). */
+ * least 16384 requests, a 2.4 GB table of 20-bit digits (6 factors for a
+ * 120-bit J instead of 15; if that allocation fails, the 16-bit table of
+ * 203 MB or the 8-bit one serves; results are the same either way). */
 int ranmar_jump(ranmar_state *d_states, const ranmar_u128 *d_J, uint64_t n, void *stream);
 
 /* a1-a4 fused in one launch: d_out[r] = f^J(seed state of d_seeds[r]) with

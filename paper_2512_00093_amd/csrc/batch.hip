@@ -135,7 +135,7 @@ struct ranmar_batch {
   size_t prepared_bytes = 0;  // descriptor bytes staged by prepare, 0 = none
   BatchBuffers B{};
   std::vector<BReq> tmp;      // prepare: slices with draws, before the final layout
-  bool tried_wtab16 = false;  // the 16-bit window table was asked for
+  bool tried_wtab = false;  // the 20-bit window table was asked for
   uint8_t* kdesc = nullptr;   // kernel argument storage for the graph node
   void* kargs[2] = {nullptr, nullptr};
 };
@@ -211,7 +211,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
     b->B.queue = b->d_queue;
     b->B.err = b->h_err;
     b->B.wtab = window_table();
-    b->B.wtab16 = nullptr;  // set by the first batch with many requests without draws
+    b->B.wtab20 = nullptr;  // set by the first batch with many requests without draws
     b->B.spare = (uint32_t)b->max_slices;
     ok = b->B.wtab != nullptr;
   }
@@ -267,12 +267,12 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     n_jo += p_jo[t];
   }
   if (total > b->max_chunks) return RANMAR_ENOMEM;
-  // Many requests without draws: jump them with 16-bit windows (the 203 MB
+  // Many requests without draws: jump them with 20-bit windows (the 2.4 GB
   // table is built once per device, on first use; if it cannot be, the 8-bit
   // table serves).  The kernel node takes the new pointer at the next launch.
-  if (n_jo >= 16384 && !b->B.wtab16 && !b->tried_wtab16) {
-    b->tried_wtab16 = true;
-    b->B.wtab16 = window16_table();
+  if (n_jo >= 16384 && !b->B.wtab20 && !b->tried_wtab) {
+    b->tried_wtab = true;
+    b->B.wtab20 = window20_table();
     b->grid_node = 0;  // forces the kernel node's arguments to be set again
   }
   // Bins: about 4 units of work (jumps + chunks) per bin at least, at most 64.
@@ -338,7 +338,7 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   }
   // Slice table: per bin, its slices with draws, then its share of the
   // requests without draws (an equal split, in order).
-  const bool octets = b->B.wtab16 != nullptr;
+  const bool octets = b->B.wtab20 != nullptr;
   const uint32_t wpb_max = std::max<uint32_t>(1, b->workers_max / nb);
   uint64_t ns = 0, ti = 0, k0 = 0;
   uint32_t wpb = 1;
@@ -348,7 +348,7 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     for (uint32_t k = 0; k < nsc[i]; ++k) sl[ns++] = tmp[ti++];
     ns += n_jo * (i + 1) / nb - n_jo * i / nb;  // filled below
     bn.ns = (uint32_t)(ns - bn.s0);
-    bn.nsc = octets ? nsc[i] : bn.ns;  // without the 16-bit table, pair items take every slice
+    bn.nsc = octets ? nsc[i] : bn.ns;  // without the 20-bit table, pair items take every slice
     bn.k0 = (uint32_t)k0;
     bn.nk = nkb[i];
     k0 += nkb[i];

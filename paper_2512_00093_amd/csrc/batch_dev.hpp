@@ -150,7 +150,7 @@ struct BatchBuffers {
   uint32_t* done;          // one flag per slice, plus one spare written by idle halves
   const uint32_t* ptab;    // 97 words per q: P_{qL}
   const uint32_t* wtab;    // window table T[w][d], 8-bit digits
-  const uint32_t* wtab16;  // window table with 16-bit digits, or nullptr
+  const uint32_t* wtab20;  // window table with 20-bit digits, or nullptr
   uint32_t* queue;         // single-request launches: [0] next item, [1] finished workgroups
   int* err;                // host-visible error word
   uint32_t spare;          // index of the spare flag
@@ -284,7 +284,7 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
 }
 
 // Eight slices without draws per wave, 8 lanes each (seed_group / jump_group
-// of coop_dev.hpp, 16-bit windows; the host makes octet items only when that
+// of coop_dev.hpp, 20-bit windows; the host makes octet items only when that
 // table exists).  Nothing waits for them: the state goes straight to the
 // caller's record, if it asked for one.
 template <class Desc>
@@ -308,7 +308,7 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
   const uint32_t c = X[97];
   const uint32_t j0 = valid ? (uint32_t)q.off_lo : 0u, j1 = valid ? (uint32_t)(q.off_lo >> 32) : 0u;
   const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
-  jump_group<8, 16>(X, Bp, B.wtab16, j0, j1, j2, j3, wave_windows<16>(j0, j1, j2, j3), l);
+  jump_group<8, 20>(X, Bp, B.wtab20, j0, j1, j2, j3, wave_windows<20>(j0, j1, j2, j3), l);
   if (active && q.state) {
     uint32_t* dst = (uint32_t*)q.state;
 #pragma unroll

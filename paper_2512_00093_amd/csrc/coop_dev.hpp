@@ -196,15 +196,22 @@ __device__ __forceinline__ void apply_half(uint32_t* X, const uint32_t* B, uint3
 // `nwin`: number of low windows to consider (uniform over the wave); windows
 // whose digit is zero in every lane of the wave are skipped.  The next
 // window's row is loaded while the current one is applied.
-// Digit w of J in base 2^WB (WB = 8 or 16, J as four 32-bit limbs).
+// Digit w of J in base 2^WB (WB = 8, 16 or 20, J as four 32-bit limbs).  A
+// 20-bit digit may straddle two limbs; the last one (bits 120..127) has 8 bits.
 template <int WB = kWinBits>
 __device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w) {
   const int bit = w * WB;
-  const uint32_t limb = bit < 32 ? j0 : bit < 64 ? j1 : bit < 96 ? j2 : j3;
-  return (limb >> (bit & 31)) & ((1u << WB) - 1u);
+  const uint32_t lo = bit < 32 ? j0 : bit < 64 ? j1 : bit < 96 ? j2 : j3;
+  if constexpr (32 % WB == 0) {
+    return (lo >> (bit & 31)) & ((1u << WB) - 1u);
+  } else {
+    const uint32_t hi = bit < 32 ? j1 : bit < 64 ? j2 : bit < 96 ? j3 : 0u;
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (bit & 31)) & ((1u << WB) - 1u);
+  }
 }
 
-// Row of the factor t^(d 2^(WB w)) in a table of 2^WB rows per window.
+// Row of the factor t^(d 2^(WB w)) in a table of 2^WB rows per window (the
+// last window of a 20-bit table has only 2^8).
 template <int WB = kWinBits>
 __device__ __forceinline__ const uint32_t* window_row(const uint32_t* __restrict__ T, uint32_t j0, uint32_t j1,
                                                       uint32_t j2, uint32_t j3, int w) {

@@ -22,6 +22,7 @@ hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar
                             hipStream_t st);
 const uint32_t* window_table();    // T[w][d] = t^(d 2^(8w)) mod phi, per device
 const uint32_t* window16_table();  // T[w][d] = t^(d 2^(16w)) mod phi, per device (nullptr if it cannot be built)
+const uint32_t* window20_table();  // T[w][d] = t^(d 2^(20w)) mod phi: 6 x 2^20 + 2^8 rows (nullptr if it cannot be built)
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
 // One record: the state of a (checked) seed at offset E, values by argument.
 hipError_t launch_seed_jump_one(uint32_t* out, int32_t seed, ranmar_u128 E, hipStream_t st);
@@ -51,7 +52,8 @@ enum JumpVariant : int {
   JUMP_QUARTER_WINDOW = 2,  // one request per 16 lanes, 8-bit windows in LDS
   JUMP_EIGHTH_WINDOW = 3,   // one request per 8 lanes, 8-bit windows in LDS
   JUMP_EIGHTH_WINDOW16 = 4, // one request per 8 lanes, 16-bit windows (203 MB table)
-  JUMP_NUM_VARIANTS = 5
+  JUMP_EIGHTH_WINDOW20 = 5, // one request per 8 lanes, 20-bit windows (2.4 GB table)
+  JUMP_NUM_VARIANTS = 6
 };
 int jump_variant_for(uint64_t n);
 // Seed (seeds != nullptr) and jump with the given variant.

@@ -299,16 +299,17 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
 // halves the number of applications.
 // ---------------------------------------------------------------------------
 static const uint32_t* build_window_table(int wb) {
-  const int windows = 128 / wb;
+  const int windows = (128 + wb - 1) / wb;
   const uint64_t digits = 1ull << wb;
-  const uint64_t n = (uint64_t)windows * digits;
+  const int last_bits = 128 - wb * (windows - 1);  // the last window may be narrower (8 bits for wb = 20)
+  const uint64_t n = (uint64_t)(windows - 1) * digits + (1ull << last_bits);
   std::vector<ranmar_u128> Jh(n);
-  for (int w = 0; w < windows; ++w)
-    for (uint64_t d = 0; d < digits; ++d) {
-      const unsigned __int128 v = (unsigned __int128)d << (wb * w);
-      Jh[w * digits + d].lo = (uint64_t)v;
-      Jh[w * digits + d].hi = (uint64_t)(v >> 64);
-    }
+  for (uint64_t r = 0; r < n; ++r) {
+    const uint64_t w = r >> wb, d = r & (digits - 1);
+    const unsigned __int128 v = (unsigned __int128)d << (wb * w);
+    Jh[r].lo = (uint64_t)v;
+    Jh[r].hi = (uint64_t)(v >> 64);
+  }
   uint32_t* T = nullptr;
   ranmar_u128* dJ = nullptr;
   hipStream_t st = nullptr;
@@ -341,6 +342,7 @@ static const uint32_t* cached_window_table(int wb) {
 
 const uint32_t* window_table() { return cached_window_table(8); }
 const uint32_t* window16_table() { return cached_window_table(16); }
+const uint32_t* window20_table() { return cached_window_table(20); }
 
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                             hipStream_t st) {
@@ -361,7 +363,7 @@ static hipError_t launch_jump_grp(uint32_t* states, const int32_t* seeds, const 
   constexpr uint64_t kPerWg = 256 / G;
   if (!n) return hipSuccess;
   if ((n + kPerWg - 1) / kPerWg > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  const uint32_t* T = WB == 16 ? window16_table() : window_table();
+  const uint32_t* T = WB == 20 ? window20_table() : WB == 16 ? window16_table() : window_table();
   if (!T) return hipErrorOutOfMemory;
   const dim3 grid((unsigned)((n + kPerWg - 1) / kPerWg));
   if (seeds)
@@ -375,8 +377,10 @@ hipError_t launch_jump_variant(int v, uint32_t* states, const int32_t* seeds, co
                                hipStream_t st) {
   if (v == JUMP_QUARTER_WINDOW) return launch_jump_grp<16, 8>(states, seeds, J, n, st);
   if (v == JUMP_EIGHTH_WINDOW) return launch_jump_grp<8, 8>(states, seeds, J, n, st);
-  if (v == JUMP_EIGHTH_WINDOW16) {
-    // The 16-bit table is large; without it the 8-bit windows do the same job.
+  // The 20- and 16-bit tables are large; without them narrower windows do
+  // the same job.
+  if (v == JUMP_EIGHTH_WINDOW20 && window20_table()) return launch_jump_grp<8, 20>(states, seeds, J, n, st);
+  if (v == JUMP_EIGHTH_WINDOW20 || v == JUMP_EIGHTH_WINDOW16) {
     if (window16_table()) return launch_jump_grp<8, 16>(states, seeds, J, n, st);
     return launch_jump_grp<8, 8>(states, seeds, J, n, st);
   }
