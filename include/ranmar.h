@@ -270,7 +270,9 @@ typedef struct ranmar_server ranmar_server;
 /* Starts a server thread on the current device.  d_arena/arena_bytes is the
  * HBM budget: all request outputs are sub-allocated from it (256-byte
  * aligned); the caller keeps ownership and must keep it alive until
- * ranmar_serve_destroy.  cfg may be NULL for defaults. */
+ * ranmar_serve_destroy.  cfg may be NULL for defaults.  Besides the arena,
+ * the library keeps the 2.4 GB table of 20-bit jump digits (see ranmar_jump),
+ * built here if it does not exist yet, so that no request waits for it. */
 int ranmar_serve_create(void *d_arena, uint64_t arena_bytes, const ranmar_serve_cfg *cfg,
                         ranmar_server **out);
 

@@ -175,6 +175,18 @@ static uint64_t chunk_offset(uint64_t n, uint32_t nb) {
   return (req_offset(nb) + sizeof(BReq) * (n + nb) + 15) & ~15ull;
 }
 
+namespace ranmar {
+void batch_use_wide_windows(ranmar_batch* b) {
+  if (!b) return;
+  b->tried_wtab = true;
+  const uint32_t* T = window20_table();
+  if (T && b->B.wtab20 != T) {
+    b->B.wtab20 = T;
+    b->grid_node = 0;  // the kernel node takes the pointer at the next launch
+  }
+}
+}  // namespace ranmar
+
 extern "C" {
 
 int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chunk_draws, ranmar_batch** out) {
@@ -500,7 +512,7 @@ extern "C" int ranmar_run_unbatched(const ranmar_request* reqs, uint64_t n, void
     d.r0 = to_breq(reqs[r]);
     d.L = kDefaultChunk;
     d.epoch = ++c.epoch;
-    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), nullptr, c.queue, c.err, 1u};
+    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), window20_table_ready(), c.queue, c.err, 1u};
     if (!B.wtab) return RANMAR_ENOMEM;
     const uint64_t items = 1 + (nq + 1) / 2;
     const unsigned grid = (unsigned)(items < maxgrid ? items : maxgrid);

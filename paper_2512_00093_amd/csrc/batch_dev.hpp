@@ -201,7 +201,10 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   const uint32_t c = X[97];
   const uint32_t j0 = valid ? (uint32_t)q.off_lo : 0u, j1 = valid ? (uint32_t)(q.off_lo >> 32) : 0u;
   const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
-  jump_half(X, Bp, B.wtab, j0, j1, j2, j3, wave_windows(j0, j1, j2, j3), l);
+  if (B.wtab20)  // uniform: 6 factors for a 120-bit offset instead of 15
+    jump_half<20>(X, Bp, B.wtab20, j0, j1, j2, j3, wave_windows<20>(j0, j1, j2, j3), l);
+  else
+    jump_half<8>(X, Bp, B.wtab, j0, j1, j2, j3, wave_windows<8>(j0, j1, j2, j3), l);
   // A request with no draws but a state output is written straight to the
   // caller's record.  The words go out as device-scope stores (written
   // through to the device's coherence point, see publish_wait), so chunks on

@@ -226,11 +226,12 @@ __device__ __forceinline__ int next_window(uint32_t j0, uint32_t j1, uint32_t j2
   return w;
 }
 
+template <int WB = kWinBits>
 __device__ __forceinline__ void jump_half(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
                                           uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
-  int w = next_window(j0, j1, j2, j3, 0, nwin);
+  int w = next_window<WB>(j0, j1, j2, j3, 0, nwin);
   if (w >= nwin) return;
-  const uint32_t* row = window_row(T, j0, j1, j2, j3, w);
+  const uint32_t* row = window_row<WB>(T, j0, j1, j2, j3, w);
   uint32_t r0 = row[l], r1 = row[l + 32], r2 = row[l + 64], r3 = row[96];
   while (w < nwin) {
     B[l] = r0;
@@ -238,9 +239,9 @@ __device__ __forceinline__ void jump_half(uint32_t* X, uint32_t* B, const uint32
     B[l + 64] = r2;
     if (l == 0) B[96] = r3;
     wave_sync();
-    const int wn = next_window(j0, j1, j2, j3, w + 1, nwin);
+    const int wn = next_window<WB>(j0, j1, j2, j3, w + 1, nwin);
     if (wn < nwin) {
-      row = window_row(T, j0, j1, j2, j3, wn);
+      row = window_row<WB>(T, j0, j1, j2, j3, wn);
       r0 = row[l];
       r1 = row[l + 32];
       r2 = row[l + 64];

@@ -23,6 +23,9 @@ hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar
 const uint32_t* window_table();    // T[w][d] = t^(d 2^(8w)) mod phi, per device
 const uint32_t* window16_table();  // T[w][d] = t^(d 2^(16w)) mod phi, per device (nullptr if it cannot be built)
 const uint32_t* window20_table();  // T[w][d] = t^(d 2^(20w)) mod phi: 6 x 2^20 + 2^8 rows (nullptr if it cannot be built)
+const uint32_t* window20_table_ready();  // the same if already built on this device, else nullptr (never builds)
+// Makes the batch's jumps use the 20-bit table (building it now if needed).
+void batch_use_wide_windows(ranmar_batch* b);
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
 // One record: the state of a (checked) seed at offset E, values by argument.
 hipError_t launch_seed_jump_one(uint32_t* out, int32_t seed, ranmar_u128 E, hipStream_t st);

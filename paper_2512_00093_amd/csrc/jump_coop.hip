@@ -1,5 +1,6 @@
 // Half-wave cooperative seeding and windowed jump-ahead (see coop_dev.hpp):
 // eight requests per 256-thread workgroup, state and polynomial in LDS.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -327,6 +328,10 @@ static const uint32_t* build_window_table(int wb) {
   return T;
 }
 
+// Built 20-bit tables, published for readers that must not wait for a build
+// (devices 0..63).
+static std::atomic<const uint32_t*> g_t20_ready[64];
+
 static const uint32_t* cached_window_table(int wb) {
   static std::mutex mu;
   static std::map<std::pair<int, int>, const uint32_t*> tabs;  // (device, width) -> table; failures cached too
@@ -337,12 +342,19 @@ static const uint32_t* cached_window_table(int wb) {
   if (it != tabs.end()) return it->second;
   const uint32_t* T = build_window_table(wb);
   tabs[{dev, wb}] = T;
+  if (wb == 20 && dev >= 0 && dev < 64) g_t20_ready[dev].store(T, std::memory_order_release);
   return T;
 }
 
 const uint32_t* window_table() { return cached_window_table(8); }
 const uint32_t* window16_table() { return cached_window_table(16); }
 const uint32_t* window20_table() { return cached_window_table(20); }
+
+const uint32_t* window20_table_ready() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  return g_t20_ready[dev].load(std::memory_order_acquire);
+}
 
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                             hipStream_t st) {

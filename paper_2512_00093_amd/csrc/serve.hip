@@ -326,8 +326,12 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
     if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming) != hipSuccess)
       rc = RANMAR_EHIP;
-    if (!rc && !s->cfg.unbatched)
+    if (!rc && !s->cfg.unbatched) {
       rc = ranmar_batch_create(s->max_tick_requests, s->cfg.max_tick_chunks, s->L, &ln.b);
+      // Every request jumps to a 120-bit offset: the 20-bit table (built here,
+      // once per device, not on a request's path) takes 6 factors, not 15.
+      if (!rc) ranmar::batch_use_wide_windows(ln.b);
+    }
     if (rc) break;
   }
   if (rc) {
