@@ -86,6 +86,8 @@ def _parse():
     ap.add_argument("--jump", default="family", choices=["family", "lanes"],
                     help="family65k: stream starts by prefix doubling or one jump per stream")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the library's autotuner (defaults instead of measured variants)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy", action="store_true",
@@ -444,6 +446,26 @@ def run_serve(R, torch, n_req, qps, n_base):
                                    f"{min(n_base, n_req)} requests served one launch per request"}}
 
 
+def autotune(R, workload, extras):
+    """Runs the library's autotuner on this device for the shapes the timed
+    workloads use; later calls with those shapes take the fastest variant.
+    Returns {shape: variant name}."""
+    shapes = []
+    if workload == "family65k":
+        shapes += [(R.RANMAR_K_FAMILY, synth.FAMILY_65K["streams"], 40),
+                   (R.RANMAR_K_GENERATE, synth.FAMILY_65K["streams"], synth.FAMILY_65K["draws"])]
+    if workload == "bulk1m" or extras:
+        shapes.append((R.RANMAR_K_GENERATE, synth.BULK_1M["streams"], synth.BULK_1M["draws"]))
+    if workload == "jumps1m" or extras:
+        shapes.append((R.RANMAR_K_JUMP, synth.BATCH_JUMPS["requests"], 120))
+    names = {R.RANMAR_K_GENERATE: "generate", R.RANMAR_K_JUMP: "jump", R.RANMAR_K_FAMILY: "family"}
+    out = {}
+    for k, n, c in shapes:
+        best, _ = R.ranmar_tune_run(k, n, c)
+        out[f"{names[k]} {n}x{c}"] = R.ranmar_tune_variant_name(k, best)
+    return out
+
+
 def main():
     a = _parse()
     if a.gpus != 1:
@@ -462,6 +484,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = {} if a.no_tune else autotune(R, a.workload, not a.no_extras and a.workload == "family65k")
+    if tuned:
+        _progress("autotuned: " + json.dumps(tuned))
     if a.workload == "family65k":
         res = run_family65k(R, torch, a.steps, a.warmup, a.jump)
         _progress("family65k done")
@@ -482,6 +507,7 @@ def main():
     for k in ("breakdown_ms", "output_write_GBps", "output_write_frac"):
         if k in res:
             line[k] = res[k]
+    line["tuned"] = tuned
     if not a.no_extras and a.workload == "family65k":
         also = {}
         for name, fn in (("bulk1m", run_bulk1m), ("jumps1m", run_jumps1m)):

@@ -4,6 +4,7 @@
 // loaded from a small text file ("kernel log2n log2count variant" per line).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -73,6 +74,34 @@ int gen_variant_for(uint64_t n, uint64_t count) {
   return n >= 32768 ? GEN_LANES32_NT_R2 : GEN_WIDE4;
 }
 
+// Times every variant in `rounds` passes over all of them (so that slow
+// drifts of clock or memory state hit each alike), `reps` launches per pass
+// after one untimed launch, and keeps each variant's best pass.  Returns the
+// fastest variant, or -1 on a HIP error.
+template <class Run>
+static int time_variants(int nv, Run run, double* ms_out, hipEvent_t e0, hipEvent_t e1, hipStream_t st,
+                         int reps = 5, int rounds = 3) {
+  std::vector<double> best(nv, 1e30);
+  for (int rd = 0; rd < rounds; ++rd)
+    for (int v = 0; v < nv; ++v) {
+      if (run(v) != hipSuccess) return -1;
+      hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r)
+        if (run(v) != hipSuccess) return -1;
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) return -1;
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      best[v] = std::min(best[v], (double)ms / reps);
+    }
+  int bv = 0;
+  for (int v = 0; v < nv; ++v) {
+    if (ms_out) ms_out[v] = best[v];
+    if (best[v] < best[bv]) bv = v;
+  }
+  return bv;
+}
+
 // Times the jump variants on n seed+jump requests with `bits`-bit offsets.
 static int tune_jump(uint64_t n, int bits, double* ms_out, hipStream_t st) {
   if (n > (1ull << 24) || bits < 1 || bits > 128) return RANMAR_EINVAL;
@@ -96,7 +125,6 @@ static int tune_jump(uint64_t n, int bits, double* ms_out, hipStream_t st) {
   uint32_t* d_states = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = RANMAR_EHIP;
-  double best = 1e30;
   int best_v = 0;
   if (hipMalloc(&d_seeds, 4 * n) != hipSuccess || hipMalloc(&d_J, 16 * n) != hipSuccess ||
       hipMalloc(&d_states, sizeof(ranmar_state) * n) != hipSuccess)
@@ -105,24 +133,10 @@ static int tune_jump(uint64_t n, int bits, double* ms_out, hipStream_t st) {
       hipMemcpyAsync(d_J, J.data(), 16 * n, hipMemcpyHostToDevice, st) != hipSuccess)
     goto done;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
-  for (int v = 0; v < JUMP_NUM_VARIANTS; ++v) {
-    auto run = [&] { return launch_jump_variant(v, d_states, d_seeds, d_J, n, st); };
-    if (run() != hipSuccess) goto done;
-    hipEventRecord(e0, st);
-    const int reps = 3;
-    for (int r = 0; r < reps; ++r)
-      if (run() != hipSuccess) goto done;
-    hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) goto done;
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    const double per = ms / reps;
-    if (ms_out) ms_out[v] = per;
-    if (per < best) {
-      best = per;
-      best_v = v;
-    }
-  }
+  best_v = time_variants(
+      JUMP_NUM_VARIANTS, [&](int v) { return launch_jump_variant(v, d_states, d_seeds, d_J, n, st); }, ms_out, e0,
+      e1, st, 3, 2);
+  if (best_v < 0) goto done;
   {
     std::lock_guard<std::mutex> g(g_mu);
     g_table[{RANMAR_K_JUMP, ilog2(n), 0}] = best_v;
@@ -148,30 +162,16 @@ static int tune_family(uint64_t n, int lg, double* ms_out, hipStream_t st) {
   uint32_t *d_base = nullptr, *d_out = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = RANMAR_EHIP;
-  double best = 1e30;
   int best_v = 0;
   if (hipMalloc(&d_base, sizeof(ranmar_state)) != hipSuccess ||
       hipMalloc(&d_out, sizeof(ranmar_state) * n) != hipSuccess)
     goto done;
   if (hipMemcpyAsync(d_base, &h, sizeof h, hipMemcpyHostToDevice, st) != hipSuccess) goto done;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
-  for (int v = 0; v < FAMILY_NUM_VARIANTS; ++v) {
-    if (launch_family_variant(v, d_base, delta, n, d_out, st) != hipSuccess) goto done;
-    hipEventRecord(e0, st);
-    const int reps = 5;
-    for (int r = 0; r < reps; ++r)
-      if (launch_family_variant(v, d_base, delta, n, d_out, st) != hipSuccess) goto done;
-    hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) goto done;
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    const double per = ms / reps;
-    if (ms_out) ms_out[v] = per;
-    if (per < best) {
-      best = per;
-      best_v = v;
-    }
-  }
+  best_v = time_variants(
+      FAMILY_NUM_VARIANTS, [&](int v) { return launch_family_variant(v, d_base, delta, n, d_out, st); }, ms_out, e0,
+      e1, st);
+  if (best_v < 0) goto done;
   {
     std::lock_guard<std::mutex> g(g_mu);
     g_table[{RANMAR_K_FAMILY, ilog2(n), 0}] = best_v;
@@ -237,7 +237,6 @@ int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void
   for (uint64_t i = 0; i < n; ++i) seeds[i] = (int32_t)(1 + (i * 2654435761ull) % 900000000ull);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rc = RANMAR_EHIP;
-  double best = 1e30;
   int best_v = 0;
   if (hipMalloc(&d_seeds, 4 * n) != hipSuccess) goto done;
   if (hipMalloc(&d_states, sizeof(ranmar_state) * n) != hipSuccess) goto done;
@@ -245,23 +244,10 @@ int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void
   if (hipMemcpyAsync(d_seeds, seeds.data(), 4 * n, hipMemcpyHostToDevice, st) != hipSuccess) goto done;
   if (launch_seed(d_seeds, n, d_states, st) != hipSuccess) goto done;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
-  for (int v = 0; v < nv; ++v) {
-    const int reps = 5;
-    if (launch_generate(v, d_states, nullptr, n, count, RANMAR_F32, d_out, count, st) != hipSuccess) goto done;
-    hipEventRecord(e0, st);
-    for (int r = 0; r < reps; ++r)
-      if (launch_generate(v, d_states, nullptr, n, count, RANMAR_F32, d_out, count, st) != hipSuccess) goto done;
-    hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) goto done;
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    const double per = ms / reps;
-    if (ms_out) ms_out[v] = per;
-    if (per < best) {
-      best = per;
-      best_v = v;
-    }
-  }
+  best_v = time_variants(
+      nv, [&](int v) { return launch_generate(v, d_states, nullptr, n, count, RANMAR_F32, d_out, count, st); },
+      ms_out, e0, e1, st);
+  if (best_v < 0) goto done;
   {
     std::lock_guard<std::mutex> g(g_mu);
     g_table[{kernel, ilog2(n), ilog2(count)}] = best_v;
