@@ -167,8 +167,9 @@ int ranmar_jump_family(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n
  * describes no such warm-up, and 0 is its own convention.  seed must be in
  * [1, 9e8], discard_first 0 or 1, and first_rank * J + discard_first below
  * 2^128, else RANMAR_EINVAL (nothing launched).  Seeding and every jump run on
- * the GPU (one seed-and-jump record, then ranmar_jump_family around it).
- * d_out: n_ranks records, 4-byte aligned. */
+ * the GPU: with the product-form family the seeding happens inside its first
+ * launch, otherwise one seed-and-jump record is made and the family built
+ * around it.  d_out: n_ranks records, 4-byte aligned. */
 int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64_t n_ranks, int discard_first,
                         ranmar_state *d_out, void *stream);
 
@@ -339,9 +340,11 @@ int ranmar_tune_set(int kernel, int variant);
 /* Times every variant of `kernel` on synthetic data of the given shape
  * (n streams/requests; count = draws, jump bits, or for RANMAR_K_FAMILY
  * log2 of the spacing delta) on `stream`, stores the
- * winner for the shape bucket and writes the per-variant mean time (ms) to
+ * winner for the shape bucket (log2 n, log2 count) and writes the per-variant
+ * time (ms per launch, the best of several passes over all variants) to
  * ms_out[variant] (host, ranmar_tune_variants() entries, may be NULL).
- * Returns the winning variant index, or a negative status. */
+ * Returns the winning variant index, or a negative status.  Allocates its
+ * own synthetic inputs and outputs for the duration of the call. */
 int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double *ms_out, void *stream);
 
 /* Saves / loads the tuned table (text file, one line per bucket). */

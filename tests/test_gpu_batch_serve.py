@@ -321,7 +321,7 @@ def test_batch_splits_requests_across_bins(orc):
 
 def test_batch_jump_octets_and_pairs(orc):
     """From 16384 requests without draws the batch jumps them eight per wave
-    with 16-bit windows (octet items), after the slices with draws.  Same bits
+    with 20-bit windows (octet items), after the slices with draws.  Same bits
     as ranmar_seed_jump and the oracle; the requests with draws in the same
     batch match too."""
     n = 20000
