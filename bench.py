@@ -522,6 +522,15 @@ def main():
         r = run_serve(R, torch, a.serve_requests, a.serve_light_qps, a.serve_baseline_requests)
         also["serve_light"] = {"config": r["config"], **r["serve"]}
         _progress("serve_light done")
+        # Saturation (every request arrives at once), then 50% and 80% of the
+        # request rate the batched server sustained there.
+        r = run_serve(R, torch, a.serve_requests, 1e9, a.serve_baseline_requests)
+        also["serve_saturation"] = {"config": r["config"], **r["serve"]}
+        sat_qps = a.serve_requests / r["serve"]["batched"]["wall_s"]
+        for frac in (0.5, 0.8):
+            r = run_serve(R, torch, a.serve_requests, frac * sat_qps, a.serve_baseline_requests)
+            also[f"serve_{int(frac * 100)}pct_of_saturation"] = {"config": r["config"], **r["serve"]}
+        _progress("serve saturation sweep done")
         line["also"] = also
     if not a.no_cpu:
         _progress("cpu baseline (oracle) ...")
