@@ -172,8 +172,9 @@ struct SrcTile {
 };
 
 // Reads stay inside the output buffer: the last source record is A - 1 and
-// the furthest word read is 127 of it, below row A + 1 <= n.  Words >= 97
-// are loaded but replaced by zero (they are c or the next record).
+// the furthest word read is 127 of it, inside row A < n.  Words >= 97 are
+// loaded but replaced by zero before use (they are c or the start of the
+// next record, which another workgroup may be writing: the value is unused).
 __device__ __forceinline__ void load_tile(const uint32_t* rec, uint32_t kg, SrcTile& s) {
 #pragma unroll
   for (int kk = 0; kk < 2; ++kk) {
@@ -192,9 +193,10 @@ __device__ __forceinline__ void load_tile(const uint32_t* rec, uint32_t kg, SrcT
 
 // The product kernel.  Workgroup (x, jq): factor j = jq + 1, source tiles
 // (4 x + wave) tpw + tt.  Every wave first loads its first tile, then the
-// workgroup expands h_j into Q_j in LDS; tiles are multiplied from
-// registers and written straight from the accumulators (16 consecutive words
-// of 4 records per store; the L2 merges a tile's 6272 bytes).
+// workgroup turns h_j into the shifted limb sequences in LDS; tiles are
+// multiplied from registers and written straight from the accumulators (16
+// consecutive words of 4 records per store; the L2 merges a tile's 6272
+// bytes).  At most 168 VGPRs (three waves per SIMD).
 __global__ __launch_bounds__(256, 3) void k_family_gemm(uint32_t* out, const uint32_t* __restrict__ H, uint64_t A,
                                                      uint64_t n, uint32_t ad_mod, uint32_t tpw) {
   __shared__ __attribute__((aligned(16))) uint8_t tq[16 * kCopyStride];
