@@ -247,7 +247,7 @@ int ranmar_batch_destroy(ranmar_batch *b);
 
 typedef struct ranmar_serve_cfg {
     uint64_t max_inflight;   /* requests admitted but not released (0 = 65536) */
-    uint64_t chunk_draws;    /* draws per chunk (0 = 16384) */
+    uint64_t chunk_draws;    /* draws per chunk (0 = 8192) */
     uint64_t max_tick_chunks;/* chunks per launch (0 = 16384) */
     uint32_t lanes;          /* concurrent HIP streams for ticks (1..8, 0 = 2) */
     uint32_t queue_when_full;/* 1: over-budget requests wait; 0: EAGAIN */

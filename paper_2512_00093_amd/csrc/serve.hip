@@ -312,7 +312,9 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
   s->arena_bytes = arena_bytes & ~(kAlign - 1);
   if (cfg) s->cfg = *cfg;
   if (!s->cfg.max_inflight) s->cfg.max_inflight = 65536;
-  if (!s->cfg.chunk_draws) s->cfg.chunk_draws = 16384;
+  // 8192: measured lower p50/p99 than 16384 at 2e4 and 5e5 requests/s (more
+  // chunks of a request run at once), at the same throughput.
+  if (!s->cfg.chunk_draws) s->cfg.chunk_draws = 8192;
   if (!s->cfg.max_tick_chunks) s->cfg.max_tick_chunks = 16384;
   if (!s->cfg.lanes) s->cfg.lanes = 2;
   if (s->cfg.lanes > 8 || s->cfg.chunk_draws > (1u << 24) || s->cfg.max_tick_chunks > (1u << 22)) {
