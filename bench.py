@@ -365,6 +365,69 @@ def run_jumps1m(R, torch, steps, warmup):
     }
 
 
+def run_paper_table1(R, torch, steps, warmup):
+    """The paper's Table 1 workload on the GPU: 10^9 draws of ONE stream (seed
+    12345, uint32).  Block splitting (Sec. 1): segment k of 16,000 draws starts
+    at offset k * 16,000, so the 62,500 rows of the [62500][16000] output,
+    contiguous in memory, are the stream itself, bit for bit."""
+    p = synth.PAPER_TABLE1
+    K = p["segments"]
+    L = p["draws"] // K
+    dev = torch.device("cuda:0")
+    states = torch.empty((K, 98), dtype=torch.int32, device=dev)
+    out = torch.empty((K, L), dtype=torch.int32, device=dev)
+
+    def step():
+        R.ranmar_rank_streams(p["seed"], L, 0, K, out=states)
+        R.ranmar_generate(states, L, R.RANMAR_U24, out=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"value": p["draws"] / dt, "unit": "draws/s", "seconds_for_1e9_draws": dt,
+            "paper_seconds_cpu": {"apple": 1.27, "arm": 6.14, "ryzen": 2.07, "intel": 1.01},
+            "config": {"workload": "paper Table 1 shape: 10^9 uint32 draws of one stream (seed 12345) as 62,500 "
+                                   "segments of 16,000 jumped to their offsets and generated at once; the output "
+                                   "array is the single stream in order"}}
+
+
+def run_paper_table2(R, torch, reps=20):
+    """The paper's Table 2 workload: t^J mod phi for one all-ones J (64 and
+    120 bits), one request per launch (latency), and the full jump of one
+    state with the windowed tables."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    tm = Timer(torch)
+    res = {}
+    for J in synth.PAPER_TABLE2["jumps"]:
+        bits = J.bit_length()
+        jt = torch.from_numpy(np.array([[J & ((1 << 64) - 1), J >> 64]], dtype=np.uint64).view(np.int64)).to(dev)
+        st = R.ranmar_seed_batch(torch.tensor([12345], dtype=torch.int32, device=dev))
+        for name, fn in (("jump_poly_us", lambda: R.ranmar_jump_poly(jt)),
+                         ("windowed_jump_us", lambda: R.ranmar_jump(st, jt))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            for _ in range(reps):
+                a, e = tm.span(f"{name}{bits}")
+                a.record()
+                fn()
+                e.record()
+            torch.cuda.synchronize()
+            res.setdefault(f"J=2^{bits}-1", {})[name] = tm.mean_ms(f"{name}{bits}") * 1e3
+    res["paper_us_cpu_ntl"] = {"J=2^64-1": {"apple": 1347, "arm": 10395, "ryzen": 946, "intel": 2702},
+                               "J=2^120-1": {"apple": 2556, "arm": 21411, "ryzen": 1946, "intel": 4697}}
+    res["config"] = {"workload": "paper Table 2 shape: one all-ones J per launch; jump_poly = t^J mod phi alone "
+                                 "(square-and-multiply, one lane), windowed_jump = the whole jump of one state "
+                                 "(table factors, 32 lanes)"}
+    return res
+
+
 def run_jumps1m_batched(R, torch, steps, warmup):
     """The 10^6 seed+jump requests through the batch executor: one persistent,
     graph-launched kernel (count 0, state out)."""
@@ -533,6 +596,9 @@ def main():
             _progress(f"{name} done")
         also["jumps1m_batched"] = run_jumps1m_batched(R, torch, 5, 1)
         _progress("jumps1m_batched done")
+        also["paper_table1"] = run_paper_table1(R, torch, 5, 1)
+        also["paper_table2"] = run_paper_table2(R, torch)
+        _progress("paper tables done")
         r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_baseline_requests)
         also["serve"] = {"config": r["config"], **r["serve"]}
         _progress("serve done")

@@ -22,6 +22,10 @@ SINGLE_STREAM = dict(seed=12345, draws=1_000_000, jump=1 << 20)
 FAMILY_65K = dict(seed=4711, streams=65_536, spacing=1 << 40, draws=4_096)
 BULK_1M = dict(seed=900_000, streams=1 << 20, spacing=1 << 100, draws=1_024)
 BATCH_JUMPS = dict(requests=1_000_000, jump_bits=120)
+# The paper's own workloads (Tables 1 and 2): one stream of 10^9 draws, and
+# t^J mod phi for all-ones J of 64 and 120 bits.
+PAPER_TABLE1 = dict(seed=12345, draws=1_000_000_000, segments=62_500)  # 62,500 rows of 16,000 = 10^9 (rows of 500 x 128 B)
+PAPER_TABLE2 = dict(jumps=((1 << 64) - 1, (1 << 120) - 1))
 SERVE = dict(requests=200_000, count_log10=(2.0, 7.0), offset_bits=120, budget_bytes=64 << 30)
 
 

@@ -332,6 +332,21 @@ def test_rank_streams_rejects_bad_arguments():
         assert rc == -1, (seed, J, first, discard)
 
 
+# --- one stream by block splitting -------------------------------------------------
+@pytest.mark.parametrize("K,L", [(64, 16384), (40_000, 25), (1000, 1000)])
+def test_single_stream_by_block_splitting(orc, K, L):
+    """Sec. 1's block splitting: K segments of L draws, segment k started at
+    offset k L and written to row k of a [K][L] array, give the single
+    stream's first K L draws in order (40,000 segments take the matrix-core
+    family path)."""
+    seed = 12345
+    say(f"single stream by splitting K={K} L={L}")
+    st = R.ranmar_rank_streams(seed, L, 0, K, device=dev())
+    out = R.ranmar_generate(st, L, R.RANMAR_U24)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(out).reshape(-1), orc.int_draws(seed, K * L))
+
+
 # --- configurations at full size -------------------------------------------------
 def test_config1_single_stream(orc):
     p = synth.SINGLE_STREAM
