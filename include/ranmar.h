@@ -180,7 +180,7 @@ int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64
 /* For each stream r < n: `count` consecutive draws of Algorithm 2 starting
  * from d_in[r], written to row r of d_out (row stride `ld` elements,
  * ld >= count; element type uint32 for RANMAR_U24, float for RANMAR_F32).
- * RANMAR_U24_F32 writes every draw in both forms in one pass: uint32 k in
+ * RANMAR_U24_F32 writes every draw in both forms in one launch: uint32 k in
  * plane 0 (d_out, as for RANMAR_U24) and float k * 2^-24 in plane 1 (starting
  * n * ld elements after d_out, same row layout).
  * If d_state_out is not NULL the state after the draws is written there

@@ -15,8 +15,18 @@ __global__ __launch_bounds__(256) void k_gen32(const uint32_t* __restrict__ sin,
   const uint32_t l = lane & 31u;
   const uint64_t s = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2u + (lane >> 5);
   if (s >= n) return;  // a whole half-wave leaves together; shifts stay inside a half
-  gen_stream32<FMT, NT>(l, lane, sin + s * kWords, sout ? sout + s * kWords : nullptr, count, FMT == RANMAR_F32,
-                        (char*)out + s * ld * 4u, plane);
+  const uint32_t* W = sin + s * kWords;
+  char* row = (char*)out + s * ld * 4u;
+  if constexpr (FMT == RANMAR_U24_F32) {
+    // Both formats as two sweeps over the stream from the same start state
+    // (uint32 row, then float row), so that a half-wave has one row in
+    // flight at a time, as with one format.
+    const StreamRegs st = load_stream(W, l);
+    gen_regs32<RANMAR_U24, NT>(l, lane, st, W, nullptr, count, false, row);
+    gen_regs32<RANMAR_F32, NT>(l, lane, st, W, sout ? sout + s * kWords : nullptr, count, true, row + plane * 4u);
+  } else {
+    gen_stream32<FMT, NT>(l, lane, W, sout ? sout + s * kWords : nullptr, count, FMT == RANMAR_F32, row, plane);
+  }
 }
 
 // Several streams per half-wave: half-wave h takes streams h, h + H, h + 2H,
