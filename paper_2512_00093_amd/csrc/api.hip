@@ -67,7 +67,7 @@ static int seed_host(int64_t seed, ranmar_state* out) {
 hipError_t launch_family_variant(int v, const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out,
                                  hipStream_t st) {
   hipError_t e = hipErrorInvalidValue;
-  if (v == FAMILY_GEMM) e = launch_family_gemm(base, delta, n, out, st);
+  if (v == FAMILY_GEMM || v == FAMILY_GEMM32) e = launch_family_gemm(base, delta, n, out, st, v == FAMILY_GEMM32 ? 32 : 16);
   if (e == hipErrorInvalidValue) e = launch_family_window(base, delta, n, out, st);
   if (e == hipErrorInvalidValue) e = launch_family(base, delta, n, out, st);
   return e;
@@ -180,9 +180,11 @@ int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   const ranmar_u128 e0{(uint64_t)E0, (uint64_t)(E0 >> 64)};
-  if (n_ranks > 1 && family_variant_for(n_ranks) == FAMILY_GEMM) {
+  const int fv = n_ranks > 1 ? family_variant_for(n_ranks) : FAMILY_RADIX;
+  if (fv == FAMILY_GEMM || fv == FAMILY_GEMM32) {
     // Seeding inside the product form's first launch (one launch fewer).
-    const hipError_t g = launch_family_gemm_seeded(seed, e0, J, n_ranks, (uint32_t*)d_out, st);
+    const hipError_t g =
+        launch_family_gemm_seeded(seed, e0, J, n_ranks, (uint32_t*)d_out, st, fv == FAMILY_GEMM32 ? 32 : 16);
     if (g != hipErrorInvalidValue) return hip_status(g);
   }
   hipError_t e = launch_seed_jump_one((uint32_t*)d_out, seed, e0, st);

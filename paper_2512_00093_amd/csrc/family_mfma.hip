@@ -317,6 +317,173 @@ __global__ __launch_bounds__(256, 3) void k_family_gemm(uint32_t* out, const uin
   }
 }
 
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// One 32-row tile's sources for v_mfma_i32_32x32x32_i8: lane (mrow = l mod 32,
+// kg = l / 32) holds words 32 kk + 16 kg + e (kk < 3, e < 16) of record
+// i0 + mrow, all below 96, and the record's word 96 and c.  Every read is
+// inside the record.
+struct SrcTile32 {
+  uint32_t w[3][16];
+  uint32_t w96, c;
+};
+
+__device__ __forceinline__ void load_tile32(const uint32_t* rec, uint32_t kg, SrcTile32& s) {
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    const u32x4a* p = (const u32x4a*)(rec + kk * 32 + kg * 16);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const u32x4a v = p[d];
+      s.w[kk][4 * d] = v.x;
+      s.w[kk][4 * d + 1] = v.y;
+      s.w[kk][4 * d + 2] = v.z;
+      s.w[kk][4 * d + 3] = v.w;
+    }
+  }
+  s.w96 = rec[96];
+  s.c = rec[97];
+}
+
+// The product kernel with 32 x 32 x 32 int8 MFMAs (lane layouts checked on
+// the device with a probe: A and B by row / column l mod 32 and
+// k = 16 (l / 32) + 0..15; accumulator i of lane l is row
+// 8 (i / 4) + 4 (l / 32) + i mod 4, column l mod 32).  The matrix cores take
+// rows and columns 0..95 of Q_j (three K-steps of 32, the first two in the
+// band r <= 63, the third in r >= 64; three column tiles of 32); the VALU
+// adds row 96 (W[s][96] Q_j[96][o] with Q_j[96][o] = h[o]) and computes column
+// 96 (a dot product of length 97 with Q_j[r][96] = h[192 - r] + [r <= 63]
+// h[159 - r]).  Tiles of 32 starts; B operands from the same shifted limb
+// sequences as k_family_gemm.
+__global__ __launch_bounds__(256, 2) void k_family_gemm32(uint32_t* out, const uint32_t* __restrict__ H, uint64_t A,
+                                                       uint64_t n, uint32_t ad_mod, uint32_t tpw) {
+  __shared__ __attribute__((aligned(16))) uint8_t tq[16 * kCopyStride];
+  __shared__ __attribute__((aligned(16))) uint8_t tb[6 * kBaseLen];
+  __shared__ __attribute__((aligned(16))) uint32_t hl[196];
+  __shared__ __attribute__((aligned(16))) uint32_t qcol[128];  // Q_j[r][96], r < 97 (rest 0)
+  __shared__ __attribute__((aligned(16))) uint32_t w96s[4][32];  // per wave: word 96 of the tile's rows
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t mrow = lane & 31u, kg = lane >> 5;
+  const uint64_t jq = blockIdx.y, j = jq + 1;
+  const uint64_t tiles = A / 32;
+  const uint64_t tile0 = ((uint64_t)blockIdx.x * 4 + wave) * tpw;
+  auto tile_ok = [&](uint64_t tile) { return tile < tiles && j * A + tile * 32 < n; };
+  SrcTile32 cur;
+  if (tile_ok(tile0)) load_tile32(out + (tile0 * 32 + mrow) * kWords, kg, cur);
+  if (threadIdx.x < 193) hl[threadIdx.x] = H[jq * kHWords + threadIdx.x];
+  __syncthreads();
+  {  // the six limb sequences (entry m = threadIdx.x) and Q_j's column 96
+    const int m = (int)threadIdx.x, i1 = 208 - m, i2 = 175 - m;
+    const uint32_t va = (i1 >= 0 && i1 <= 192) ? hl[i1] : 0u;
+    const uint32_t vb = (va + ((i2 >= 0 && i2 <= 192) ? hl[i2] : 0u)) & kMask;
+    int a0, a1, a2, b0, b1, b2;
+    limbs3(vb, b0, b1, b2);  // rows r <= 63
+    limbs3(va, a0, a1, a2);  // rows r >= 64
+    tb[0 * kBaseLen + m] = (uint8_t)b0;
+    tb[1 * kBaseLen + m] = (uint8_t)b1;
+    tb[2 * kBaseLen + m] = (uint8_t)b2;
+    tb[3 * kBaseLen + m] = (uint8_t)a0;
+    tb[4 * kBaseLen + m] = (uint8_t)a1;
+    tb[5 * kBaseLen + m] = (uint8_t)a2;
+    if (m < 128) qcol[m] = m < 97 ? (hl[192 - m] + (m <= 63 ? hl[159 - m] : 0u)) & kMask : 0u;
+  }
+  __syncthreads();
+  {
+    const uint32_t* tb32 = (const uint32_t*)tb;
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane(wave);
+#pragma unroll
+    for (uint32_t k = 0; k < 24; ++k) {
+      const uint32_t it = w0 + 4 * k, c = it / 6, cb = it % 6;
+      if (lane < kSeqLen / 4) {
+        const uint32_t wi = cb * (kBaseLen / 4) + (c >> 2) + lane;
+        const uint32_t w = __builtin_amdgcn_alignbyte(tb32[wi + 1], tb32[wi], c & 3u);
+        *(uint32_t*)(tq + c * kCopyStride + cb * kSeqLen + 4 * lane) = w;
+      }
+    }
+  }
+  __syncthreads();  // every wave reaches the three barriers
+  const uint32_t jm = (uint32_t)(j * ad_mod % kMod);
+  // B operands: column o = 32 nt + mrow, K-step kk, lane group kg: entries
+  // m0 = 112 - o + 32 kk + 16 kg of copy c = (16 - mrow mod 16) mod 16, at
+  // byte m0 - c = qbase + 32 (2 - nt) + 32 kk of sequence (band, b).
+  const uint32_t cq = (16u - (mrow & 15u)) & 15u;
+  const uint32_t qbase = ((mrow & 15u) == 0 ? 112u : 96u) - 16u * ((mrow >> 4) & 1u) + 16u * kg - 64u;
+  const uint8_t* qb = tq + cq * kCopyStride + qbase;
+  uint32_t* w96w = w96s[wave];
+  for (uint32_t tt = 0; tt < tpw; ++tt) {
+    const uint64_t tile = tile0 + tt;
+    if (!tile_ok(tile)) break;  // and so are the later tiles
+    const uint64_t s0 = j * A + tile * 32;
+    v4i a[3][3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        uint32_t x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = limb_bytes(cur.w[kk][4 * d + e]);
+        const uint32_t lo01 = __builtin_amdgcn_perm(x[1], x[0], 0x05010400u);
+        const uint32_t lo23 = __builtin_amdgcn_perm(x[3], x[2], 0x05010400u);
+        const uint32_t hi01 = __builtin_amdgcn_perm(x[1], x[0], 0x0C0C0602u);
+        const uint32_t hi23 = __builtin_amdgcn_perm(x[3], x[2], 0x0C0C0602u);
+        a[0][kk][d] = (int)__builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+        a[1][kk][d] = (int)__builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+        a[2][kk][d] = (int)__builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+      }
+    // Column 96 of this lane's row (two lanes per row: halves of the sum).
+    uint32_t col96 = 0;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) col96 = mad24(cur.w[kk][e], qcol[kk * 32 + kg * 16 + e], col96);
+    if (kg == 0) col96 = mad24(cur.w96, qcol[96], col96);
+    col96 += (uint32_t)__shfl_xor((int)col96, 32, 64);
+    const uint32_t c_src = cur.c;
+    if (kg == 0) w96w[mrow] = cur.w96;
+    wave_sync();
+    uint32_t w96r[16];  // word 96 of the accumulator rows 8 (i / 4) + 4 kg + i mod 4
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w96r[i] = w96w[8 * (i / 4) + 4 * kg + (i % 4)];
+    if (tt + 1 < tpw && tile_ok(tile + 1)) load_tile32(out + ((tile + 1) * 32 + mrow) * kWords, kg, cur);
+    const uint32_t rows = (uint32_t)(n - s0 < 32 ? n - s0 : 32);  // s0 < n: checked above
+    uint32_t* dst = out + s0 * kWords;
+    uint32_t* lp = dst + 4 * kg * kWords + mrow;  // row 4 kg, column mrow; the rest are constant offsets
+#pragma unroll
+    for (int nt = 0; nt < 3; ++nt) {
+      v4i q[3][3];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          q[b][kk] = *(const v4i*)(qb + (kk < 2 ? 0 : 3 * kSeqLen) + b * kSeqLen + (2 - nt) * 32 + kk * 32);
+      v16i acc0 = {}, acc1 = {}, acc2a = {}, acc2b = {};
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0][kk], q[0][kk], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0][kk], q[1][kk], acc1, 0, 0, 0);
+        acc2a = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0][kk], q[2][kk], acc2a, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1][kk], q[0][kk], acc1, 0, 0, 0);
+        acc2b = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1][kk], q[1][kk], acc2b, 0, 0, 0);
+        acc2a = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2][kk], q[0][kk], acc2a, 0, 0, 0);
+      }
+      const uint32_t q96 = hl[32 * nt + mrow];  // Q_j[96][o] = h[o]
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        uint32_t y = (uint32_t)acc0[i] + ((uint32_t)acc1[i] << 8) + ((uint32_t)(acc2a[i] + acc2b[i]) << 16);
+        y = mad24(w96r[i], q96, y) & kMask;
+        const uint32_t row = 8 * (i / 4) + 4 * kg + (i % 4);
+        if (row < rows) lp[(8 * (i / 4) + (i % 4)) * kWords + 32 * nt] = y;
+      }
+    }
+    // Column 96 and c (Sec. 3.2: c_i jumped by j A delta) of the tile's rows.
+    if (kg == 0 && mrow < rows) {
+      dst[mrow * kWords + 96] = col96 & kMask;
+      dst[mrow * kWords + 97] = c_jump(c_src, jm);
+    }
+    wave_sync();  // w96w is rewritten by the next tile
+  }
+}
+
 }  // namespace
 
 // Returns hipErrorInvalidValue (nothing launched) when the family is too small
@@ -324,14 +491,15 @@ __global__ __launch_bounds__(256, 3) void k_family_gemm(uint32_t* out, const uin
 // bits.  Starts from `base` (seed == 0, E0 == 0) or from the state of `seed`
 // at offset E0.
 static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n,
-                              uint32_t* out, hipStream_t st) {
+                              uint32_t* out, hipStream_t st, uint32_t tr) {
   const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
   const unsigned __int128 E0 = ((unsigned __int128)e0.hi << 64) | e0.lo;
   const unsigned __int128 kMax = ~(unsigned __int128)0;
   if (n < 2 || D > (kMax - E0) / (n - 1)) return hipErrorInvalidValue;
-  // A ~ sqrt(n): A direct jumps plus B - 1 factor jumps.
-  uint64_t A = (uint64_t)std::ceil(std::sqrt((double)n) / 16.0) * 16;
-  if (A < 16) A = 16;
+  // A ~ sqrt(n) (a multiple of the tile height tr): A direct jumps plus B - 1
+  // factor jumps.
+  uint64_t A = (uint64_t)std::ceil(std::sqrt((double)n) / (double)tr) * tr;
+  if (A < tr) A = tr;
   if (2 * A > n) return hipErrorInvalidValue;
   const uint64_t B = (n + A - 1) / A;
   const uint64_t njobs = A + (B - 1);
@@ -339,15 +507,14 @@ static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0
   // at most eight (a workgroup builds its factor's sequences once).
   int dev = 0, cus = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_family_gemm, 256, 0) != hipSuccess ||
-      per_cu <= 0)
-    per_cu = 2;
+  const void* kern = tr == 32 ? (const void*)k_family_gemm32 : (const void*)k_family_gemm;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu <= 0) per_cu = 2;
   const uint64_t slots = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)per_cu;  // resident workgroups
-  const uint64_t all_tiles = (B - 1) * (A / 16);
+  const uint64_t all_tiles = (B - 1) * (A / tr);
   const uint64_t want = (all_tiles + 4 * slots - 1) / (4 * slots);
   const uint32_t tpw = (uint32_t)(want < 1 ? 1 : (want > 8 ? 8 : want));
   const uint64_t wg_tiles = 4 * (uint64_t)tpw;  // source tiles per workgroup
-  const uint64_t gx = (A / 16 + wg_tiles - 1) / wg_tiles;
+  const uint64_t gx = (A / tr + wg_tiles - 1) / wg_tiles;
   if ((njobs + 7) / 8 > 0x7FFFFFFFull || gx > 0x7FFFFFFFull || B - 1 > 65535) return hipErrorInvalidValue;
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
@@ -360,21 +527,26 @@ static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0
                      (uint32_t)(seed == 0 && base == out ? 1 : 0), seed, e0.lo, e0.hi);
   e = hipGetLastError();
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_family_gemm, dim3((unsigned)gx, (unsigned)(B - 1)), dim3(256), 0, st, out, H, A, n,
-                       (uint32_t)(AD % kMod), tpw);
+    if (tr == 32)
+      hipLaunchKernelGGL(k_family_gemm32, dim3((unsigned)gx, (unsigned)(B - 1)), dim3(256), 0, st, out, H, A, n,
+                         (uint32_t)(AD % kMod), tpw);
+    else
+      hipLaunchKernelGGL(k_family_gemm, dim3((unsigned)gx, (unsigned)(B - 1)), dim3(256), 0, st, out, H, A, n,
+                         (uint32_t)(AD % kMod), tpw);
     e = hipGetLastError();
   }
   const hipError_t f = hipFreeAsync(H, st);
   return e != hipSuccess ? e : f;
 }
 
-hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st) {
-  return family_gemm(base, 0, ranmar_u128{0, 0}, delta, n, out, st);
+hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st,
+                              uint32_t tile_rows) {
+  return family_gemm(base, 0, ranmar_u128{0, 0}, delta, n, out, st, tile_rows == 32 ? 32u : 16u);
 }
 
 hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,
-                                     hipStream_t st) {
-  return family_gemm(nullptr, seed, e0, delta, n, out, st);
+                                     hipStream_t st, uint32_t tile_rows) {
+  return family_gemm(nullptr, seed, e0, delta, n, out, st, tile_rows == 32 ? 32u : 16u);
 }
 
 }  // namespace ranmar

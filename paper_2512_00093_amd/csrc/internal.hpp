@@ -33,15 +33,18 @@ hipError_t launch_seed_jump_one(uint32_t* out, int32_t seed, ranmar_u128 E, hipS
 hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
 // Family as a matrix product on the matrix cores; hipErrorInvalidValue if
 // the family is too small for it or an exponent needs > 128 bits.
-hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
+// tile_rows: 16 (v_mfma_i32_16x16x64_i8) or 32 (v_mfma_i32_32x32x32_i8).
+hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st,
+                              uint32_t tile_rows);
 // The same family around the state of a (checked) seed at offset e0: the
 // seeding happens inside the first launch.
 hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,
-                                     hipStream_t st);
+                                     hipStream_t st, uint32_t tile_rows);
 enum FamilyVariant : int {
   FAMILY_RADIX = 0,  // radix-256 rounds, one table application per start (VALU)
-  FAMILY_GEMM = 1,   // ~sqrt(n) direct starts and factors, the rest as int8 MFMA products
-  FAMILY_NUM_VARIANTS = 2
+  FAMILY_GEMM = 1,   // ~sqrt(n) direct starts and factors, the rest as int8 MFMA products (16 x 16 x 64)
+  FAMILY_GEMM32 = 2, // the same with 32 x 32 x 32 MFMAs and row / column 96 on the VALU
+  FAMILY_NUM_VARIANTS = 3
 };
 int family_variant_for(uint64_t n);
 // A family with the given variant, falling back (radix rounds, then the

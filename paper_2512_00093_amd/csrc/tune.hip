@@ -53,10 +53,12 @@ int family_variant_for(uint64_t n) {
   if (g_forced[RANMAR_K_FAMILY] >= 0) return g_forced[RANMAR_K_FAMILY];
   auto it = g_table.find({RANMAR_K_FAMILY, ilog2(n), 0});
   if (it != g_table.end()) return it->second;
-  // Measured: the product form wins on 65,536 starts (0.023 ms against
-  // 0.036 ms) and 2^20 (0.15 ms against 0.39 ms), and loses on 16,384
-  // (0.020 ms against 0.018 ms).
-  return n >= 32768 ? FAMILY_GEMM : FAMILY_RADIX;
+  // Measured (ms; radix rounds / 16-row product / 32-row product): 16,384
+  // starts 0.018 / 0.017 / 0.022; 65,536: 0.035 / 0.025 / 0.022; 262,144:
+  // 0.106 / 0.044 / 0.044; 2^20: 0.35 / 0.148 / 0.168 (the 32-row kernel
+  // holds two waves per SIMD, the 16-row one four).
+  if (n < 32768) return FAMILY_RADIX;
+  return n < 524288 ? FAMILY_GEMM32 : FAMILY_GEMM;
 }
 
 int gen_variant_for(uint64_t n, uint64_t count) {
@@ -209,6 +211,7 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW20) return "lanes8_window20";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_RADIX) return "radix256_valu";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM) return "product_mfma_i8";
+  if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM32) return "product_mfma32_i8";
   return nullptr;
 }
 

@@ -218,18 +218,19 @@ def test_generate_both_formats(orc, n, count, ld):
         R.ranmar_tune_set(R.RANMAR_K_GENERATE, -1)
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["radix_valu", "product_mfma"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["radix_valu", "product_mfma", "product_mfma32"])
 @pytest.mark.parametrize("n,delta", [(8192, 1 << 40), (9999, (1 << 40) + 12345), (70_001, 1 << 40),
                                      (5000, (1 << 115) + 12345), (300, 1 << 40), (33, (1 << 40) + 5),
                                      (31, 12345), (32_768, 1 << 40), (131_071, 3)])
 def test_family_variants(orc, variant, n, delta):
-    """Both family variants against independent jumps: radix rounds on the
+    """Every family variant against independent jumps: radix rounds on the
     VALU, and the matrix product (about sqrt(n) direct starts and as many
-    shared factors, the rest as int8 MFMA products of signed digits).  The
-    product form covers ragged last blocks (70,001; 131,071; 33, whose last
-    factor holds one start), 15-digit factors (2^115 spacing) and the
-    default switch-over size (32,768); n = 31 is below its minimum (two
-    blocks of 16) and falls back to the radix rounds."""
+    shared factors, the rest as int8 MFMA products of signed digits, in
+    16- or 32-row tiles).  The product forms cover ragged last blocks
+    (70,001; 131,071; 33, whose last factor holds one start), 15-digit
+    factors (2^115 spacing) and the default switch-over size (32,768); below
+    two blocks of tile height (n = 31, and n = 33 for 32-row tiles) they
+    fall back to the radix rounds."""
     base = orc.state_from_seed(4711)
     R.ranmar_tune_set(R.RANMAR_K_FAMILY, variant)
     try:
@@ -243,7 +244,7 @@ def test_family_variants(orc, variant, n, delta):
         assert np.array_equal(u32(fam[k]), orc.jump(base, k * delta)), k
 
 
-@pytest.mark.parametrize("variant,n", [(0, 600), (1, 600), (1, 40_000)])
+@pytest.mark.parametrize("variant,n", [(0, 600), (1, 600), (1, 40_000), (2, 600), (2, 40_000)])
 def test_family_in_place(orc, variant, n):
     """d_base == d_out: the family is built around its own first record."""
     delta = (1 << 40) + 7
