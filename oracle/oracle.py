@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ranmar_oracle.c")
+_SRC_LFG = os.path.join(_HERE, "lfg_oracle.c")  # general (r, s, e, m, d) generator
 _BUILD_DIR = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_BUILD_DIR, "libranmar_oracle.so")
 
@@ -34,9 +35,10 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc into oracle/_build/."""
     os.makedirs(_BUILD_DIR, exist_ok=True)
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_LFG))
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", _SRC, _SRC_LFG, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -67,6 +69,13 @@ def lib():
             "orc_seed_jump_many": (ctypes.c_int, [u64, i64p, u64p, u64p, u32p]),
             "orc_draws_many": (None, [u64, u32p, u64, u32p, u64, u32p]),
             "orc_xpow_many": (None, [u64, u64p, u64p, u32p]),
+            "lfg_check": (ctypes.c_int, [u32, u32, u32, u32, u32]),
+            "lfg_step": (None, [u32, u32, u32, u32, u32, u32p, u32, u64, u32p, u32p]),
+            "lfg_draws_many": (None, [u32, u32, u32, u32, u32, u64, u32p, u64, u32p, u64, u32p]),
+            "lfg_jump_many": (None, [u32, u32, u32, u32, u32, u64, u32p, u64p, u64p, u32p]),
+            "lfg_xpow_many": (None, [u32, u32, u32, u64, u64p, u64p, u32p]),
+            "lfg_apply": (None, [u32, u32, u32, u32p, u32p, u32p]),
+            "lfg_c_jump": (u32, [u32, u32, u32, u64, u64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -230,3 +239,81 @@ def xpow_many(jumps) -> np.ndarray:
     P = np.zeros((n, 97), np.uint32)
     lib().orc_xpow_many(n, _p(lo, ctypes.c_uint64), _p(hi, ctypes.c_uint64), _u32(P))
     return P
+
+
+# --- general generator of Sec. 2 (arbitrary r, s, e, m, d) ------------------
+class LFG:
+    """Oracle for the combined generator with lags (r, s), precision e and the
+    arithmetic sequence (m, d) of Sec. 2; state records are r + 1 words
+    (u_1..u_r, u_1 oldest, then c).  Wraps ``lfg_oracle.c``."""
+
+    def __init__(self, r: int, s: int, e: int, m: int, d: int):
+        if lib().lfg_check(r, s, e, m, d):
+            raise ValueError("invalid generator parameters (r=%d s=%d e=%d m=%d d=%d)" % (r, s, e, m, d))
+        self.r, self.s, self.e, self.m, self.d = r, s, e, m, d
+        self.mask = (1 << e) - 1
+
+    @property
+    def args(self):
+        return (self.r, self.s, self.e, self.m, self.d)
+
+    def _states(self, states):
+        return np.ascontiguousarray(states, np.uint32).reshape(-1, self.r + 1)
+
+    def step(self, state, J: int) -> np.ndarray:
+        """f^J applied one transition at a time (Sec. 2)."""
+        state = np.ascontiguousarray(state, np.uint32)
+        W = np.zeros(self.r, np.uint32)
+        c = np.zeros(1, np.uint32)
+        lib().lfg_step(*self.args, _u32(state), int(state[self.r]), J, _u32(W), _u32(c))
+        return np.concatenate([W, c])
+
+    def draws_many(self, states, count: int, want_states: bool = True):
+        """(out[n, count], states after) for n independent streams."""
+        states = self._states(states)
+        n = states.shape[0]
+        out = np.zeros((n, count), np.uint32)
+        st = np.zeros((n, self.r + 1), np.uint32) if want_states else None
+        lib().lfg_draws_many(*self.args, n, _u32(states), count, _u32(out), count, _u32(st))
+        return out, st
+
+    def xpow_many(self, jumps) -> np.ndarray:
+        """P_J = t^J mod (t^r + t^(r-s) - 1) over Z/2^e, one row per J."""
+        n = len(jumps)
+        lo = np.zeros(n, np.uint64)
+        hi = np.zeros(n, np.uint64)
+        for q, J in enumerate(jumps):
+            lo[q], hi[q] = split_u128(int(J))
+        P = np.zeros((n, self.r), np.uint32)
+        lib().lfg_xpow_many(self.r, self.s, self.e, n, _p(lo, ctypes.c_uint64), _p(hi, ctypes.c_uint64), _u32(P))
+        return P
+
+    def xpow(self, J: int) -> np.ndarray:
+        return self.xpow_many([J])[0]
+
+    def apply(self, W, P) -> np.ndarray:
+        W = np.ascontiguousarray(np.asarray(W)[: self.r], np.uint32)
+        P = np.ascontiguousarray(P, np.uint32)
+        out = np.zeros(self.r, np.uint32)
+        lib().lfg_apply(self.r, self.s, self.e, _u32(W), _u32(P), _u32(out))
+        return out
+
+    def c_jump(self, c: int, J: int) -> int:
+        lo, hi = split_u128(J)
+        return int(lib().lfg_c_jump(self.m, self.d, c, lo, hi))
+
+    def jump_many(self, states, jumps) -> np.ndarray:
+        """f^J by the polynomial route (Sec. 3.1 and 3.2), one J per state."""
+        states = self._states(states)
+        n = states.shape[0]
+        lo = np.zeros(n, np.uint64)
+        hi = np.zeros(n, np.uint64)
+        for q, J in enumerate(jumps):
+            lo[q], hi[q] = split_u128(int(J))
+        out = np.zeros_like(states)
+        lib().lfg_jump_many(*self.args, n, _u32(states), _p(lo, ctypes.c_uint64), _p(hi, ctypes.c_uint64),
+                            _u32(out))
+        return out
+
+
+RANMAR_PARAMS = (R, S, E, MOD, D)

@@ -95,3 +95,43 @@ def serve_requests(n: int, qps: float, offset: int = 5, count_log10=(2.0, 7.0), 
     lo, hi = u128_uniform(g, n, bits)
     counts = np.floor(10.0 ** g.uniform(count_log10[0], count_log10[1], size=n)).astype(np.uint64)
     return dict(arrival=arrival, seeds=s, off_lo=lo, off_hi=hi, counts=counts)
+
+
+# General lagged-Fibonacci generators (Sec. 2 with other (r, s), precision e
+# and arithmetic-sequence constants (m, d); Sec. 5 anticipates larger r).
+# name -> (r, s, e, m, d).  (r, s) pairs whose trinomial t^r + t^(r-s) + 1 is
+# primitive over GF(2) are the classic long-period choices (97/33 is RANMAR's,
+# 55/24 the lags of the subtractive generator in Knuth's TAOCP, and 607/273,
+# 1279/418, 4423/2098 have Mersenne-prime degree); the small ones cover the
+# shapes a kernel must handle (s = 1, s = r - 1, s > r/2, e = 1, e = 32, m = 1).
+LFG_CASES = {
+    "ranmar": (97, 33, 24, 16777213, 7654321),
+    "r2s1e3": (2, 1, 3, 7, 3),
+    "r5s1e8": (5, 1, 8, 251, 100),
+    "r5s4e8": (5, 4, 8, 241, 7),
+    "r7s3e8": (7, 3, 8, 251, 17),
+    "r7s6e1": (7, 6, 1, 1, 0),
+    "r10s7e16": (10, 7, 16, 65521, 4321),
+    "r17s3e32": (17, 3, 32, 4294967291, 2654435761),
+    "r31s28e16": (31, 28, 16, 65521, 999),
+    "r33s32e24": (33, 32, 24, 16777213, 12345),
+    "r55s24e32": (55, 24, 32, 4294967291, 2654435761),
+    "r97s64e24": (97, 64, 24, 16777213, 7654321),
+    "r607s273e24": (607, 273, 24, 16777213, 7654321),
+    "r1279s418e32": (1279, 418, 32, 4294967291, 2654435761),
+    "r4423s2098e24": (4423, 2098, 24, 16777213, 7654321),
+}
+# Throughput workload of the general path: 65,536 streams of the r = 1279
+# generator, 4,096 draws each (the family65k shape at a 13x larger state).
+LFG_GEN = dict(case="r1279s418e32", streams=65_536, draws=4_096)
+LFG_JUMPS = dict(case="r1279s418e32", jumps=4_096, jump_bits=120)
+
+
+def lfg_states(r: int, e: int, m: int, n: int, offset: int = 10) -> np.ndarray:
+    """n state records of r + 1 uint32 words: r words uniform on [0, 2^e),
+    then c uniform on [0, m)."""
+    g = rng(offset)
+    out = np.empty((n, r + 1), np.uint32)
+    out[:, :r] = g.integers(0, 1 << e, size=(n, r), dtype=np.uint64).astype(np.uint32)
+    out[:, r] = g.integers(0, m, size=n, dtype=np.uint64).astype(np.uint32)
+    return out
