@@ -318,6 +318,54 @@ int ranmar_serve_replay(ranmar_server *s, uint64_t n, const double *t_arrival_s,
                         const ranmar_u128 *offsets, const uint64_t *counts, int fmt, double *latency_ns);
 
 /* ------------------------------------------------------------------------ */
+/* General lagged-Fibonacci generators (Sec. 2 with other parameters; Sec. 5 */
+/* anticipates a larger order r)                                             */
+/* ------------------------------------------------------------------------ */
+
+/* The combined generator of Sec. 2 with lags (r, s), precision e and the
+ * arithmetic sequence (m, d), M = 2^e:
+ *     x_n = x_{n-r} - x_{n-s} mod 2^e,   c_n = c_{n-1} - d mod m,
+ * each draw being (x_n - c_n) mod 2^e after both have stepped.  RANMAR is
+ * (97, 33, 24, 2^24 - 3, 7654321); the entry points above serve it faster.
+ * Valid parameters: 2 <= r <= RANMAR_LFG_MAX_R, 1 <= s < r, 1 <= e <= 32,
+ * 1 <= m < 2^e (any m >= 1 when e = 32), d < m.  m need not be prime.
+ * State records are r + 1 uint32 words: x[0] = u_1 (the oldest word) ..
+ * x[r-1] = u_r, then c; packed, 4-byte aligned.  Words are taken mod 2^e on
+ * input; c must be < m. */
+typedef struct ranmar_lfg_params {
+    uint32_t r, s, e, m, d;
+} ranmar_lfg_params;
+
+/* Largest order: the jump keeps 3r words of polynomial in LDS (60 KiB). */
+#define RANMAR_LFG_MAX_R 5120
+
+/* RANMAR_OK if the parameters are valid, else RANMAR_EINVAL (host only). */
+int ranmar_lfg_check(const ranmar_lfg_params *p);
+
+/* d_P[q*r + i] = coefficient b_i of t^J mod (t^r + t^(r-s) - 1) over Z/2^e
+ * for J = d_J[q], q < n (Sec. 3.1), each < 2^e.  Binary powering from the
+ * leading bits of J (Sec. 5: cost O(r^2 log J)).  d_J: n values; d_P: r*n
+ * uint32, not overlapping d_J. */
+int ranmar_lfg_jump_poly(const ranmar_lfg_params *p, const ranmar_u128 *d_J, uint64_t n, uint32_t *d_P,
+                         void *stream);
+
+/* d_out[q] = f^J(d_in[q]) with J = d_J[q], q < n: the words by P_J(A)
+ * (Sec. 3.1), c by (c - (J mod m) d) mod m (Sec. 3.2).  Equal to J single
+ * transitions.  d_in, d_out: n records of r + 1 words; d_out may equal d_in
+ * (in place) and must not otherwise overlap it or d_J. */
+int ranmar_lfg_jump(const ranmar_lfg_params *p, const uint32_t *d_in, uint32_t *d_out, const ranmar_u128 *d_J,
+                    uint64_t n, void *stream);
+
+/* For each stream q < n: `count` consecutive draws from d_in[q], written to
+ * row q of d_out (row stride ld >= count elements).  fmt RANMAR_U24 writes
+ * uint32 k < 2^e; RANMAR_F32 writes float k * 2^-e and needs e <= 24 (exact).
+ * If d_state_out is not NULL the state after the draws is written there (it
+ * may equal d_in; otherwise it must not overlap it).  d_out must not overlap
+ * the states. */
+int ranmar_lfg_generate(const ranmar_lfg_params *p, const uint32_t *d_in, uint32_t *d_state_out, uint64_t n,
+                        uint64_t count, int fmt, void *d_out, uint64_t ld, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Tuning                                                                     */
 /* ------------------------------------------------------------------------ */
 

@@ -75,6 +75,13 @@ class ranmar_serve_stats(ctypes.Structure):
                 ("busy_s", ctypes.c_double)]
 
 
+class ranmar_lfg_params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_uint32), ("s", ctypes.c_uint32), ("e", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("d", ctypes.c_uint32)]
+
+
+RANMAR_LFG_MAX_R = 5120
+
 _lib = None
 
 _vp = ctypes.c_void_p
@@ -109,6 +116,10 @@ _SIGS = {
     "ranmar_serve_stats_get": (_int, [_vp, ctypes.POINTER(ranmar_serve_stats)]),
     "ranmar_serve_destroy": (_int, [_vp]),
     "ranmar_serve_replay": (_int, [_vp, _u64, _vp, _vp, _vp, _vp, _int, _vp]),
+    "ranmar_lfg_check": (_int, [ctypes.POINTER(ranmar_lfg_params)]),
+    "ranmar_lfg_jump_poly": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, _u64, _vp, _vp]),
+    "ranmar_lfg_jump": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, _vp, _vp, _u64, _vp]),
+    "ranmar_lfg_generate": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, _vp, _u64, _u64, _int, _vp, _u64, _vp]),
     "ranmar_tune_variants": (_int, [_int]),
     "ranmar_tune_variant_name": (ctypes.c_char_p, [_int, _int]),
     "ranmar_tune_set": (_int, [_int, _int]),
@@ -253,6 +264,48 @@ def ranmar_generate(states_in, count: int, fmt: int = RANMAR_U24, out=None, stat
         raise ValueError("out must be a contiguous 4-byte tensor of at least planes * n * ld elements")
     _check(lib().ranmar_generate(_ptr(states_in), _ptr(states_out), n, count, fmt, _ptr(out) if count else None,
                                  ld, _stream(stream)), "ranmar_generate")
+    return out
+
+
+# --- general lagged-Fibonacci generators (any r, s, e, m, d) ------------------
+def lfg_params(r: int, s: int, e: int, m: int, d: int) -> ranmar_lfg_params:
+    p = ranmar_lfg_params(r, s, e, m, d)
+    _check(lib().ranmar_lfg_check(ctypes.byref(p)), "ranmar_lfg_check")
+    return p
+
+
+def ranmar_lfg_jump_poly(p: ranmar_lfg_params, jumps, out=None, stream=None):
+    """jumps: (n, 2) int64 device tensor of (lo, hi); returns (n, r) int32."""
+    n = jumps.shape[0]
+    if out is None:
+        out = torch.empty((n, p.r), dtype=torch.int32, device=jumps.device)
+    _check(lib().ranmar_lfg_jump_poly(ctypes.byref(p), _ptr(jumps), n, _ptr(out), _stream(stream)),
+           "ranmar_lfg_jump_poly")
+    return out
+
+
+def ranmar_lfg_jump(p: ranmar_lfg_params, states, jumps, out=None, stream=None):
+    """states: (n, r + 1) int32 device tensor; out defaults to in place."""
+    n = states.shape[0]
+    if out is None:
+        out = states
+    _check(lib().ranmar_lfg_jump(ctypes.byref(p), _ptr(states), _ptr(out), _ptr(jumps), n, _stream(stream)),
+           "ranmar_lfg_jump")
+    return out
+
+
+def ranmar_lfg_generate(p: ranmar_lfg_params, states_in, count: int, fmt: int = RANMAR_U24, out=None,
+                        states_out=None, ld=None, stream=None):
+    n = states_in.shape[0]
+    if ld is None:
+        ld = count if out is None else out.shape[-1]
+    if out is None:
+        dt = torch.float32 if fmt == RANMAR_F32 else torch.int32
+        out = torch.empty((n, ld), dtype=dt, device=states_in.device)
+    elif count and (not out.is_contiguous() or out.numel() < n * ld or out.element_size() != 4):
+        raise ValueError("out must be a contiguous 4-byte tensor of at least n * ld elements")
+    _check(lib().ranmar_lfg_generate(ctypes.byref(p), _ptr(states_in), _ptr(states_out), n, count, fmt,
+                                     _ptr(out) if count else None, ld, _stream(stream)), "ranmar_lfg_generate")
     return out
 
 

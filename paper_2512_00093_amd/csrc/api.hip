@@ -214,4 +214,53 @@ int ranmar_generate(const ranmar_state* d_in, ranmar_state* d_state_out, uint64_
                                     (hipStream_t)stream));
 }
 
+
+int ranmar_lfg_check(const ranmar_lfg_params* p) { return lfg_params_ok(p) ? RANMAR_OK : RANMAR_EINVAL; }
+
+int ranmar_lfg_jump_poly(const ranmar_lfg_params* p, const ranmar_u128* d_J, uint64_t n, uint32_t* d_P,
+                         void* stream) {
+  if (!lfg_params_ok(p)) return RANMAR_EINVAL;
+  if (n == 0) return RANMAR_OK;
+  if (!d_J || !d_P || !aligned(d_J, 8) || !aligned(d_P, 4)) return RANMAR_EINVAL;
+  if (n > (UINT64_MAX / 8) / p->r) return RANMAR_EINVAL;
+  if (overlap(d_J, 16 * n, d_P, 4ull * p->r * n)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_lfg_jump(*p, d_J, nullptr, nullptr, d_P, n, (hipStream_t)stream));
+}
+
+int ranmar_lfg_jump(const ranmar_lfg_params* p, const uint32_t* d_in, uint32_t* d_out, const ranmar_u128* d_J,
+                    uint64_t n, void* stream) {
+  if (!lfg_params_ok(p)) return RANMAR_EINVAL;
+  if (n == 0) return RANMAR_OK;
+  if (!d_in || !d_out || !d_J || !aligned(d_in, 4) || !aligned(d_out, 4) || !aligned(d_J, 8)) return RANMAR_EINVAL;
+  if (n > (UINT64_MAX / 8) / (p->r + 1)) return RANMAR_EINVAL;
+  const uint64_t sb = 4ull * (p->r + 1) * n;
+  if (d_out != d_in && overlap(d_in, sb, d_out, sb)) return RANMAR_EINVAL;
+  if (overlap(d_J, 16 * n, d_out, sb) || overlap(d_J, 16 * n, d_in, sb)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_lfg_jump(*p, d_J, d_in, d_out, nullptr, n, (hipStream_t)stream));
+}
+
+int ranmar_lfg_generate(const ranmar_lfg_params* p, const uint32_t* d_in, uint32_t* d_state_out, uint64_t n,
+                        uint64_t count, int fmt, void* d_out, uint64_t ld, void* stream) {
+  if (!lfg_params_ok(p)) return RANMAR_EINVAL;
+  if (fmt != RANMAR_U24 && fmt != RANMAR_F32) return RANMAR_EINVAL;
+  if (fmt == RANMAR_F32 && p->e > 24) return RANMAR_EINVAL;
+  if (n == 0) return RANMAR_OK;
+  if (!d_in || !aligned(d_in, 4) || (d_state_out && !aligned(d_state_out, 4))) return RANMAR_EINVAL;
+  if (count > 0 && (!d_out || !aligned(d_out, 4) || ld < count)) return RANMAR_EINVAL;
+  if (n > (UINT64_MAX / 8) / (p->r + 1) || ld > (UINT64_MAX / 8) / n) return RANMAR_EINVAL;
+  const uint64_t sb = 4ull * (p->r + 1) * n;
+  if (d_state_out && d_state_out != d_in && overlap(d_in, sb, d_state_out, sb)) return RANMAR_EINVAL;
+  if (count > 0) {
+    const uint64_t ob = 4 * (ld * (n - 1) + count);
+    if (overlap(d_out, ob, d_in, sb) || (d_state_out && overlap(d_out, ob, d_state_out, sb))) return RANMAR_EINVAL;
+  }
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_lfg_generate(*p, d_in, d_state_out, n, count, fmt, d_out, ld, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -40,6 +40,15 @@ hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t 
 // seeding happens inside the first launch.
 hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,
                                      hipStream_t st, uint32_t tile_rows);
+// General lagged-Fibonacci generators (any r, s, e, m, d).
+int lfg_params_ok(const ranmar_lfg_params* p);
+uint32_t lfg_jump_threads(uint32_t r);
+void lfg_gen_shape(uint32_t r, uint32_t s, uint32_t* lw, uint32_t* G, uint32_t* Z, uint32_t* waves);
+// P_out != nullptr: polynomials only; else states s_in -> s_out (may alias).
+hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
+                           uint32_t* P_out, uint64_t n, hipStream_t st);
+hipError_t launch_lfg_generate(const ranmar_lfg_params& p, const uint32_t* s_in, uint32_t* s_out, uint64_t n,
+                               uint64_t count, int fmt, void* out, uint64_t ld, hipStream_t st);
 enum FamilyVariant : int {
   FAMILY_RADIX = 0,  // radix-256 rounds, one table application per start (VALU)
   FAMILY_GEMM = 1,   // ~sqrt(n) direct starts and factors, the rest as int8 MFMA products (16 x 16 x 64)

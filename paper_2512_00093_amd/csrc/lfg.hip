@@ -1,0 +1,281 @@
+// General lagged-Fibonacci generators: the combined generator of Sec. 2 for
+// any lags 1 <= s < r, precision e <= 32 and arithmetic sequence (m, d), which
+// Sec. 5 anticipates for larger r.  RANMAR is (97, 33, 24, 2^24 - 3, 7654321);
+// the specialised kernels elsewhere in this library serve that case faster.
+//
+// Jump (Sec. 3.1, 3.2): P_J = t^J mod phi, phi = t^r + t^{r-s} - 1, over
+// Z/2^e by left-to-right binary powering in LDS, one workgroup per J; the new
+// words are the Hankel product sum_i b_i x_{i+l} over the state extended by
+// r - 1 steps, and c moves by the closed form (c - J d) mod m.
+//
+// Generate (Algorithm 2 with general lags): the last r words of each stream
+// live in an LDS ring of Z >= r + W words (Z a power of two); W lanes of a
+// wave (W = min(s, 64) rounded down to a power of two) produce W consecutive
+// words per step, since x_n .. x_{n+W-1} depend only on words older than x_n
+// when W <= s.  64 / W streams share a wave, and each stream's W draws of a
+// step form one contiguous store.
+//
+// Arithmetic is kept mod 2^32 and masked to e bits on output: for e <= 24 the
+// products use v_mad_u32_u24 (exact in the low 24 bits), for e > 24 the full
+// 32-bit multiply.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ranmar {
+namespace {
+
+struct LfgDev {
+  uint32_t r, s, mask, m, d;
+};
+
+__device__ __forceinline__ void lane_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool W32>
+__device__ __forceinline__ uint32_t mac(uint32_t a, uint32_t b, uint32_t acc) {
+  if constexpr (W32)
+    return a * b + acc;
+  else
+    return mad24(a, b, acc);
+}
+
+// (c - J d) mod m with J = hi 2^64 + lo; m < 2^32 so every product fits 64 bits.
+__device__ __forceinline__ uint32_t c_after(uint32_t c, ranmar_u128 J, uint32_t m, uint32_t d) {
+  const uint64_t M = m;
+  const uint64_t t32 = (1ull << 32) % M;
+  const uint64_t t64 = (t32 * t32) % M;
+  const uint64_t jm = ((J.hi % M) * t64 + J.lo % M) % M;
+  const uint64_t sub = (jm * d) % M;
+  return (uint32_t)(((uint64_t)c + M - sub) % M);
+}
+
+// Reduces Q[0 .. 2r-2] modulo phi in place (coefficients k >= r become zero
+// in effect; only Q[0 .. r-1] is read afterwards).  t^k = t^{k-r} - t^{k-s}
+// for k >= r.  The top coefficients are folded in blocks of at most s, from
+// the top: inside a block the targets k - r and k - s all lie below the
+// block, so one pass per target kind has no conflicts; the k - s targets of
+// one block may be folded again by a lower block.
+__device__ __forceinline__ void fold_phi(uint32_t* Q, int r, int s, int top, int tid, int bs) {
+  for (int hi = top; hi >= r;) {
+    const int lo = hi - s + 1 > r ? hi - s + 1 : r;
+    for (int k = lo + tid; k <= hi; k += bs) Q[k - r] += Q[k];
+    __syncthreads();
+    for (int k = lo + tid; k <= hi; k += bs) Q[k - s] -= Q[k];
+    __syncthreads();
+    hi = lo - 1;
+  }
+}
+
+// One workgroup per item.  Dynamic LDS: P[r], Q[2r] (3r words).
+// P_out != nullptr: write P_J (r words per item) and stop.
+// Otherwise: states s_in -> s_out (r + 1 words per record; may alias).
+template <bool W32>
+__global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js,
+                                                   const uint32_t* s_in, uint32_t* s_out, uint32_t* P_out,
+                                                   uint64_t n) {
+  extern __shared__ uint32_t lds[];
+  const int r = (int)g.r, s = (int)g.s;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  uint32_t* P = lds;
+  uint32_t* Q = lds + r;
+  for (uint64_t item = blockIdx.x; item < n; item += gridDim.x) {
+    const ranmar_u128 J = Js[item];
+    // Leading bits of J that form an exponent below r give a monomial start.
+    int bit = J.hi ? 127 - __builtin_clzll(J.hi) : (J.lo ? 63 - __builtin_clzll(J.lo) : -1);
+    uint32_t v = 0;
+    while (bit >= 0) {
+      const uint32_t b = bit >= 64 ? (uint32_t)(J.hi >> (bit - 64)) & 1u : (uint32_t)(J.lo >> bit) & 1u;
+      if (2 * v + b >= (uint32_t)r) break;
+      v = 2 * v + b;
+      --bit;
+    }
+    for (int i = tid; i < r; i += bs) P[i] = (i == (int)v) ? 1u : 0u;
+    __syncthreads();
+    for (; bit >= 0; --bit) {
+      // Square: Q[k] = 2 sum_{i < k-i} P_i P_{k-i} + [k even] P_{k/2}^2.
+      for (int k = tid; k < 2 * r - 1; k += bs) {
+        const int ilo = k - (r - 1) > 0 ? k - (r - 1) : 0;
+        const int ihi = (k - 1) >> 1;
+        uint32_t acc = 0;
+        for (int i = ilo; i <= ihi; ++i) acc = mac<W32>(P[i], P[k - i], acc);
+        acc <<= 1;
+        if (!(k & 1)) acc = mac<W32>(P[k >> 1], P[k >> 1], acc);
+        Q[k] = acc;
+      }
+      __syncthreads();
+      fold_phi(Q, r, s, 2 * r - 2, tid, bs);
+      const uint32_t b = bit >= 64 ? (uint32_t)(J.hi >> (bit - 64)) & 1u : (uint32_t)(J.lo >> bit) & 1u;
+      if (b) {
+        // Multiply by t: shift up one place; t^r = 1 - t^{r-s}.
+        const uint32_t topc = Q[r - 1];
+        for (int i = tid; i < r; i += bs) {
+          uint32_t x = i ? Q[i - 1] : topc;
+          if (i == r - s) x -= topc;
+          P[i] = x;
+        }
+      } else {
+        for (int i = tid; i < r; i += bs) P[i] = Q[i];
+      }
+      __syncthreads();
+    }
+    if (P_out) {
+      for (int i = tid; i < r; i += bs) P_out[item * r + i] = P[i] & g.mask;
+      __syncthreads();
+      continue;
+    }
+    // Apply: X = the r words of the state extended by r - 1 steps, in Q.
+    const uint32_t* src = s_in + item * (uint64_t)(r + 1);
+    const uint32_t c0 = src[r];
+    for (int i = tid; i < r; i += bs) Q[i] = src[i];
+    __syncthreads();
+    for (int lo = r; lo < 2 * r - 1; lo += s) {
+      const int hi = lo + s - 1 < 2 * r - 2 ? lo + s - 1 : 2 * r - 2;
+      for (int k = lo + tid; k <= hi; k += bs) Q[k] = Q[k - r] - Q[k - s];
+      __syncthreads();
+    }
+    uint32_t* dst = s_out + item * (uint64_t)(r + 1);
+    for (int l = tid; l < r; l += bs) {
+      uint32_t acc = 0;
+      for (int i = 0; i < r; ++i) acc = mac<W32>(P[i], Q[i + l], acc);
+      dst[l] = acc & g.mask;
+    }
+    if (tid == 0) dst[r] = c_after(c0, J, g.m, g.d);
+    __syncthreads();
+  }
+}
+
+// Generation.  Dynamic LDS: (waves per workgroup) x G rings of Z words, with
+// G <= 64 / W streams per wave (fewer when the rings would not fit).
+template <int FMT>
+__global__ __launch_bounds__(256) void k_lfg_gen(LfgDev g, uint32_t lw, uint32_t G, uint32_t Z, const uint32_t* s_in,
+                                                 uint32_t* s_out, uint64_t n, uint64_t count, void* out,
+                                                 uint64_t ld, float scale) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t r = g.r, s = g.s, mask = g.mask, m = g.m;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t W = 1u << lw;
+  const uint32_t grp = lane >> lw, j = lane & (W - 1u);
+  const uint64_t stream = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * G + grp;
+  const bool active = grp < G && stream < n;
+  uint32_t* ring = lds + (wave * G + (grp < G ? grp : 0u)) * Z;  // idle lanes only read
+  const uint32_t zm = Z - 1u;
+  const uint32_t* src = s_in + (active ? stream : 0) * (uint64_t)(r + 1);
+  if (active)
+    for (uint32_t i = j; i < r; i += W) ring[i] = src[i];
+  const uint32_t c0 = active ? src[r] : 0u;
+  lane_order();
+  // c before draw q + j is c_q - (j + 1) d; c_q steps by W d per step.
+  const uint32_t dj = (uint32_t)(((uint64_t)(j + 1) * g.d) % m);
+  const uint32_t dW = (uint32_t)(((uint64_t)W * g.d) % m);
+  uint32_t c = c0;
+  uint32_t pos = r;  // sequence index of the next word, kept mod 2^32 (Z divides 2^32)
+  const uint64_t row = (active ? stream : 0) * ld;
+  for (uint64_t q = 0; q < count; q += W) {
+    const bool live = active && q + j < count;
+    const uint32_t a = ring[(pos + j - r) & zm];
+    const uint32_t b = ring[(pos + j - s) & zm];
+    const uint32_t x = (a - b) & mask;
+    const uint32_t cj = c >= dj ? c - dj : c - dj + m;
+    const uint32_t k = (x - cj) & mask;
+    if (live) {
+      ring[(pos + j) & zm] = x;
+      if constexpr (FMT == 0)
+        __builtin_nontemporal_store(k, (uint32_t*)out + row + q + j);
+      else
+        __builtin_nontemporal_store((float)k * scale, (float*)out + row + q + j);
+    }
+    c = c >= dW ? c - dW : c - dW + m;
+    pos += W;
+    lane_order();
+  }
+  if (active && s_out) {
+    uint32_t* dst = s_out + stream * (uint64_t)(r + 1);
+    const uint32_t end = (uint32_t)count;  // sequence index of the oldest kept word, mod 2^32
+    for (uint32_t i = j; i < r; i += W) dst[i] = ring[(end + i) & zm];
+    if (j == 0) {
+      const uint64_t M = m;
+      const uint64_t sub = ((count % M) * g.d) % M;
+      dst[r] = (uint32_t)(((uint64_t)c0 + M - sub) % M);
+    }
+  }
+}
+
+LfgDev to_dev(const ranmar_lfg_params& p) {
+  return LfgDev{p.r, p.s, p.e >= 32 ? 0xFFFFFFFFu : ((1u << p.e) - 1u), p.m, p.d};
+}
+
+}  // namespace
+
+int lfg_params_ok(const ranmar_lfg_params* p) {
+  if (!p) return 0;
+  if (p->r < 2 || p->r > RANMAR_LFG_MAX_R || p->s < 1 || p->s >= p->r || p->e < 1 || p->e > 32) return 0;
+  const uint32_t mask = p->e >= 32 ? 0xFFFFFFFFu : ((1u << p->e) - 1u);
+  if (p->m < 1 || (p->e < 32 && p->m > mask) || p->d >= p->m) return 0;
+  return 1;
+}
+
+uint32_t lfg_jump_threads(uint32_t r) { return r <= 128 ? 128u : r <= 512 ? 256u : r <= 2048 ? 512u : 1024u; }
+
+hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
+                           uint32_t* P_out, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const LfgDev g = to_dev(p);
+  const uint32_t bs = lfg_jump_threads(p.r);
+  const size_t lds = (size_t)3 * p.r * sizeof(uint32_t);
+  const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
+  if (p.e > 24)
+    hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n);
+  else
+    hipLaunchKernelGGL(k_lfg_jump<false>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n);
+  return hipGetLastError();
+}
+
+// Launch shape of the generator: log2 of the lanes per stream, streams per
+// wave, ring words, waves per workgroup.  Every workgroup's rings fit in
+// 64 KiB: Z <= 8192 for r <= RANMAR_LFG_MAX_R, and G is capped at 16384 / Z.
+void lfg_gen_shape(uint32_t r, uint32_t s, uint32_t* lw, uint32_t* G, uint32_t* Z, uint32_t* waves) {
+  uint32_t w = 0;
+  while ((2u << w) <= s && (2u << w) <= 64u) ++w;
+  uint32_t z = 64;
+  while (z < r + (1u << w)) z <<= 1;
+  uint32_t gr = 64u >> w;
+  if (gr > 16384u / z) gr = 16384u / z;
+  if (gr < 1) gr = 1;
+  const uint32_t per_wave = gr * z * 4u;  // bytes of ring per wave, <= 64 KiB
+  uint32_t wv = 65536u / per_wave;
+  if (wv > 4) wv = 4;
+  if (wv < 1) wv = 1;
+  *lw = w;
+  *G = gr;
+  *Z = z;
+  *waves = wv;
+}
+
+hipError_t launch_lfg_generate(const ranmar_lfg_params& p, const uint32_t* s_in, uint32_t* s_out, uint64_t n,
+                               uint64_t count, int fmt, void* out, uint64_t ld, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const LfgDev g = to_dev(p);
+  uint32_t lw, G, Z, waves;
+  lfg_gen_shape(p.r, p.s, &lw, &G, &Z, &waves);
+  const uint64_t per_wg = (uint64_t)waves * G;
+  const uint64_t grid = (n + per_wg - 1) / per_wg;
+  if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const size_t lds = (size_t)waves * G * Z * sizeof(uint32_t);
+  const float scale = 1.0f / (float)(1u << (p.e < 24 ? p.e : 24));
+  if (fmt == RANMAR_F32)
+    hipLaunchKernelGGL(k_lfg_gen<1>, dim3((uint32_t)grid), dim3(64 * waves), lds, st, g, lw, G, Z, s_in, s_out, n,
+                       count, out, ld, scale);
+  else
+    hipLaunchKernelGGL(k_lfg_gen<0>, dim3((uint32_t)grid), dim3(64 * waves), lds, st, g, lw, G, Z, s_in, s_out, n,
+                       count, out, ld, scale);
+  return hipGetLastError();
+}
+
+}  // namespace ranmar

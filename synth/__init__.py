@@ -120,6 +120,7 @@ LFG_CASES = {
     "r607s273e24": (607, 273, 24, 16777213, 7654321),
     "r1279s418e32": (1279, 418, 32, 4294967291, 2654435761),
     "r4423s2098e24": (4423, 2098, 24, 16777213, 7654321),
+    "r1000s3e16": (1000, 3, 16, 65521, 77),  # large r, small s: many small rings per wave
 }
 # Throughput workload of the general path: 65,536 streams of the r = 1279
 # generator, 4,096 draws each (the family65k shape at a 13x larger state).
