@@ -78,7 +78,8 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="family65k", choices=["family65k", "bulk1m", "jumps1m", "serve"])
+    ap.add_argument("--workload", default="family65k",
+                    choices=["family65k", "bulk1m", "jumps1m", "serve", "lfg_gen", "lfg_jumps"])
     ap.add_argument("--serve-requests", type=int, default=synth.SERVE["requests"])
     ap.add_argument("--serve-qps", type=float, default=5e5)
     ap.add_argument("--serve-light-qps", type=float, default=2e4)
@@ -365,6 +366,104 @@ def run_jumps1m(R, torch, steps, warmup):
     }
 
 
+def _lfg_setup(R, torch, n, offset):
+    import numpy as np
+    cfg = synth.LFG_GEN
+    r, s_, e, m, d = synth.LFG_CASES[cfg["case"]]
+    st = synth.lfg_states(r, e, m, n, offset=offset)
+    d_st = torch.from_numpy(st.view(np.int32).copy()).to(torch.device("cuda:0"))
+    return R.lfg_params(r, s_, e, m, d), d_st
+
+
+def run_lfg_gen(R, torch, steps, warmup):
+    """General lagged-Fibonacci generation (Sec. 2 with r = 1279, s = 418,
+    e = 24): 65,536 streams x 4,096 uint32 draws per step, states advanced in
+    place.  HBM-bound: the draws are written once and each state (r + 1
+    words) is read and written once."""
+    cfg = synth.LFG_GEN
+    n, count = cfg["streams"], cfg["draws"]
+    p, d_st = _lfg_setup(R, torch, n, offset=30)
+    out = torch.empty((n, count), dtype=torch.int32, device=torch.device("cuda:0"))
+    tm = Timer(torch)
+    for _ in range(warmup):
+        R.ranmar_lfg_generate(p, d_st, count, R.RANMAR_U24, out=out, states_out=d_st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b = tm.span("lfg_gen")
+        a.record()
+        R.ranmar_lfg_generate(p, d_st, count, R.RANMAR_U24, out=out, states_out=d_st)
+        b.record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms = tm.mean_ms("lfg_gen")
+    algo = 4.0 * n * count + 2 * 4.0 * n * (p.r + 1)
+    lanes = 64
+    return {
+        "metric": "draws/s", "value": n * count / dt, "unit": "draws/s", "ms_per_step": dt * 1e3, "dtype": "u24",
+        "config": {"workload": f"lfg_gen: general lagged-Fibonacci generator (r, s, e) = ({p.r}, {p.s}, {p.e}), "
+                               f"{n} streams x {count} uint32 draws, states advanced in place", "streams": n,
+                   "draws": count},
+        "roofline": {"bound": "hbm", "kernel": "k_lfg_gen<0>", "achieved": algo / (ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("k_lfg_gen<0>", n // 4 * 4 * lanes),
+                     "bytes_per_launch": algo, "launch_ms": ms},
+    }
+
+
+def lfg_squarings(J: int, r: int) -> int:
+    """Squarings of the left-to-right powering of t after the monomial start
+    (the leading bits of J that form an exponent below r)."""
+    bit, v = J.bit_length() - 1, 0
+    while bit >= 0:
+        b = (J >> bit) & 1
+        if 2 * v + b >= r:
+            break
+        v = 2 * v + b
+        bit -= 1
+    return bit + 1
+
+
+def run_lfg_jumps(R, torch, steps, warmup):
+    """General lagged-Fibonacci jump-ahead (Sec. 3.1 and 3.2 at r = 1279,
+    Sec. 5 cost O(r^2 log J)): 4,096 states, each jumped by its own uniform
+    120-bit J, one launch.  ALU-bound: r (r + 1) / 2 multiply-adds per
+    symmetric squaring and r^2 for the final application."""
+    import numpy as np
+    jc = synth.LFG_JUMPS
+    n = jc["jumps"]
+    p, d_st = _lfg_setup(R, torch, n, offset=31)
+    lo, hi = synth.u128_uniform(synth.rng(32), n, jc["jump_bits"])
+    dev = torch.device("cuda:0")
+    jt = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
+    out = torch.empty_like(d_st)
+    tm = Timer(torch)
+    for _ in range(warmup):
+        R.ranmar_lfg_jump(p, d_st, jt, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b = tm.span("lfg_jump")
+        a.record()
+        R.ranmar_lfg_jump(p, d_st, jt, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms = tm.mean_ms("lfg_jump")
+    r = p.r
+    sq = sum(lfg_squarings(J, r) for J in synth.u128_to_int(lo, hi))
+    macs = float(sq) * r * (r + 1) / 2 + float(n) * r * r
+    ach = macs / (ms * 1e-3) / 1e12
+    return {
+        "metric": "jumps/s", "value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3, "dtype": "u24",
+        "config": {"workload": f"lfg_jumps: general lagged-Fibonacci generator (r, s, e) = ({p.r}, {p.s}, {p.e}), "
+                               f"{n} states each jumped by a uniform 120-bit J, one launch", "jumps": n},
+        "roofline": {"bound": "alu", "kernel": "k_lfg_jump<false>", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                     "unit": "T lane-ops/s (24-bit multiply-adds of the squarings and the application)",
+                     "frac": ach / VALU_PEAK_TOPS, "traffic": None, "ops_per_launch": macs, "launch_ms": ms},
+    }
+
+
 def run_paper_table1(R, torch, steps, warmup):
     """The paper's Table 1 workload on the GPU: 10^9 draws of ONE stream (seed
     12345, uint32).  Block splitting (Sec. 1): segment k of 16,000 draws starts
@@ -578,6 +677,10 @@ def main():
                           "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "config": r["config"],
                           "serve": r["serve"]}), flush=True)
         return
+    elif a.workload == "lfg_gen":
+        res = run_lfg_gen(R, torch, a.steps, a.warmup)
+    elif a.workload == "lfg_jumps":
+        res = run_lfg_jumps(R, torch, a.steps, a.warmup)
     else:
         res = run_jumps1m(R, torch, a.steps, a.warmup)
     line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"], "n_gpus": 1, "steps": a.steps,
@@ -596,6 +699,10 @@ def main():
             _progress(f"{name} done")
         also["jumps1m_batched"] = run_jumps1m_batched(R, torch, 5, 1)
         _progress("jumps1m_batched done")
+        for name, fn in (("lfg_gen", run_lfg_gen), ("lfg_jumps", run_lfg_jumps)):
+            r = fn(R, torch, 5, 1)
+            also[name] = {k: r[k] for k in r if k not in ("metric",)}
+            _progress(f"{name} done")
         also["paper_table1"] = run_paper_table1(R, torch, 5, 1)
         also["paper_table2"] = run_paper_table2(R, torch)
         _progress("paper tables done")
@@ -615,7 +722,7 @@ def main():
             also[f"serve_{int(frac * 100)}pct_of_saturation"] = {"config": r["config"], **r["serve"]}
         _progress("serve saturation sweep done")
         line["also"] = also
-    if not a.no_cpu:
+    if not a.no_cpu and a.workload not in ("lfg_gen", "lfg_jumps"):
         _progress("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -73,18 +73,103 @@ __device__ __forceinline__ void fold_phi(uint32_t* Q, int r, int s, int top, int
   }
 }
 
-// One workgroup per item.  Dynamic LDS: P[r], Q[2r] (3r words).
+// Square of P into Q[k0 .. k0 + kTile - 1] (k < 2r - 1 only):
+// Q[k] = 2 sum_{i < k - i} P_i P_{k-i} + [k even] P_{k/2}^2.  P is read through
+// a zero-padded view (P[i] = 0 for i < 0 and i >= r), so the ranges need no
+// bounds tests: blocks of kTile terms i, each with the kTile + kTile - 1 words
+// P[k0 - i ..] they meet held in registers (about 0.27 LDS reads per
+// multiply-add instead of 2).  Blocks that reach the diagonal keep a term only
+// when 2 i < k.
+constexpr int kTile = 8;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The kTile coefficients P[ib ..] and the 2 kTile - 1 words P[k0 - ib - kTile + 1 ..]
+// of one block, as 16-byte LDS reads: every start is a multiple of kTile words
+// from a 32-byte aligned base, and lanes kTile words apart hit distinct banks.
+__device__ __forceinline__ void load_block(const uint32_t* Pp, int ib, int k0, uint32_t (&a)[kTile],
+                                           uint32_t (&x)[2 * kTile - 1]) {
+  const u32x4* pa = (const u32x4*)(Pp + ib);
+  const u32x4* px = (const u32x4*)(Pp + k0 - ib - kTile);
+  uint32_t xx[2 * kTile];
+#pragma unroll
+  for (int v = 0; v < kTile / 4; ++v) {
+    const u32x4 t = pa[v];
+    a[4 * v] = t.x, a[4 * v + 1] = t.y, a[4 * v + 2] = t.z, a[4 * v + 3] = t.w;
+  }
+#pragma unroll
+  for (int v = 0; v < kTile / 2; ++v) {
+    const u32x4 t = px[v];
+    xx[4 * v] = t.x, xx[4 * v + 1] = t.y, xx[4 * v + 2] = t.z, xx[4 * v + 3] = t.w;
+  }
+#pragma unroll
+  for (int q = 0; q < 2 * kTile - 1; ++q) x[q] = xx[q + 1];
+}
+
+template <bool W32>
+__device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int r, int k0) {
+  uint32_t acc[kTile];
+#pragma unroll
+  for (int u = 0; u < kTile; ++u) acc[u] = 0;
+  const int ilo = k0 - (r - 1) > 0 ? k0 - (r - 1) : 0;
+  int ib = ilo & ~(kTile - 1);
+  const int full_max = (k0 - 1) >> 1;        // 2 i < k0 <= k: the term belongs to every output of the tile
+  const int i_end = (k0 + kTile - 2) >> 1;   // largest i any output of the tile takes
+  for (; ib + kTile - 1 <= full_max; ib += kTile) {
+    uint32_t a[kTile], x[2 * kTile - 1];
+    load_block(Pp, ib, k0, a, x);
+#pragma unroll
+    for (int q = 0; q < kTile; ++q)
+#pragma unroll
+      for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
+  }
+  for (; ib <= i_end; ib += kTile) {
+    uint32_t a[kTile], x[2 * kTile - 1];
+    load_block(Pp, ib, k0, a, x);
+#pragma unroll
+    for (int q = 0; q < kTile; ++q)
+#pragma unroll
+      for (int u = 0; u < kTile; ++u) {
+        const uint32_t t = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
+        acc[u] = 2 * (ib + q) < k0 + u ? t : acc[u];
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < kTile; ++u) {
+    const int k = k0 + u;
+    if (k < 2 * r - 1) {
+      uint32_t v = acc[u] << 1;
+      if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
+      Q[k] = v;
+    }
+  }
+}
+
+// Threads of the jump workgroup: each squares the tile pair (t, t + T/2) of
+// the T = ceil((2r - 1) / kTile) output tiles, which balances the triangular
+// work profile (tile k and tile k + r take about r / 2 terms together).
+uint32_t jump_threads(uint32_t r) {
+  const uint32_t tiles = (2 * r - 1 + kTile - 1) / kTile;
+  const uint32_t pairs = (tiles + 1) / 2;
+  return (pairs + 63) / 64 * 64;
+}
+
+// Words of dynamic LDS: padded P (kTile below, 3 kTile above) and Q[2r].
+size_t jump_lds_words(uint32_t r) { return (size_t)r + 4 * kTile + 2 * (size_t)r; }
+
+// One workgroup per item.  Dynamic LDS: padded P, then Q[2r].
 // P_out != nullptr: write P_J (r words per item) and stop.
 // Otherwise: states s_in -> s_out (r + 1 words per record; may alias).
 template <bool W32>
 __global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js,
                                                    const uint32_t* s_in, uint32_t* s_out, uint32_t* P_out,
                                                    uint64_t n) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int r = (int)g.r, s = (int)g.s;
   const int tid = threadIdx.x, bs = blockDim.x;
-  uint32_t* P = lds;
-  uint32_t* Q = lds + r;
+  uint32_t* P = lds + kTile;  // P[-kTile .. r + 3 kTile - 1]; zero outside [0, r)
+  uint32_t* Q = lds + r + 4 * kTile;
+  const int tiles = (2 * r - 1 + kTile - 1) / kTile, half = (tiles + 1) / 2;
   for (uint64_t item = blockIdx.x; item < n; item += gridDim.x) {
     const ranmar_u128 J = Js[item];
     // Leading bits of J that form an exponent below r give a monomial start.
@@ -96,18 +181,12 @@ __global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* 
       v = 2 * v + b;
       --bit;
     }
-    for (int i = tid; i < r; i += bs) P[i] = (i == (int)v) ? 1u : 0u;
+    for (int i = tid - kTile; i < r + 3 * kTile; i += bs) P[i] = (i == (int)v) ? 1u : 0u;
     __syncthreads();
     for (; bit >= 0; --bit) {
-      // Square: Q[k] = 2 sum_{i < k-i} P_i P_{k-i} + [k even] P_{k/2}^2.
-      for (int k = tid; k < 2 * r - 1; k += bs) {
-        const int ilo = k - (r - 1) > 0 ? k - (r - 1) : 0;
-        const int ihi = (k - 1) >> 1;
-        uint32_t acc = 0;
-        for (int i = ilo; i <= ihi; ++i) acc = mac<W32>(P[i], P[k - i], acc);
-        acc <<= 1;
-        if (!(k & 1)) acc = mac<W32>(P[k >> 1], P[k >> 1], acc);
-        Q[k] = acc;
+      if (tid < half) {
+        square_tile<W32>(P, Q, r, tid * kTile);
+        if (tid + half < tiles) square_tile<W32>(P, Q, r, (tid + half) * kTile);
       }
       __syncthreads();
       fold_phi(Q, r, s, 2 * r - 2, tid, bs);
@@ -167,9 +246,21 @@ __global__ __launch_bounds__(256) void k_lfg_gen(LfgDev g, uint32_t lw, uint32_t
   uint32_t* ring = lds + (wave * G + (grp < G ? grp : 0u)) * Z;  // idle lanes only read
   const uint32_t zm = Z - 1u;
   const uint32_t* src = s_in + (active ? stream : 0) * (uint64_t)(r + 1);
-  if (active)
-    for (uint32_t i = j; i < r; i += W) ring[i] = src[i];
   const uint32_t c0 = active ? src[r] : 0u;
+  // The state, 16 loads in flight per lane before their LDS writes.
+  for (uint32_t base = 0; base < r; base += 16 * W) {
+    uint32_t v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const uint32_t i = base + j + u * W;
+      v[u] = (active && i < r) ? src[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const uint32_t i = base + j + u * W;
+      if (active && i < r) ring[i] = v[u];
+    }
+  }
   lane_order();
   // c before draw q + j is c_q - (j + 1) d; c_q steps by W d per step.
   const uint32_t dj = (uint32_t)(((uint64_t)(j + 1) * g.d) % m);
@@ -198,7 +289,16 @@ __global__ __launch_bounds__(256) void k_lfg_gen(LfgDev g, uint32_t lw, uint32_t
   if (active && s_out) {
     uint32_t* dst = s_out + stream * (uint64_t)(r + 1);
     const uint32_t end = (uint32_t)count;  // sequence index of the oldest kept word, mod 2^32
-    for (uint32_t i = j; i < r; i += W) dst[i] = ring[(end + i) & zm];
+    for (uint32_t base = 0; base < r; base += 16 * W) {
+      uint32_t v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = ring[(end + base + j + u * W) & zm];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const uint32_t i = base + j + u * W;
+        if (i < r) dst[i] = v[u];
+      }
+    }
     if (j == 0) {
       const uint64_t M = m;
       const uint64_t sub = ((count % M) * g.d) % M;
@@ -221,14 +321,14 @@ int lfg_params_ok(const ranmar_lfg_params* p) {
   return 1;
 }
 
-uint32_t lfg_jump_threads(uint32_t r) { return r <= 128 ? 128u : r <= 512 ? 256u : r <= 2048 ? 512u : 1024u; }
+uint32_t lfg_jump_threads(uint32_t r) { return jump_threads(r); }
 
 hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
                            uint32_t* P_out, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const LfgDev g = to_dev(p);
   const uint32_t bs = lfg_jump_threads(p.r);
-  const size_t lds = (size_t)3 * p.r * sizeof(uint32_t);
+  const size_t lds = jump_lds_words(p.r) * sizeof(uint32_t);
   const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
   if (p.e > 24)
     hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n);

@@ -121,11 +121,12 @@ LFG_CASES = {
     "r1279s418e32": (1279, 418, 32, 4294967291, 2654435761),
     "r4423s2098e24": (4423, 2098, 24, 16777213, 7654321),
     "r1000s3e16": (1000, 3, 16, 65521, 77),  # large r, small s: many small rings per wave
+    "r1279s418e24": (1279, 418, 24, 16777213, 7654321),  # RANMAR's precision and c constants
 }
 # Throughput workload of the general path: 65,536 streams of the r = 1279
 # generator, 4,096 draws each (the family65k shape at a 13x larger state).
-LFG_GEN = dict(case="r1279s418e32", streams=65_536, draws=4_096)
-LFG_JUMPS = dict(case="r1279s418e32", jumps=4_096, jump_bits=120)
+LFG_GEN = dict(case="r1279s418e24", streams=65_536, draws=4_096)
+LFG_JUMPS = dict(case="r1279s418e24", jumps=4_096, jump_bits=120)
 
 
 def lfg_states(r: int, e: int, m: int, n: int, offset: int = 10) -> np.ndarray:
