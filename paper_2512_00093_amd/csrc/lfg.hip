@@ -106,52 +106,63 @@ __device__ __forceinline__ void load_block(const uint32_t* Pp, int ib, int k0, u
   for (int q = 0; q < 2 * kTile - 1; ++q) x[q] = xx[q + 1];
 }
 
+// One tile, its term blocks split over the 8 lanes of a lane group: lane l
+// takes the blocks ib0 + kTile (l + 8 m), and an xor butterfly over the group
+// sums the partial tiles; lane l then stores output k0 + l.  The 8 tiles of
+// a wave are adjacent, so their blocks run in step and only the last one or
+// two blocks of a tile (those reaching the diagonal) take the predicated form.
 template <bool W32>
-__device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int r, int k0) {
+__device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int r, int k0, int l) {
   uint32_t acc[kTile];
 #pragma unroll
   for (int u = 0; u < kTile; ++u) acc[u] = 0;
   const int ilo = k0 - (r - 1) > 0 ? k0 - (r - 1) : 0;
-  int ib = ilo & ~(kTile - 1);
   const int full_max = (k0 - 1) >> 1;        // 2 i < k0 <= k: the term belongs to every output of the tile
   const int i_end = (k0 + kTile - 2) >> 1;   // largest i any output of the tile takes
-  for (; ib + kTile - 1 <= full_max; ib += kTile) {
+  for (int ib = (ilo & ~(kTile - 1)) + kTile * l; ib <= i_end; ib += 8 * kTile) {
     uint32_t a[kTile], x[2 * kTile - 1];
     load_block(Pp, ib, k0, a, x);
+    if (ib + kTile - 1 <= full_max) {
 #pragma unroll
-    for (int q = 0; q < kTile; ++q)
+      for (int q = 0; q < kTile; ++q)
 #pragma unroll
-      for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
-  }
-  for (; ib <= i_end; ib += kTile) {
-    uint32_t a[kTile], x[2 * kTile - 1];
-    load_block(Pp, ib, k0, a, x);
+        for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < kTile; ++q)
+      for (int q = 0; q < kTile; ++q)
 #pragma unroll
-      for (int u = 0; u < kTile; ++u) {
-        const uint32_t t = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
-        acc[u] = 2 * (ib + q) < k0 + u ? t : acc[u];
-      }
+        for (int u = 0; u < kTile; ++u) {
+          const uint32_t t = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
+          acc[u] = 2 * (ib + q) < k0 + u ? t : acc[u];
+        }
+    }
   }
 #pragma unroll
   for (int u = 0; u < kTile; ++u) {
-    const int k = k0 + u;
-    if (k < 2 * r - 1) {
-      uint32_t v = acc[u] << 1;
-      if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
-      Q[k] = v;
-    }
+    acc[u] += (uint32_t)__shfl_xor((int)acc[u], 1, 64);
+    acc[u] += (uint32_t)__shfl_xor((int)acc[u], 2, 64);
+    acc[u] += (uint32_t)__shfl_xor((int)acc[u], 4, 64);
+  }
+  uint32_t mine = acc[0];
+#pragma unroll
+  for (int u = 1; u < kTile; ++u) mine = l == u ? acc[u] : mine;
+  const int k = k0 + l;
+  if (k < 2 * r - 1) {
+    uint32_t v = mine << 1;
+    if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
+    Q[k] = v;
   }
 }
 
-// Threads of the jump workgroup: each squares the tile pair (t, t + T/2) of
-// the T = ceil((2r - 1) / kTile) output tiles, which balances the triangular
-// work profile (tile k and tile k + r take about r / 2 terms together).
+// Threads of the jump workgroup: 8 lanes per tile of kTile outputs, up to 32
+// lane groups.  Group g squares the tiles c NG + g (c even) and
+// (c + 1) NG - 1 - g (c odd) of the T = ceil((2r - 1) / kTile) tiles, NG the
+// number of groups: the sweep alternates direction, which balances the
+// triangular work profile across groups.
 uint32_t jump_threads(uint32_t r) {
   const uint32_t tiles = (2 * r - 1 + kTile - 1) / kTile;
-  const uint32_t pairs = (tiles + 1) / 2;
-  return (pairs + 63) / 64 * 64;
+  const uint32_t lanes = 8 * tiles;
+  return lanes >= 256 ? 256u : (lanes + 63) / 64 * 64;
 }
 
 // Words of dynamic LDS: padded P (kTile below, 3 kTile above) and Q[2r].
@@ -169,7 +180,7 @@ __global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* 
   const int tid = threadIdx.x, bs = blockDim.x;
   uint32_t* P = lds + kTile;  // P[-kTile .. r + 3 kTile - 1]; zero outside [0, r)
   uint32_t* Q = lds + r + 4 * kTile;
-  const int tiles = (2 * r - 1 + kTile - 1) / kTile, half = (tiles + 1) / 2;
+  const int tiles = (2 * r - 1 + kTile - 1) / kTile, groups = bs / 8, grp = tid >> 3, gl = tid & 7;
   for (uint64_t item = blockIdx.x; item < n; item += gridDim.x) {
     const ranmar_u128 J = Js[item];
     // Leading bits of J that form an exponent below r give a monomial start.
@@ -184,9 +195,9 @@ __global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* 
     for (int i = tid - kTile; i < r + 3 * kTile; i += bs) P[i] = (i == (int)v) ? 1u : 0u;
     __syncthreads();
     for (; bit >= 0; --bit) {
-      if (tid < half) {
-        square_tile<W32>(P, Q, r, tid * kTile);
-        if (tid + half < tiles) square_tile<W32>(P, Q, r, (tid + half) * kTile);
+      for (int c = 0; c * groups < tiles; ++c) {
+        const int t = (c & 1) ? (c + 1) * groups - 1 - grp : c * groups + grp;
+        if (t < tiles) square_tile<W32>(P, Q, r, t * kTile, gl);
       }
       __syncthreads();
       fold_phi(Q, r, s, 2 * r - 2, tid, bs);
