@@ -243,7 +243,7 @@ __global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* 
 
 // Generation.  Dynamic LDS: (waves per workgroup) x G rings of Z words, with
 // G <= 64 / W streams per wave (fewer when the rings would not fit).
-template <int FMT>
+template <int FMT, int U>
 __global__ __launch_bounds__(256) void k_lfg_gen(LfgDev g, uint32_t lw, uint32_t G, uint32_t Z, const uint32_t* s_in,
                                                  uint32_t* s_out, uint64_t n, uint64_t count, void* out,
                                                  uint64_t ld, float scale) {
@@ -279,7 +279,40 @@ __global__ __launch_bounds__(256) void k_lfg_gen(LfgDev g, uint32_t lw, uint32_t
   uint32_t c = c0;
   uint32_t pos = r;  // sequence index of the next word, kept mod 2^32 (Z divides 2^32)
   const uint64_t row = (active ? stream : 0) * ld;
-  for (uint64_t q = 0; q < count; q += W) {
+  uint64_t q = 0;
+  if constexpr (U > 1) {
+    // U steps at once (U W <= s): every operand of the U W new words is older
+    // than the first of them, so all reads precede the writes.
+    uint32_t du[U];  // (u W + j + 1) d mod m
+#pragma unroll
+    for (int u = 0; u < U; ++u) du[u] = (uint32_t)(((uint64_t)(u * W + j + 1) * g.d) % m);
+    const uint32_t dUW = (uint32_t)(((uint64_t)U * W * g.d) % m);
+    for (; q + (uint64_t)U * W <= count; q += (uint64_t)U * W) {
+      uint32_t a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = ring[(pos + u * W + j - r) & zm];
+        b[u] = ring[(pos + u * W + j - s) & zm];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t x = (a[u] - b[u]) & mask;
+        const uint32_t cj = c >= du[u] ? c - du[u] : c - du[u] + m;
+        const uint32_t k = (x - cj) & mask;
+        if (active) {
+          ring[(pos + u * W + j) & zm] = x;
+          if constexpr (FMT == 0)
+            __builtin_nontemporal_store(k, (uint32_t*)out + row + q + u * W + j);
+          else
+            __builtin_nontemporal_store((float)k * scale, (float*)out + row + q + u * W + j);
+        }
+      }
+      c = c >= dUW ? c - dUW : c - dUW + m;
+      pos += U * W;
+      lane_order();
+    }
+  }
+  for (; q < count; q += W) {
     const bool live = active && q + j < count;
     const uint32_t a = ring[(pos + j - r) & zm];
     const uint32_t b = ring[(pos + j - s) & zm];
@@ -380,12 +413,21 @@ hipError_t launch_lfg_generate(const ranmar_lfg_params& p, const uint32_t* s_in,
   if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const size_t lds = (size_t)waves * G * Z * sizeof(uint32_t);
   const float scale = 1.0f / (float)(1u << (p.e < 24 ? p.e : 24));
-  if (fmt == RANMAR_F32)
-    hipLaunchKernelGGL(k_lfg_gen<1>, dim3((uint32_t)grid), dim3(64 * waves), lds, st, g, lw, G, Z, s_in, s_out, n,
-                       count, out, ld, scale);
-  else
-    hipLaunchKernelGGL(k_lfg_gen<0>, dim3((uint32_t)grid), dim3(64 * waves), lds, st, g, lw, G, Z, s_in, s_out, n,
-                       count, out, ld, scale);
+  const uint32_t W = 1u << lw;
+  const int U = 4 * W <= p.s ? 4 : 2 * W <= p.s ? 2 : 1;  // steps issued together
+#define LFG_GEN_LAUNCH(F, UU)                                                                                  \
+  hipLaunchKernelGGL((k_lfg_gen<F, UU>), dim3((uint32_t)grid), dim3(64 * waves), lds, st, g, lw, G, Z, s_in, s_out, \
+                     n, count, out, ld, scale)
+  if (fmt == RANMAR_F32) {
+    if (U == 4) LFG_GEN_LAUNCH(1, 4);
+    else if (U == 2) LFG_GEN_LAUNCH(1, 2);
+    else LFG_GEN_LAUNCH(1, 1);
+  } else {
+    if (U == 4) LFG_GEN_LAUNCH(0, 4);
+    else if (U == 2) LFG_GEN_LAUNCH(0, 2);
+    else LFG_GEN_LAUNCH(0, 1);
+  }
+#undef LFG_GEN_LAUNCH
   return hipGetLastError();
 }
 
