@@ -172,7 +172,7 @@ size_t jump_lds_words(uint32_t r) { return (size_t)r + 4 * kTile + 2 * (size_t)r
 // P_out != nullptr: write P_J (r words per item) and stop.
 // Otherwise: states s_in -> s_out (r + 1 words per record; may alias).
 template <bool W32>
-__global__ __launch_bounds__(1024) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W32 ? 1 : 8))) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js,
                                                    const uint32_t* s_in, uint32_t* s_out, uint32_t* P_out,
                                                    uint64_t n) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
