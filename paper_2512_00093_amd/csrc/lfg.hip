@@ -166,59 +166,23 @@ uint32_t jump_threads(uint32_t r) {
 }
 
 // LDS layout of the jump (words; every buffer starts on a multiple of kTile
-// words, so the 16-byte tile reads are aligned):
-//   P   padded: kTile below, r rounded up to kTile, 3 kTile above
-//   Q   the square, 2 r8 + kTile words (index 2r is read by the Karatsuba form)
-// and with one Karatsuba level (h = ceil(r / 2) > 0):
-//   A0, A1, SM  padded copies of a0 = P[0 .. h), a1 = P[h .. r) and a0 + a1
-//   T   (a0 + a1)^2, 2 h8 words
-struct JumpLayout {
-  uint32_t q, a0, a1, sm, t, words;
-};
-JumpLayout jump_layout(uint32_t r, uint32_t h) {
-  const uint32_t r8 = (r + kTile - 1) / kTile * kTile, h8 = (h + kTile - 1) / kTile * kTile;
-  JumpLayout L;
-  L.q = r8 + 4 * kTile;
-  L.a0 = L.q + 2 * r8 + kTile;
-  if (!h) {
-    L.a1 = L.sm = L.t = L.words = L.a0;
-    return L;
-  }
-  L.a1 = L.a0 + h8 + 4 * kTile;
-  L.sm = L.a1 + h8 + 4 * kTile;
-  L.t = L.sm + h8 + 4 * kTile;
-  L.words = L.t + 2 * h8;
-  return L;
-}
+// words, so the 16-byte tile reads are aligned): P padded with kTile words
+// below and 3 kTile above r rounded up to kTile, then Q[2 r8].
+uint32_t jump_q_offset(uint32_t r) { return (r + kTile - 1) / kTile * kTile + 4 * kTile; }
+size_t jump_lds_words(uint32_t r) { return jump_q_offset(r) + 2 * (size_t)((r + kTile - 1) / kTile * kTile); }
 
-// One Karatsuba level (Sec. 5: faster multiplication for a larger order) when
-// its buffers fit in 64 KiB of LDS and the order is large enough to gain:
-// (a0 + a1 t^h)^2 = a0^2 + ((a0 + a1)^2 - a0^2 - a1^2) t^h + a1^2 t^{2h},
-// three squares of half the size (3/4 of the multiply-adds), exact in Z/2^32.
-uint32_t karatsuba_half(uint32_t r) {
-  const uint32_t h = (r + 1) / 2;
-  return (r >= 256 && jump_layout(r, h).words <= 16384u) ? h : 0u;
-}
-
-// One workgroup per item.  Dynamic LDS: jump_layout(r, kh).
+// One workgroup per item.  Dynamic LDS: jump_lds_words(r).
 // P_out != nullptr: write P_J (r words per item) and stop.
 // Otherwise: states s_in -> s_out (r + 1 words per record; may alias).
 template <bool W32>
-__global__ __launch_bounds__(256) void k_lfg_jump(
-    LfgDev g, const ranmar_u128* __restrict__ Js, const uint32_t* s_in, uint32_t* s_out, uint32_t* P_out, uint64_t n,
-    int kh, JumpLayout L) {
+__global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js, const uint32_t* s_in,
+                                                  uint32_t* s_out, uint32_t* P_out, uint64_t n, uint32_t q_off) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int r = (int)g.r, s = (int)g.s;
   const int tid = threadIdx.x, bs = blockDim.x;
   uint32_t* P = lds + kTile;  // P[-kTile .. r + 3 kTile - 1]; zero outside [0, r)
-  uint32_t* Q = lds + L.q;
-  uint32_t* A0 = lds + L.a0 + kTile;  // Karatsuba halves, each zero outside [0, h)
-  uint32_t* A1 = lds + L.a1 + kTile;
-  uint32_t* SM = lds + L.sm + kTile;
-  uint32_t* T = lds + L.t;
+  uint32_t* Q = lds + q_off;
   const int tiles = (2 * r - 1 + kTile - 1) / kTile, groups = bs / 8, grp = tid >> 3, gl = tid & 7;
-  const int h = kh, r1 = r - kh;
-  const int t0 = kh ? (2 * h - 1 + kTile - 1) / kTile : 0, t1 = kh ? (2 * r1 - 1 + kTile - 1) / kTile : 0;
   for (uint64_t item = blockIdx.x; item < n; item += gridDim.x) {
     const ranmar_u128 J = Js[item];
     // Leading bits of J that form an exponent below r give a monomial start.
@@ -231,46 +195,13 @@ __global__ __launch_bounds__(256) void k_lfg_jump(
       --bit;
     }
     for (int i = tid - kTile; i < r + 3 * kTile; i += bs) P[i] = (i == (int)v) ? 1u : 0u;
-    if (kh)
-      for (int i = tid - kTile; i < h + 3 * kTile; i += bs) {
-        const uint32_t x0 = (i >= 0 && i < h && i == (int)v) ? 1u : 0u;
-        const uint32_t x1 = (i >= 0 && i < r1 && i + h == (int)v) ? 1u : 0u;
-        A0[i] = x0;
-        A1[i] = x1;
-        SM[i] = x0 + x1;
-      }
     __syncthreads();
     for (; bit >= 0; --bit) {
-      if (!kh) {
-        for (int c = 0; c * groups < tiles; ++c) {
-          const int t = (c & 1) ? (c + 1) * groups - 1 - grp : c * groups + grp;
-          if (t < tiles) square_tile<W32>(P, Q, r, t * kTile, gl);
-        }
-        __syncthreads();
-      } else {
-        // a0^2 -> Q[0 .. 2h-2], a1^2 -> Q[2h .. 2r-2], (a0 + a1)^2 -> T, as
-        // one list of tiles; then T -= a0^2 + a1^2 and Q[h ..] += T.
-        const int tot = 2 * t0 + t1;
-        for (int c = 0; c * groups < tot; ++c) {
-          const int t = (c & 1) ? (c + 1) * groups - 1 - grp : c * groups + grp;
-          if (t < t0)
-            square_tile<W32>(A0, Q, h, t * kTile, gl);
-          else if (t < t0 + t1)
-            square_tile<W32>(A1, Q + 2 * h, r1, (t - t0) * kTile, gl);
-          else if (t < tot)
-            square_tile<W32>(SM, T, h, (t - t0 - t1) * kTile, gl);
-        }
-        if (tid == 0) {  // the words no square writes but the sums below read
-          Q[2 * h - 1] = 0;
-          Q[2 * r - 1] = 0;
-          Q[2 * r] = 0;
-        }
-        __syncthreads();
-        for (int k = tid; k < 2 * h - 1; k += bs) T[k] -= Q[k] + Q[2 * h + k];
-        __syncthreads();
-        for (int k = tid; k < 2 * h - 1; k += bs) Q[h + k] += T[k];
-        __syncthreads();
+      for (int c = 0; c * groups < tiles; ++c) {
+        const int t = (c & 1) ? (c + 1) * groups - 1 - grp : c * groups + grp;
+        if (t < tiles) square_tile<W32>(P, Q, r, t * kTile, gl);
       }
+      __syncthreads();
       fold_phi(Q, r, s, 2 * r - 2, tid, bs);
       const uint32_t b = bit >= 64 ? (uint32_t)(J.hi >> (bit - 64)) & 1u : (uint32_t)(J.lo >> bit) & 1u;
       // The new P: Q mod phi, times t if the bit is set (shift up one place;
@@ -282,19 +213,7 @@ __global__ __launch_bounds__(256) void k_lfg_jump(
         if (i == r - s) x -= topc;
         return x;
       };
-      if (!kh) {
-        for (int i = tid; i < r; i += bs) P[i] = next(i);
-      } else {
-        for (int i = tid; i < h; i += bs) {
-          const uint32_t x0 = next(i);
-          const uint32_t x1 = i < r1 ? next(i + h) : 0u;
-          P[i] = x0;
-          if (i < r1) P[i + h] = x1;
-          A0[i] = x0;
-          A1[i] = x1;
-          SM[i] = x0 + x1;
-        }
-      }
+      for (int i = tid; i < r; i += bs) P[i] = next(i);
       __syncthreads();
     }
     if (P_out) {
@@ -448,21 +367,19 @@ int lfg_params_ok(const ranmar_lfg_params* p) {
 }
 
 uint32_t lfg_jump_threads(uint32_t r) { return jump_threads(r); }
-uint32_t lfg_jump_karatsuba(uint32_t r) { return karatsuba_half(r); }
 
 hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
                            uint32_t* P_out, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const LfgDev g = to_dev(p);
   const uint32_t bs = lfg_jump_threads(p.r);
-  const int kh = (int)karatsuba_half(p.r);
-  const JumpLayout L = jump_layout(p.r, (uint32_t)kh);
-  const size_t lds = (size_t)L.words * sizeof(uint32_t);
+  const size_t lds = jump_lds_words(p.r) * sizeof(uint32_t);
+  const uint32_t q_off = jump_q_offset(p.r);
   const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
   if (p.e > 24)
-    hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n, kh, L);
+    hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n, q_off);
   else
-    hipLaunchKernelGGL(k_lfg_jump<false>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n, kh, L);
+    hipLaunchKernelGGL(k_lfg_jump<false>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n, q_off);
   return hipGetLastError();
 }
 
