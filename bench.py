@@ -404,9 +404,9 @@ def run_lfg_gen(R, torch, steps, warmup):
         "config": {"workload": f"lfg_gen: general lagged-Fibonacci generator (r, s, e) = ({p.r}, {p.s}, {p.e}), "
                                f"{n} streams x {count} uint32 draws, states advanced in place", "streams": n,
                    "draws": count},
-        "roofline": {"bound": "hbm", "kernel": "k_lfg_gen<0>", "achieved": algo / (ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "k_lfg_gen<0, 4>", "achieved": algo / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_lfg_gen<0>", n // 4 * 4 * lanes),
+                     "traffic": profiled_traffic("k_lfg_gen<0, 4>", n // 4 * 4 * lanes),
                      "bytes_per_launch": algo, "launch_ms": ms},
     }
 
