@@ -121,3 +121,48 @@ def test_batch_and_serve_argument_errors(L):
     assert L.ranmar_serve_release(None, 1) == B.RANMAR_EINVAL
     assert L.ranmar_serve_destroy(None) == B.RANMAR_EINVAL
     assert L.ranmar_serve_replay(None, 1, None, None, None, None, 0, None) == B.RANMAR_EINVAL
+
+
+def test_lfg_parameter_check_matches_oracle(L, orc):
+    """The library's host check of general-generator parameters accepts exactly
+    what the oracle's independent check accepts (up to the library's order
+    limit)."""
+    from paper_2512_00093_amd import _binding as B
+    import itertools
+    vals_r = [0, 1, 2, 3, 97, B.RANMAR_LFG_MAX_R, B.RANMAR_LFG_MAX_R + 1]
+    vals_s = [0, 1, 2, 96, 97]
+    vals_e = [0, 1, 2, 24, 32, 33]
+    vals_m = [0, 1, 2, 3, 16777213, 16777216, 4294967295]
+    vals_d = [0, 1, 2, 7654321, 4294967294]
+    n = 0
+    for r, s, e, m, d in itertools.product(vals_r, vals_s, vals_e, vals_m, vals_d):
+        p = B.ranmar_lfg_params(r, s, e, m, d)
+        lib_ok = L.ranmar_lfg_check(ctypes.byref(p)) == 0
+        orc_ok = orc.lib().lfg_check(r, s, e, m, d) == 0 and r <= B.RANMAR_LFG_MAX_R
+        assert lib_ok == orc_ok, (r, s, e, m, d)
+        n += lib_ok
+    assert n > 50
+
+
+def test_lfg_argument_errors_before_device_work(L):
+    from paper_2512_00093_amd import _binding as B
+    p = ctypes.c_void_p
+    EINVAL = B.RANMAR_EINVAL
+    ok = ctypes.byref(B.ranmar_lfg_params(97, 33, 24, 16777213, 7654321))
+    wide = ctypes.byref(B.ranmar_lfg_params(55, 24, 32, 4294967291, 2654435761))
+    bad = ctypes.byref(B.ranmar_lfg_params(97, 97, 24, 16777213, 7654321))
+    rec = 4 * 98
+    assert L.ranmar_lfg_jump_poly(bad, p(0x1000), 3, p(0x90000), None) == EINVAL
+    assert L.ranmar_lfg_jump_poly(ok, p(0x1004), 3, p(0x90000), None) == EINVAL          # J misaligned
+    assert L.ranmar_lfg_jump_poly(ok, p(0x1000), 3, p(0x1010), None) == EINVAL           # P overlaps J
+    assert L.ranmar_lfg_jump(ok, None, p(0x10000), p(0x1000), 3, None) == EINVAL
+    assert L.ranmar_lfg_jump(ok, p(0x10000), p(0x10000 + rec), p(0x1000), 3, None) == EINVAL  # partial alias
+    assert L.ranmar_lfg_jump(ok, p(0x10000), p(0x10000), p(0x10010), 3, None) == EINVAL  # J inside states
+    assert L.ranmar_lfg_generate(ok, p(0x10000), None, 4, 10, 7, p(0x900000), 10, None) == EINVAL   # fmt
+    assert L.ranmar_lfg_generate(wide, p(0x10000), None, 4, 10, B.RANMAR_F32, p(0x900000), 10, None) == EINVAL
+    assert L.ranmar_lfg_generate(ok, p(0x10000), None, 4, 10, 0, p(0x900000), 5, None) == EINVAL   # ld < count
+    assert L.ranmar_lfg_generate(ok, p(0x10000), None, 4, 10, 0, p(0x10004), 10, None) == EINVAL   # out on states
+    assert L.ranmar_lfg_generate(bad, p(0x10000), None, 4, 10, 0, p(0x900000), 10, None) == EINVAL
+    # n == 0 with valid parameters succeeds without a device.
+    assert L.ranmar_lfg_jump(ok, None, None, None, 0, None) == 0
+    assert L.ranmar_lfg_generate(ok, None, None, 0, 10, 0, None, 10, None) == 0
