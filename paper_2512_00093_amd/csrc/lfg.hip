@@ -106,47 +106,46 @@ __device__ __forceinline__ void load_block(const uint32_t* Pp, int ib, int k0, u
   for (int q = 0; q < 2 * kTile - 1; ++q) x[q] = xx[q + 1];
 }
 
-// One tile, its term blocks split over the 8 lanes of a lane group: lane l
-// takes the blocks ib0 + kTile (l + 8 m), and an xor butterfly over the group
-// sums the partial tiles; lane l then stores output k0 + l.  The 8 tiles of
-// a wave are adjacent, so their blocks run in step and only the last one or
-// two blocks of a tile (those reaching the diagonal) take the predicated form.
+// Sum over the 8 lanes of an aligned lane group, left in every lane of it:
+// DPP swaps of neighbours (quad_perm 1,0,3,2), of pairs (quad_perm 2,3,0,1)
+// and of the two halves of the 8 (row_half_mirror).
+__device__ __forceinline__ uint32_t group8_sum(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+  return v;
+}
+
+// One tile of the square, its term blocks split over the 8 lanes of a lane
+// group: lane l takes the blocks ib0 + kTile (l + 8 m) among those whose
+// every term has 2 i < k0, i.e. belongs to all kTile outputs of the tile, so
+// the blocks need no predicate.  After the group sum, lane l owns output
+// k0 + l and adds the few terms ib_stop <= i < k - i that are left (at most
+// kTile) one by one.
 template <bool W32>
 __device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int r, int k0, int l) {
   uint32_t acc[kTile];
 #pragma unroll
   for (int u = 0; u < kTile; ++u) acc[u] = 0;
   const int ilo = k0 - (r - 1) > 0 ? k0 - (r - 1) : 0;
-  const int full_max = (k0 - 1) >> 1;        // 2 i < k0 <= k: the term belongs to every output of the tile
-  const int i_end = (k0 + kTile - 2) >> 1;   // largest i any output of the tile takes
-  for (int ib = (ilo & ~(kTile - 1)) + kTile * l; ib <= i_end; ib += 8 * kTile) {
+  const int ib0 = ilo & ~(kTile - 1);
+  const int span = ((k0 - 1) >> 1) - ib0 + 1;  // terms ib0 .. (k0 - 1) / 2
+  const int ib_stop = ib0 + (span >= kTile ? span / kTile * kTile : 0);
+  for (int ib = ib0 + kTile * l; ib < ib_stop; ib += 8 * kTile) {
     uint32_t a[kTile], x[2 * kTile - 1];
     load_block(Pp, ib, k0, a, x);
-    if (ib + kTile - 1 <= full_max) {
 #pragma unroll
-      for (int q = 0; q < kTile; ++q)
+    for (int q = 0; q < kTile; ++q)
 #pragma unroll
-        for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < kTile; ++q)
-#pragma unroll
-        for (int u = 0; u < kTile; ++u) {
-          const uint32_t t = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
-          acc[u] = 2 * (ib + q) < k0 + u ? t : acc[u];
-        }
-    }
+      for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
   }
 #pragma unroll
-  for (int u = 0; u < kTile; ++u) {
-    acc[u] += (uint32_t)__shfl_xor((int)acc[u], 1, 64);
-    acc[u] += (uint32_t)__shfl_xor((int)acc[u], 2, 64);
-    acc[u] += (uint32_t)__shfl_xor((int)acc[u], 4, 64);
-  }
+  for (int u = 0; u < kTile; ++u) acc[u] = group8_sum(acc[u]);
   uint32_t mine = acc[0];
 #pragma unroll
   for (int u = 1; u < kTile; ++u) mine = l == u ? acc[u] : mine;
   const int k = k0 + l;
+  for (int i = ib_stop; 2 * i < k; ++i) mine = mac<W32>(Pp[i], Pp[k - i], mine);
   if (k < 2 * r - 1) {
     uint32_t v = mine << 1;
     if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
