@@ -166,9 +166,13 @@ uint32_t jump_threads(uint32_t r) {
 
 // LDS layout of the jump (words; every buffer starts on a multiple of kTile
 // words, so the 16-byte tile reads are aligned): P padded with kTile words
-// below and 3 kTile above r rounded up to kTile, then Q[2 r8].
+// below and 3 kTile above r rounded up to kTile, then Q[2 r8 + 2 kTile] (the
+// application's 16-word windows reach index 2r + 13; words past 2r - 2 only
+// meet zero coefficients or outputs past r - 1).
 uint32_t jump_q_offset(uint32_t r) { return (r + kTile - 1) / kTile * kTile + 4 * kTile; }
-size_t jump_lds_words(uint32_t r) { return jump_q_offset(r) + 2 * (size_t)((r + kTile - 1) / kTile * kTile); }
+size_t jump_lds_words(uint32_t r) {
+  return jump_q_offset(r) + 2 * (size_t)((r + kTile - 1) / kTile * kTile) + 2 * kTile;
+}
 
 // One workgroup per item.  Dynamic LDS: jump_lds_words(r).
 // P_out != nullptr: write P_J (r words per item) and stop.
@@ -230,11 +234,42 @@ __global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* _
       for (int k = lo + tid; k <= hi; k += bs) Q[k] = Q[k - r] - Q[k - s];
       __syncthreads();
     }
+    // x'_l = sum_i b_i X_{i+l}: tiles of kTile outputs per lane group, lane gl
+    // taking the blocks kTile (gl + 8 m) of i, then the group sum.
     uint32_t* dst = s_out + item * (uint64_t)(r + 1);
-    for (int l = tid; l < r; l += bs) {
-      uint32_t acc = 0;
-      for (int i = 0; i < r; ++i) acc = mac<W32>(P[i], Q[i + l], acc);
-      dst[l] = acc & g.mask;
+    const int otiles = (r + kTile - 1) / kTile;
+    for (int c = 0; c * groups < otiles; ++c) {
+      const int t = c * groups + grp;
+      if (t >= otiles) continue;
+      const int l0 = t * kTile;
+      uint32_t acc[kTile];
+#pragma unroll
+      for (int u = 0; u < kTile; ++u) acc[u] = 0;
+      for (int ib = kTile * gl; ib < r; ib += 8 * kTile) {
+        const u32x4* pa = (const u32x4*)(P + ib);
+        const u32x4* px = (const u32x4*)(Q + ib + l0);
+        uint32_t a[kTile], xx[2 * kTile];
+#pragma unroll
+        for (int v = 0; v < kTile / 4; ++v) {
+          const u32x4 w = pa[v];
+          a[4 * v] = w.x, a[4 * v + 1] = w.y, a[4 * v + 2] = w.z, a[4 * v + 3] = w.w;
+        }
+#pragma unroll
+        for (int v = 0; v < kTile / 2; ++v) {
+          const u32x4 w = px[v];
+          xx[4 * v] = w.x, xx[4 * v + 1] = w.y, xx[4 * v + 2] = w.z, xx[4 * v + 3] = w.w;
+        }
+#pragma unroll
+        for (int q = 0; q < kTile; ++q)
+#pragma unroll
+          for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], xx[q + u], acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kTile; ++u) acc[u] = group8_sum(acc[u]);
+      uint32_t mine = acc[0];
+#pragma unroll
+      for (int u = 1; u < kTile; ++u) mine = gl == u ? acc[u] : mine;
+      if (l0 + gl < r) dst[l0 + gl] = mine & g.mask;
     }
     if (tid == 0) dst[r] = c_after(c0, J, g.m, g.d);
     __syncthreads();
