@@ -116,6 +116,15 @@ def _cpu_worker(args):
             st = O.jump(O.state_from_seed(p["seed"]), int(k) * p["spacing"])
             O.state_draws(st, p["draws"])
             units += p["draws"]
+        elif kind == "lfg_gen":
+            g = O.LFG(*synth.LFG_CASES[synth.LFG_GEN["case"]])
+            g.draws_many(k, synth.LFG_GEN["draws"], want_states=True)
+            units += synth.LFG_GEN["draws"]
+        elif kind == "lfg_jumps":
+            g = O.LFG(*synth.LFG_CASES[synth.LFG_JUMPS["case"]])
+            st, J = k
+            g.jump_many(st, [J])
+            units += 1
         else:
             s, lo, hi = k
             O.seed_jump_many([s], [(int(hi) << 64) | int(lo)])
@@ -132,6 +141,17 @@ def cpu_baseline(kind: str, seconds: float):
         s, lo, hi = synth.batch_jumps(4000 * workers, 120, offset=4)
         items = list(zip(s.tolist(), lo.tolist(), hi.tolist()))
         unit, sample = "jumps/s", "seed + jump of 10^6-workload requests (J uniform 120-bit)"
+    elif kind in ("lfg_gen", "lfg_jumps"):
+        r, _, e, m, _ = synth.LFG_CASES[synth.LFG_GEN["case"]]
+        n_items = (4096 if kind == "lfg_gen" else 64) * workers
+        st = synth.lfg_states(r, e, m, n_items, offset=30 if kind == "lfg_gen" else 31)
+        if kind == "lfg_gen":
+            items = [st[i] for i in range(n_items)]
+            unit, sample = "draws/s", f"streams of the r = {r} generator: oracle draws of {synth.LFG_GEN['draws']} each"
+        else:
+            lo, hi = synth.u128_uniform(synth.rng(32), n_items, synth.LFG_JUMPS["jump_bits"])
+            items = list(zip([st[i] for i in range(n_items)], synth.u128_to_int(lo, hi)))
+            unit, sample = "jumps/s", f"states of the r = {r} generator: oracle jump by a uniform 120-bit J"
     else:
         n = synth.FAMILY_65K["streams"] if kind == "family65k" else synth.BULK_1M["streams"]
         g = synth.rng(77)
@@ -702,6 +722,8 @@ def main():
         for name, fn in (("lfg_gen", run_lfg_gen), ("lfg_jumps", run_lfg_jumps)):
             r = fn(R, torch, 5, 1)
             also[name] = {k: r[k] for k in r if k not in ("metric",)}
+            if not a.no_cpu:
+                also[name]["cpu_baseline"] = cpu_baseline(name, min(a.cpu_seconds, 3.0))
             _progress(f"{name} done")
         also["paper_table1"] = run_paper_table1(R, torch, 5, 1)
         also["paper_table2"] = run_paper_table2(R, torch)
