@@ -356,6 +356,18 @@ int ranmar_lfg_jump_poly(const ranmar_lfg_params *p, const ranmar_u128 *d_J, uin
 int ranmar_lfg_jump(const ranmar_lfg_params *p, const uint32_t *d_in, uint32_t *d_out, const ranmar_u128 *d_J,
                     uint64_t n, void *stream);
 
+/* Stream family of a general generator (Sec. 1, block splitting):
+ * d_out[k] = f^(k*delta)(*d_base) for k < n, bit-identical to n separate
+ * jumps.  About sqrt(n) starts are direct jumps, about sqrt(n) shared
+ * polynomials P_{b A delta} are formed, and every other start is one of
+ * them applied to a direct start (Sec. 3.1; an r^2 application instead of a
+ * whole jump).  (n - 1) * delta must be below 2^128 and n <= 2^32, else
+ * RANMAR_EINVAL.  d_base: one record; it may be d_out itself (d_out[0]) and
+ * must not otherwise overlap d_out.  Scratch: (about 2 sqrt(n)) * 16 + (about
+ * sqrt(n)) * 4r bytes of stream-ordered device memory for the call. */
+int ranmar_lfg_jump_family(const ranmar_lfg_params *p, const uint32_t *d_base, ranmar_u128 delta, uint64_t n,
+                           uint32_t *d_out, void *stream);
+
 /* For each stream q < n: `count` consecutive draws from d_in[q], written to
  * row q of d_out (row stride ld >= count elements).  fmt RANMAR_U24 writes
  * uint32 k < 2^e; RANMAR_F32 writes float k * 2^-e and needs e <= 24 (exact).

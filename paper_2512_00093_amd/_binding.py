@@ -120,6 +120,7 @@ _SIGS = {
     "ranmar_lfg_jump_poly": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, _u64, _vp, _vp]),
     "ranmar_lfg_jump": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, _vp, _vp, _u64, _vp]),
     "ranmar_lfg_generate": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, _vp, _u64, _u64, _int, _vp, _u64, _vp]),
+    "ranmar_lfg_jump_family": (_int, [ctypes.POINTER(ranmar_lfg_params), _vp, ranmar_u128, _u64, _vp, _vp]),
     "ranmar_tune_variants": (_int, [_int]),
     "ranmar_tune_variant_name": (ctypes.c_char_p, [_int, _int]),
     "ranmar_tune_set": (_int, [_int, _int]),
@@ -291,6 +292,15 @@ def ranmar_lfg_jump(p: ranmar_lfg_params, states, jumps, out=None, stream=None):
         out = states
     _check(lib().ranmar_lfg_jump(ctypes.byref(p), _ptr(states), _ptr(out), _ptr(jumps), n, _stream(stream)),
            "ranmar_lfg_jump")
+    return out
+
+
+def ranmar_lfg_jump_family(p: ranmar_lfg_params, base, delta: int, n: int, out=None, stream=None):
+    """out[k] = f^(k*delta)(base), k < n; base: one (r + 1)-word record (device)."""
+    if out is None:
+        out = torch.empty((n, p.r + 1), dtype=torch.int32, device=base.device)
+    _check(lib().ranmar_lfg_jump_family(ctypes.byref(p), _ptr(base), _u128(delta), n, _ptr(out), _stream(stream)),
+           "ranmar_lfg_jump_family")
     return out
 
 

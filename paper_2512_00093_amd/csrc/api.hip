@@ -243,6 +243,21 @@ int ranmar_lfg_jump(const ranmar_lfg_params* p, const uint32_t* d_in, uint32_t* 
   return hip_status(launch_lfg_jump(*p, d_J, d_in, d_out, nullptr, n, (hipStream_t)stream));
 }
 
+int ranmar_lfg_jump_family(const ranmar_lfg_params* p, const uint32_t* d_base, ranmar_u128 delta, uint64_t n,
+                           uint32_t* d_out, void* stream) {
+  if (!lfg_params_ok(p)) return RANMAR_EINVAL;
+  if (n == 0) return RANMAR_OK;
+  if (!d_base || !d_out || !aligned(d_base, 4) || !aligned(d_out, 4)) return RANMAR_EINVAL;
+  if (n > (1ull << 32)) return RANMAR_EINVAL;
+  const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
+  if (n > 1 && D > ~(unsigned __int128)0 / (n - 1)) return RANMAR_EINVAL;
+  const uint64_t rec = 4ull * (p->r + 1);
+  if (d_base != d_out && overlap(d_base, rec, d_out, rec * n)) return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  return hip_status(launch_lfg_family(*p, d_base, delta, n, d_out, (hipStream_t)stream));
+}
+
 int ranmar_lfg_generate(const ranmar_lfg_params* p, const uint32_t* d_in, uint32_t* d_state_out, uint64_t n,
                         uint64_t count, int fmt, void* d_out, uint64_t ld, void* stream) {
   if (!lfg_params_ok(p)) return RANMAR_EINVAL;

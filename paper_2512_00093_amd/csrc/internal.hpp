@@ -47,6 +47,10 @@ void lfg_gen_shape(uint32_t r, uint32_t s, uint32_t* lw, uint32_t* G, uint32_t* 
 // P_out != nullptr: polynomials only; else states s_in -> s_out (may alias).
 hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
                            uint32_t* P_out, uint64_t n, hipStream_t st);
+// out[k] = f^{k delta}(*base), k < n; hipErrorInvalidValue if (n - 1) delta
+// needs more than 128 bits or n > 2^32.
+hipError_t launch_lfg_family(const ranmar_lfg_params& p, const uint32_t* base, ranmar_u128 delta, uint64_t n,
+                             uint32_t* out, hipStream_t st);
 hipError_t launch_lfg_generate(const ranmar_lfg_params& p, const uint32_t* s_in, uint32_t* s_out, uint64_t n,
                                uint64_t count, int fmt, void* out, uint64_t ld, hipStream_t st);
 enum FamilyVariant : int {

@@ -20,6 +20,7 @@
 // 32-bit multiply.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "common.hpp"
@@ -46,14 +47,12 @@ __device__ __forceinline__ uint32_t mac(uint32_t a, uint32_t b, uint32_t acc) {
     return mad24(a, b, acc);
 }
 
-// (c - J d) mod m with J = hi 2^64 + lo; m < 2^32 so every product fits 64 bits.
-__device__ __forceinline__ uint32_t c_after(uint32_t c, ranmar_u128 J, uint32_t m, uint32_t d) {
+// J mod m for J = hi 2^64 + lo; m < 2^32 so every product fits 64 bits.
+__device__ __forceinline__ uint32_t j_mod_m(ranmar_u128 J, uint32_t m) {
   const uint64_t M = m;
   const uint64_t t32 = (1ull << 32) % M;
   const uint64_t t64 = (t32 * t32) % M;
-  const uint64_t jm = ((J.hi % M) * t64 + J.lo % M) % M;
-  const uint64_t sub = (jm * d) % M;
-  return (uint32_t)(((uint64_t)c + M - sub) % M);
+  return (uint32_t)(((J.hi % M) * t64 + J.lo % M) % M);
 }
 
 // Reduces Q[0 .. 2r-2] modulo phi in place (coefficients k >= r become zero
@@ -174,12 +173,74 @@ size_t jump_lds_words(uint32_t r) {
   return jump_q_offset(r) + 2 * (size_t)((r + kTile - 1) / kTile * kTile) + 2 * kTile;
 }
 
+// The state src jumped by J, written to dst (may alias src): the words by
+// the polynomial P_J in LDS (padded view), the Hankel product
+// x'_l = sum_i b_i X_{i+l} over the window extended by r - 1 steps (in Q), c by
+// (c - (J mod m) d) mod m with jm = J mod m.  Called by the whole workgroup.
+template <bool W32>
+__device__ __forceinline__ void apply_state(const LfgDev& g, const uint32_t* P, uint32_t* Q, const uint32_t* src,
+                                            uint32_t* dst, uint32_t jm) {
+  const int r = (int)g.r, s = (int)g.s;
+  const int tid = threadIdx.x, bs = blockDim.x, groups = bs / 8, grp = tid >> 3, gl = tid & 7;
+  const uint32_t c0 = src[r];
+  for (int i = tid; i < r; i += bs) Q[i] = src[i];
+  __syncthreads();
+  for (int lo = r; lo < 2 * r - 1; lo += s) {
+    const int hi = lo + s - 1 < 2 * r - 2 ? lo + s - 1 : 2 * r - 2;
+    for (int k = lo + tid; k <= hi; k += bs) Q[k] = Q[k - r] - Q[k - s];
+    __syncthreads();
+  }
+  // Tiles of kTile outputs per lane group, lane gl taking the blocks
+  // kTile (gl + 8 m) of i, then the group sum.
+  const int otiles = (r + kTile - 1) / kTile;
+  for (int c = 0; c * groups < otiles; ++c) {
+    const int t = c * groups + grp;
+    if (t >= otiles) continue;
+    const int l0 = t * kTile;
+    uint32_t acc[kTile];
+#pragma unroll
+    for (int u = 0; u < kTile; ++u) acc[u] = 0;
+    for (int ib = kTile * gl; ib < r; ib += 8 * kTile) {
+      const u32x4* pa = (const u32x4*)(P + ib);
+      const u32x4* px = (const u32x4*)(Q + ib + l0);
+      uint32_t a[kTile], xx[2 * kTile];
+#pragma unroll
+      for (int v = 0; v < kTile / 4; ++v) {
+        const u32x4 w = pa[v];
+        a[4 * v] = w.x, a[4 * v + 1] = w.y, a[4 * v + 2] = w.z, a[4 * v + 3] = w.w;
+      }
+#pragma unroll
+      for (int v = 0; v < kTile / 2; ++v) {
+        const u32x4 w = px[v];
+        xx[4 * v] = w.x, xx[4 * v + 1] = w.y, xx[4 * v + 2] = w.z, xx[4 * v + 3] = w.w;
+      }
+#pragma unroll
+      for (int q = 0; q < kTile; ++q)
+#pragma unroll
+        for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], xx[q + u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kTile; ++u) acc[u] = group8_sum(acc[u]);
+    uint32_t mine = acc[0];
+#pragma unroll
+    for (int u = 1; u < kTile; ++u) mine = gl == u ? acc[u] : mine;
+    if (l0 + gl < r) dst[l0 + gl] = mine & g.mask;
+  }
+  if (tid == 0) {
+    const uint64_t M = g.m;
+    dst[r] = (uint32_t)(((uint64_t)c0 + M - ((uint64_t)jm * g.d) % M) % M);
+  }
+  __syncthreads();
+}
+
 // One workgroup per item.  Dynamic LDS: jump_lds_words(r).
 // P_out != nullptr: write P_J (r words per item) and stop.
 // Otherwise: states s_in -> s_out (r + 1 words per record; may alias).
+// s_in: record item at s_in + item * in_stride (in_stride 0: one shared input).
 template <bool W32>
 __global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js, const uint32_t* s_in,
-                                                  uint32_t* s_out, uint32_t* P_out, uint64_t n, uint32_t q_off) {
+                                                  uint64_t in_stride, uint32_t* s_out, uint32_t* P_out, uint64_t n,
+                                                  uint32_t q_off) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int r = (int)g.r, s = (int)g.s;
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -224,55 +285,7 @@ __global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* _
       __syncthreads();
       continue;
     }
-    // Apply: X = the r words of the state extended by r - 1 steps, in Q.
-    const uint32_t* src = s_in + item * (uint64_t)(r + 1);
-    const uint32_t c0 = src[r];
-    for (int i = tid; i < r; i += bs) Q[i] = src[i];
-    __syncthreads();
-    for (int lo = r; lo < 2 * r - 1; lo += s) {
-      const int hi = lo + s - 1 < 2 * r - 2 ? lo + s - 1 : 2 * r - 2;
-      for (int k = lo + tid; k <= hi; k += bs) Q[k] = Q[k - r] - Q[k - s];
-      __syncthreads();
-    }
-    // x'_l = sum_i b_i X_{i+l}: tiles of kTile outputs per lane group, lane gl
-    // taking the blocks kTile (gl + 8 m) of i, then the group sum.
-    uint32_t* dst = s_out + item * (uint64_t)(r + 1);
-    const int otiles = (r + kTile - 1) / kTile;
-    for (int c = 0; c * groups < otiles; ++c) {
-      const int t = c * groups + grp;
-      if (t >= otiles) continue;
-      const int l0 = t * kTile;
-      uint32_t acc[kTile];
-#pragma unroll
-      for (int u = 0; u < kTile; ++u) acc[u] = 0;
-      for (int ib = kTile * gl; ib < r; ib += 8 * kTile) {
-        const u32x4* pa = (const u32x4*)(P + ib);
-        const u32x4* px = (const u32x4*)(Q + ib + l0);
-        uint32_t a[kTile], xx[2 * kTile];
-#pragma unroll
-        for (int v = 0; v < kTile / 4; ++v) {
-          const u32x4 w = pa[v];
-          a[4 * v] = w.x, a[4 * v + 1] = w.y, a[4 * v + 2] = w.z, a[4 * v + 3] = w.w;
-        }
-#pragma unroll
-        for (int v = 0; v < kTile / 2; ++v) {
-          const u32x4 w = px[v];
-          xx[4 * v] = w.x, xx[4 * v + 1] = w.y, xx[4 * v + 2] = w.z, xx[4 * v + 3] = w.w;
-        }
-#pragma unroll
-        for (int q = 0; q < kTile; ++q)
-#pragma unroll
-          for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], xx[q + u], acc[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < kTile; ++u) acc[u] = group8_sum(acc[u]);
-      uint32_t mine = acc[0];
-#pragma unroll
-      for (int u = 1; u < kTile; ++u) mine = gl == u ? acc[u] : mine;
-      if (l0 + gl < r) dst[l0 + gl] = mine & g.mask;
-    }
-    if (tid == 0) dst[r] = c_after(c0, J, g.m, g.d);
-    __syncthreads();
+    apply_state<W32>(g, P, Q, s_in + item * in_stride, s_out + item * (uint64_t)(r + 1), j_mod_m(J, g.m));
   }
 }
 
@@ -402,8 +415,9 @@ int lfg_params_ok(const ranmar_lfg_params* p) {
 
 uint32_t lfg_jump_threads(uint32_t r) { return jump_threads(r); }
 
-hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
-                           uint32_t* P_out, uint64_t n, hipStream_t st) {
+
+static hipError_t lfg_jump_strided(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in,
+                                   uint64_t in_stride, uint32_t* s_out, uint32_t* P_out, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const LfgDev g = to_dev(p);
   const uint32_t bs = lfg_jump_threads(p.r);
@@ -411,10 +425,110 @@ hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, con
   const uint32_t q_off = jump_q_offset(p.r);
   const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
   if (p.e > 24)
-    hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n, q_off);
+    hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, in_stride, s_out, P_out,
+                       n, q_off);
   else
-    hipLaunchKernelGGL(k_lfg_jump<false>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, s_out, P_out, n, q_off);
+    hipLaunchKernelGGL(k_lfg_jump<false>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, in_stride, s_out, P_out,
+                       n, q_off);
   return hipGetLastError();
+}
+
+hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
+                           uint32_t* P_out, uint64_t n, hipStream_t st) {
+  return lfg_jump_strided(p, J, s_in, (uint64_t)p.r + 1, s_out, P_out, n, st);
+}
+
+// Families (Sec. 1 block splitting for any generator): out[k] = f^{k delta}
+// of one base state.  With A ~ sqrt(n) and B = ceil(n / A), the starts
+// a < A are direct jumps by a delta, the B - 1 shared polynomials are
+// P_{b A delta}, and every other start is out[a + b A] = P_{b A delta}
+// applied to out[a]: one r^2 application instead of a jump of ~log2(J)
+// squarings.
+__global__ void k_lfg_multiples(ranmar_u128* J, uint64_t count, uint64_t first, uint64_t step_lo, uint64_t step_hi) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const unsigned __int128 v = (unsigned __int128)(first + i) * (((unsigned __int128)step_hi << 64) | step_lo);
+  J[i] = ranmar_u128{(uint64_t)v, (uint64_t)(v >> 64)};
+}
+
+// Workgroup (x, y): polynomial b = y + 1 (LDS, padded view), starts
+// a = x per_wg .. x per_wg + per_wg - 1 (a < A, a + b A < n).
+template <bool W32>
+__global__ __launch_bounds__(256) void k_lfg_family(LfgDev g, const uint32_t* polys, uint32_t* out, uint64_t n,
+                                                    uint64_t A, uint32_t per_wg, uint32_t adm, uint32_t q_off) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  const int r = (int)g.r;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  uint32_t* P = lds + kTile;
+  uint32_t* Q = lds + q_off;
+  const uint64_t b = (uint64_t)blockIdx.y + 1;
+  const uint32_t* pb = polys + (b - 1) * (uint64_t)r;
+  for (int i = tid - kTile; i < r + 3 * kTile; i += bs) P[i] = (i >= 0 && i < r) ? pb[i] : 0u;
+  __syncthreads();
+  const uint32_t jm = (uint32_t)(((b % g.m) * (uint64_t)adm) % g.m);  // b A delta mod m
+  for (uint32_t t = 0; t < per_wg; ++t) {
+    const uint64_t a = (uint64_t)blockIdx.x * per_wg + t;
+    const uint64_t k = a + b * A;
+    if (a >= A || k >= n) break;
+    apply_state<W32>(g, P, Q, out + a * (uint64_t)(r + 1), out + k * (uint64_t)(r + 1), jm);
+  }
+}
+
+hipError_t launch_lfg_family(const ranmar_lfg_params& p, const uint32_t* base, ranmar_u128 delta, uint64_t n,
+                             uint32_t* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
+  if (n > 1 && D > ~(unsigned __int128)0 / (n - 1)) return hipErrorInvalidValue;
+  if (n > (1ull << 32)) return hipErrorInvalidValue;
+  uint64_t A = (uint64_t)std::ceil(std::sqrt((double)n));
+  if (A < 1) A = 1;
+  if (A > n) A = n;
+  const uint64_t B = (n + A - 1) / A;
+  if (B - 1 > 65535) return hipErrorInvalidValue;
+  ranmar_u128* J = nullptr;
+  uint32_t* polys = nullptr;
+  hipError_t e = hipMallocAsync((void**)&J, sizeof(ranmar_u128) * (A + B), st);
+  if (e != hipSuccess) return e;
+  if (B > 1) e = hipMallocAsync((void**)&polys, sizeof(uint32_t) * p.r * (B - 1), st);
+  if (e == hipSuccess) {
+    // J[a] = a delta (a < A); J[A + b - 1] = b A delta (1 <= b < B).
+    const unsigned __int128 AD = D * A;  // <= (n - 1) delta when B > 1
+    hipLaunchKernelGGL(k_lfg_multiples, dim3((uint32_t)((A + 255) / 256)), dim3(256), 0, st, J, A, 0ull,
+                       (uint64_t)D, (uint64_t)(D >> 64));
+    if (B > 1)
+      hipLaunchKernelGGL(k_lfg_multiples, dim3((uint32_t)((B - 1 + 255) / 256)), dim3(256), 0, st, J + A, B - 1, 1ull,
+                         (uint64_t)AD, (uint64_t)(AD >> 64));
+    e = hipGetLastError();
+    // Direct starts from the one base record (stride 0), then the polynomials.
+    if (e == hipSuccess) e = lfg_jump_strided(p, J, base, 0, out, nullptr, A, st);
+    if (e == hipSuccess && B > 1) e = lfg_jump_strided(p, J + A, nullptr, 0, nullptr, polys, B - 1, st);
+    if (e == hipSuccess && B > 1) {
+      const LfgDev g = to_dev(p);
+      int dev = 0, cus = 256;
+      if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      // Enough workgroups to fill the device a few times over; each loads its
+      // polynomial once for per_wg starts.
+      const uint64_t target = 8ull * (uint64_t)(cus > 0 ? cus : 256);
+      uint64_t per = (A * (B - 1) + target - 1) / target;
+      if (per < 1) per = 1;
+      if (per > A) per = A;
+      const uint64_t gx = (A + per - 1) / per;
+      const uint32_t adm = (uint32_t)(AD % p.m);
+      const size_t lds = jump_lds_words(p.r) * sizeof(uint32_t);
+      const uint32_t q_off = jump_q_offset(p.r);
+      const uint32_t bs = jump_threads(p.r);
+      if (p.e > 24)
+        hipLaunchKernelGGL(k_lfg_family<true>, dim3((uint32_t)gx, (uint32_t)(B - 1)), dim3(bs), lds, st, g, polys, out,
+                           n, A, (uint32_t)per, adm, q_off);
+      else
+        hipLaunchKernelGGL(k_lfg_family<false>, dim3((uint32_t)gx, (uint32_t)(B - 1)), dim3(bs), lds, st, g, polys,
+                           out, n, A, (uint32_t)per, adm, q_off);
+      e = hipGetLastError();
+    }
+  }
+  const hipError_t f1 = polys ? hipFreeAsync(polys, st) : hipSuccess;
+  const hipError_t f2 = hipFreeAsync(J, st);
+  return e != hipSuccess ? e : (f1 != hipSuccess ? f1 : f2);
 }
 
 // Launch shape of the generator: log2 of the lanes per stream, streams per

@@ -163,6 +163,11 @@ def test_lfg_argument_errors_before_device_work(L):
     assert L.ranmar_lfg_generate(ok, p(0x10000), None, 4, 10, 0, p(0x900000), 5, None) == EINVAL   # ld < count
     assert L.ranmar_lfg_generate(ok, p(0x10000), None, 4, 10, 0, p(0x10004), 10, None) == EINVAL   # out on states
     assert L.ranmar_lfg_generate(bad, p(0x10000), None, 4, 10, 0, p(0x900000), 10, None) == EINVAL
+    big = B.ranmar_u128(0, 1 << 63)
+    assert L.ranmar_lfg_jump_family(ok, p(0x10000), big, 3, p(0x20000), None) == EINVAL   # (n - 1) delta >= 2^128
+    assert L.ranmar_lfg_jump_family(ok, p(0x10000 + rec), B.ranmar_u128(1, 0), 3, p(0x10000), None) == EINVAL  # base in out
+    assert L.ranmar_lfg_jump_family(bad, p(0x10000), B.ranmar_u128(1, 0), 3, p(0x20000), None) == EINVAL
     # n == 0 with valid parameters succeeds without a device.
+    assert L.ranmar_lfg_jump_family(ok, None, B.ranmar_u128(1, 0), 0, None, None) == 0
     assert L.ranmar_lfg_jump(ok, None, None, None, 0, None) == 0
     assert L.ranmar_lfg_generate(ok, None, None, 0, 10, 0, None, 10, None) == 0

@@ -161,3 +161,57 @@ def test_lfg_rejects_bad_arguments():
     st = torch.zeros((2, 56), dtype=torch.int32, device=dev())
     with pytest.raises(R.RanmarError):
         R.ranmar_lfg_generate(p, st, 10, R.RANMAR_F32)  # float output needs e <= 24
+
+
+@pytest.mark.parametrize("name", ["r5s1e8", "r17s3e32", "ranmar", "r607s273e24", "r1000s3e16"])
+@pytest.mark.parametrize("n,delta", [(1, 5), (2, 1), (3, 97), (17, 1 << 40), (100, 12345), (1000, (1 << 100) + 7)])
+def test_lfg_family(orc, name, n, delta):
+    """Family starts out[k] = f^(k delta)(base) against the oracle's jumps."""
+    g = orc.LFG(*synth.LFG_CASES[name])
+    base = synth.lfg_states(g.r, g.e, g.m, 1, offset=33)
+    say(f"lfg_jump_family {name} n={n} delta={delta}")
+    got = u32(R.ranmar_lfg_jump_family(_params(name), _states_t(base), delta, n))
+    rows = sorted({0, 1, n // 2, n - 1} | set(int(x) for x in synth.rng(34).integers(0, n, 6))) if n > 8 else range(n)
+    rows = [k for k in rows if k < n]
+    want = g.jump_many(np.repeat(base, len(rows), 0), [k * delta for k in rows])
+    assert np.array_equal(got[rows], want), (name, n, delta)
+
+
+def test_lfg_family_equals_jumps_whole_array():
+    """Every start of a 4,100-stream family at r = 1279 equals the per-stream
+    jump to k delta (two independent GPU routes, whole array)."""
+    name = "r1279s418e24"
+    r, s, e, m, d = synth.LFG_CASES[name]
+    base = synth.lfg_states(r, e, m, 1, offset=35)
+    n, delta = 4100, (1 << 90) + 3
+    say(f"lfg family vs jumps n={n}")
+    p = _params(name)
+    fam = u32(R.ranmar_lfg_jump_family(p, _states_t(base), delta, n))
+    d = _states_t(np.repeat(base, n, 0))
+    R.ranmar_lfg_jump(p, d, jumps_t([k * delta for k in range(n)]))
+    assert np.array_equal(fam, u32(d))
+
+
+def test_lfg_family_in_place_and_full_size(orc):
+    """base == out[0] (in place), at the benchmark's family shape: 65,536
+    starts of the r = 1279 generator spaced 2^40 apart, sampled rows against
+    the oracle."""
+    name = synth.LFG_GEN["case"]
+    g = orc.LFG(*synth.LFG_CASES[name])
+    n, delta = 65_536, 1 << 40
+    base = synth.lfg_states(g.r, g.e, g.m, 1, offset=36)
+    say(f"lfg family in place n={n}")
+    out = torch.zeros((n, g.r + 1), dtype=torch.int32, device=dev())
+    out[0] = _states_t(base)[0]
+    R.ranmar_lfg_jump_family(_params(name), out[0:1], delta, n, out=out)
+    torch.cuda.synchronize()
+    rows = [0, 1, 255, 256, 257, 65_535] + [int(x) for x in synth.rng(37).integers(0, n, 6)]
+    want = g.jump_many(np.repeat(base, len(rows), 0), [k * delta for k in rows])
+    assert np.array_equal(u32(out)[rows], want)
+
+
+def test_lfg_family_rejects_overflow():
+    p = R.lfg_params(*synth.LFG_CASES["ranmar"])
+    base = torch.zeros((1, 98), dtype=torch.int32, device=dev())
+    with pytest.raises(R.RanmarError):
+        R.ranmar_lfg_jump_family(p, base, 1 << 127, 3)
