@@ -79,7 +79,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="family65k",
-                    choices=["family65k", "bulk1m", "jumps1m", "serve", "lfg_gen", "lfg_jumps"])
+                    choices=["family65k", "bulk1m", "jumps1m", "serve", "lfg_gen", "lfg_jumps", "lfg_family"])
     ap.add_argument("--serve-requests", type=int, default=synth.SERVE["requests"])
     ap.add_argument("--serve-qps", type=float, default=5e5)
     ap.add_argument("--serve-light-qps", type=float, default=2e4)
@@ -484,6 +484,45 @@ def run_lfg_jumps(R, torch, steps, warmup):
     }
 
 
+def run_lfg_family(R, torch, steps, warmup):
+    """General-generator family (block splitting at r = 1279, e = 24): 65,536
+    starts spaced 2^40 apart from one base state, one call.  ALU-bound: ~256
+    direct jumps and ~256 shared polynomials (squarings of r (r + 1) / 2
+    multiply-adds), and an r^2 application for every start."""
+    import math
+    n, delta = synth.FAMILY_65K["streams"], synth.FAMILY_65K["spacing"]
+    p, base = _lfg_setup(R, torch, 1, offset=38)
+    out = torch.empty((n, p.r + 1), dtype=torch.int32, device=torch.device("cuda:0"))
+    tm = Timer(torch)
+    for _ in range(warmup):
+        R.ranmar_lfg_jump_family(p, base, delta, n, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b = tm.span("lfg_family")
+        a.record()
+        R.ranmar_lfg_jump_family(p, base, delta, n, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms = tm.mean_ms("lfg_family")
+    r = p.r
+    A = max(1, min(n, math.ceil(math.sqrt(n))))
+    B = (n + A - 1) // A
+    sq = sum(lfg_squarings(a * delta, r) for a in range(A)) + sum(lfg_squarings(b * A * delta, r) for b in range(1, B))
+    macs = float(sq) * r * (r + 1) / 2 + float(A) * r * r + float(n - A) * r * r
+    ach = macs / (ms * 1e-3) / 1e12
+    return {
+        "metric": "starts/s", "value": n / dt, "unit": "starts/s", "ms_per_step": dt * 1e3, "dtype": "u24",
+        "config": {"workload": f"lfg_family: {n} starts spaced 2^40 of the general generator (r, s, e) = "
+                               f"({p.r}, {p.s}, {p.e}), one call ({A} direct jumps, {B - 1} shared polynomials, "
+                               f"{n - A} applications)", "starts": n},
+        "roofline": {"bound": "alu", "kernel": "k_lfg_jump + k_lfg_family (whole call)", "achieved": ach,
+                     "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s (24-bit multiply-adds)",
+                     "frac": ach / VALU_PEAK_TOPS, "traffic": None, "ops_per_launch": macs, "launch_ms": ms},
+    }
+
+
 def run_paper_table1(R, torch, steps, warmup):
     """The paper's Table 1 workload on the GPU: 10^9 draws of ONE stream (seed
     12345, uint32).  Block splitting (Sec. 1): segment k of 16,000 draws starts
@@ -701,6 +740,8 @@ def main():
         res = run_lfg_gen(R, torch, a.steps, a.warmup)
     elif a.workload == "lfg_jumps":
         res = run_lfg_jumps(R, torch, a.steps, a.warmup)
+    elif a.workload == "lfg_family":
+        res = run_lfg_family(R, torch, a.steps, a.warmup)
     else:
         res = run_jumps1m(R, torch, a.steps, a.warmup)
     line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"], "n_gpus": 1, "steps": a.steps,
@@ -725,6 +766,9 @@ def main():
             if not a.no_cpu:
                 also[name]["cpu_baseline"] = cpu_baseline(name, min(a.cpu_seconds, 3.0))
             _progress(f"{name} done")
+        r = run_lfg_family(R, torch, 5, 1)
+        also["lfg_family"] = {k: r[k] for k in r if k not in ("metric",)}
+        _progress("lfg_family done")
         also["paper_table1"] = run_paper_table1(R, torch, 5, 1)
         also["paper_table2"] = run_paper_table2(R, torch)
         _progress("paper tables done")
@@ -744,7 +788,7 @@ def main():
             also[f"serve_{int(frac * 100)}pct_of_saturation"] = {"config": r["config"], **r["serve"]}
         _progress("serve saturation sweep done")
         line["also"] = also
-    if not a.no_cpu and a.workload not in ("lfg_gen", "lfg_jumps"):
+    if not a.no_cpu and a.workload not in ("lfg_gen", "lfg_jumps", "lfg_family"):
         _progress("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
     print(json.dumps(line), flush=True)
