@@ -12,8 +12,13 @@
 // live in an LDS ring of Z >= r + W words (Z a power of two); W lanes of a
 // wave (W = min(s, 64) rounded down to a power of two) produce W consecutive
 // words per step, since x_n .. x_{n+W-1} depend only on words older than x_n
-// when W <= s.  64 / W streams share a wave, and each stream's W draws of a
-// step form one contiguous store.
+// when W <= s; U steps (U W <= s, U <= 4) read all their operands before any
+// is written.  Up to 64 / W streams share a wave (fewer when their rings would
+// not fit), and each stream's W draws of a step form one contiguous store.
+//
+// Families (Sec. 1, block splitting): ~sqrt(n) direct jumps and ~sqrt(n)
+// shared polynomials, every other start one polynomial applied to a direct
+// start.
 //
 // Arithmetic is kept mod 2^32 and masked to e bits on output: for e <= 24 the
 // products use v_mad_u32_u24 (exact in the low 24 bits), for e > 24 the full
@@ -72,13 +77,12 @@ __device__ __forceinline__ void fold_phi(uint32_t* Q, int r, int s, int top, int
   }
 }
 
-// Square of P into Q[k0 .. k0 + kTile - 1] (k < 2r - 1 only):
-// Q[k] = 2 sum_{i < k - i} P_i P_{k-i} + [k even] P_{k/2}^2.  P is read through
-// a zero-padded view (P[i] = 0 for i < 0 and i >= r), so the ranges need no
-// bounds tests: blocks of kTile terms i, each with the kTile + kTile - 1 words
-// P[k0 - i ..] they meet held in registers (about 0.27 LDS reads per
-// multiply-add instead of 2).  Blocks that reach the diagonal keep a term only
-// when 2 i < k.
+// Squares and applications work on tiles of kTile consecutive outputs, the
+// square as Q[k] = 2 sum_{i < k - i} P_i P_{k-i} + [k even] P_{k/2}^2.  P is
+// read through a zero-padded view (P[i] = 0 for i < 0 and i >= r), so the
+// ranges need no bounds tests: blocks of kTile terms i, each with the
+// 2 kTile - 1 words P[k0 - i ..] they meet held in registers (six 16-byte LDS
+// reads per kTile^2 multiply-adds instead of two 4-byte reads per multiply-add).
 constexpr int kTile = 8;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
