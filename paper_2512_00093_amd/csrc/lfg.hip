@@ -238,13 +238,13 @@ __device__ __forceinline__ void apply_state(const LfgDev& g, const uint32_t* P, 
 }
 
 // One workgroup per item.  Dynamic LDS: jump_lds_words(r).
-// P_out != nullptr: write P_J (r words per item) and stop.
-// Otherwise: states s_in -> s_out (r + 1 words per record; may alias).
-// s_in: record item at s_in + item * in_stride (in_stride 0: one shared input).
+// Items below n_state jump states s_in -> s_out (r + 1 words per record; may
+// alias), the record of item q at s_in + q * in_stride (in_stride 0: one shared
+// input).  Items from n_state on write P_J (r words each) to P_out and stop.
 template <bool W32>
 __global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* __restrict__ Js, const uint32_t* s_in,
                                                   uint64_t in_stride, uint32_t* s_out, uint32_t* P_out, uint64_t n,
-                                                  uint32_t q_off) {
+                                                  uint64_t n_state, uint32_t q_off) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int r = (int)g.r, s = (int)g.s;
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -284,8 +284,8 @@ __global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* _
       for (int i = tid; i < r; i += bs) P[i] = next(i);
       __syncthreads();
     }
-    if (P_out) {
-      for (int i = tid; i < r; i += bs) P_out[item * r + i] = P[i] & g.mask;
+    if (item >= n_state) {
+      for (int i = tid; i < r; i += bs) P_out[(item - n_state) * r + i] = P[i] & g.mask;
       __syncthreads();
       continue;
     }
@@ -421,7 +421,8 @@ uint32_t lfg_jump_threads(uint32_t r) { return jump_threads(r); }
 
 
 static hipError_t lfg_jump_strided(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in,
-                                   uint64_t in_stride, uint32_t* s_out, uint32_t* P_out, uint64_t n, hipStream_t st) {
+                                   uint64_t in_stride, uint32_t* s_out, uint32_t* P_out, uint64_t n, uint64_t n_state,
+                                   hipStream_t st) {
   if (n == 0) return hipSuccess;
   const LfgDev g = to_dev(p);
   const uint32_t bs = lfg_jump_threads(p.r);
@@ -430,16 +431,16 @@ static hipError_t lfg_jump_strided(const ranmar_lfg_params& p, const ranmar_u128
   const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
   if (p.e > 24)
     hipLaunchKernelGGL(k_lfg_jump<true>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, in_stride, s_out, P_out,
-                       n, q_off);
+                       n, n_state, q_off);
   else
     hipLaunchKernelGGL(k_lfg_jump<false>, dim3((uint32_t)grid), dim3(bs), lds, st, g, J, s_in, in_stride, s_out, P_out,
-                       n, q_off);
+                       n, n_state, q_off);
   return hipGetLastError();
 }
 
 hipError_t launch_lfg_jump(const ranmar_lfg_params& p, const ranmar_u128* J, const uint32_t* s_in, uint32_t* s_out,
                            uint32_t* P_out, uint64_t n, hipStream_t st) {
-  return lfg_jump_strided(p, J, s_in, (uint64_t)p.r + 1, s_out, P_out, n, st);
+  return lfg_jump_strided(p, J, s_in, (uint64_t)p.r + 1, s_out, P_out, n, P_out ? 0 : n, st);
 }
 
 // Families (Sec. 1 block splitting for any generator): out[k] = f^{k delta}
@@ -503,9 +504,9 @@ hipError_t launch_lfg_family(const ranmar_lfg_params& p, const uint32_t* base, r
       hipLaunchKernelGGL(k_lfg_multiples, dim3((uint32_t)((B - 1 + 255) / 256)), dim3(256), 0, st, J + A, B - 1, 1ull,
                          (uint64_t)AD, (uint64_t)(AD >> 64));
     e = hipGetLastError();
-    // Direct starts from the one base record (stride 0), then the polynomials.
-    if (e == hipSuccess) e = lfg_jump_strided(p, J, base, 0, out, nullptr, A, st);
-    if (e == hipSuccess && B > 1) e = lfg_jump_strided(p, J + A, nullptr, 0, nullptr, polys, B - 1, st);
+    // One launch: the direct starts from the one base record (stride 0) and
+    // the polynomials, which are independent and run side by side.
+    if (e == hipSuccess) e = lfg_jump_strided(p, J, base, 0, out, polys, A + (B - 1), A, st);
     if (e == hipSuccess && B > 1) {
       const LfgDev g = to_dev(p);
       int dev = 0, cus = 256;
