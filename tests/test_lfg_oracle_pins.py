@@ -222,3 +222,17 @@ def test_c_jump(orc, name):
     assert g.c_jump(c, g.m) == c
     big = (1 << 127) + 12345
     assert g.c_jump(c, big) == g.c_jump(c, big % g.m)
+
+
+@pytest.mark.parametrize("name", ["r2s1e3", "r5s1e8", "r10s7e16"])
+def test_c_sequence_every_start(orc, name):
+    """Sec. 2 (f_2): from every c_0 in [0, m), k transitions give
+    (c_0 - k d) mod m, always below m (the boundary c = d included)."""
+    g = orc.LFG(*synth.LFG_CASES[name])
+    u = np.zeros(g.r + 1, np.uint32)
+    for c0 in sorted(set(range(min(g.m, 40))) | {g.d, (g.d + 1) % g.m, g.m - 1}):
+        u[g.r] = c0
+        for k in (1, 2, g.m - 1, g.m, 2 * g.m + 3):
+            c = int(g.step(u, k)[g.r])
+            assert c == (c0 - k * g.d) % g.m and c < g.m, (name, c0, k)
+
