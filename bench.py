@@ -120,7 +120,7 @@ def _cpu_worker(args):
             g = O.LFG(*synth.LFG_CASES[synth.LFG_GEN["case"]])
             g.draws_many(k, synth.LFG_GEN["draws"], want_states=True)
             units += synth.LFG_GEN["draws"]
-        elif kind == "lfg_jumps":
+        elif kind in ("lfg_jumps", "lfg_family"):
             g = O.LFG(*synth.LFG_CASES[synth.LFG_JUMPS["case"]])
             st, J = k
             g.jump_many(st, [J])
@@ -141,6 +141,13 @@ def cpu_baseline(kind: str, seconds: float):
         s, lo, hi = synth.batch_jumps(4000 * workers, 120, offset=4)
         items = list(zip(s.tolist(), lo.tolist(), hi.tolist()))
         unit, sample = "jumps/s", "seed + jump of 10^6-workload requests (J uniform 120-bit)"
+    elif kind == "lfg_family":
+        r, _, e, m, _ = synth.LFG_CASES[synth.LFG_GEN["case"]]
+        base = synth.lfg_states(r, e, m, 1, offset=38)[0]
+        n = synth.FAMILY_65K["streams"]
+        ks = synth.rng(39).choice(n, size=64 * workers, replace=False)
+        items = [(base, int(k) * synth.FAMILY_65K["spacing"]) for k in ks]
+        unit, sample = "starts/s", f"starts of the r = {r} family: oracle jump of the base state to k * 2^40"
     elif kind in ("lfg_gen", "lfg_jumps"):
         r, _, e, m, _ = synth.LFG_CASES[synth.LFG_GEN["case"]]
         n_items = (4096 if kind == "lfg_gen" else 64) * workers
@@ -768,6 +775,8 @@ def main():
             _progress(f"{name} done")
         r = run_lfg_family(R, torch, 5, 1)
         also["lfg_family"] = {k: r[k] for k in r if k not in ("metric",)}
+        if not a.no_cpu:
+            also["lfg_family"]["cpu_baseline"] = cpu_baseline("lfg_family", min(a.cpu_seconds, 3.0))
         _progress("lfg_family done")
         also["paper_table1"] = run_paper_table1(R, torch, 5, 1)
         also["paper_table2"] = run_paper_table2(R, torch)
