@@ -767,8 +767,8 @@ def main():
             _progress(f"{name} done")
         also["jumps1m_batched"] = run_jumps1m_batched(R, torch, 5, 1)
         _progress("jumps1m_batched done")
-        for name, fn in (("lfg_gen", run_lfg_gen), ("lfg_jumps", run_lfg_jumps)):
-            r = fn(R, torch, 5, 1)
+        for name, fn, st_, wu_ in (("lfg_gen", run_lfg_gen, 20, 5), ("lfg_jumps", run_lfg_jumps, 5, 1)):
+            r = fn(R, torch, st_, wu_)
             also[name] = {k: r[k] for k in r if k not in ("metric",)}
             if not a.no_cpu:
                 also[name]["cpu_baseline"] = cpu_baseline(name, min(a.cpu_seconds, 3.0))
