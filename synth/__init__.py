@@ -123,6 +123,7 @@ LFG_CASES = {
     "r1000s3e16": (1000, 3, 16, 65521, 77),  # large r, small s: many small rings per wave
     "r1279s418e24": (1279, 418, 24, 16777213, 7654321),  # RANMAR's precision and c constants
     "r200s150e20": (200, 150, 20, 1048573, 12345),  # 128 <= s < 256: two 64-word steps at once
+    "r5120s2000e24": (5120, 2000, 24, 16777213, 7654321),  # the largest order the library accepts
 }
 # Throughput workload of the general path: 65,536 streams of the r = 1279
 # generator, 4,096 draws each (the family65k shape at a 13x larger state).
