@@ -123,8 +123,9 @@ __device__ __forceinline__ uint32_t group8_sum(uint32_t v) {
 // group: lane l takes the blocks ib0 + kTile (l + 8 m) among those whose
 // every term has 2 i < k0, i.e. belongs to all kTile outputs of the tile, so
 // the blocks need no predicate.  After the group sum, lane l owns output
-// k0 + l and adds the few terms ib_stop <= i < k - i that are left (at most
-// kTile) one by one.
+// k0 + l; the terms ib_stop <= i < k - i that are left all lie in the one
+// block starting at ib_stop (k0 is a multiple of kTile), which lane l adds
+// with a predicate per term.
 template <bool W32>
 __device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int r, int k0, int l) {
   uint32_t acc[kTile];
@@ -148,7 +149,17 @@ __device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int
 #pragma unroll
   for (int u = 1; u < kTile; ++u) mine = l == u ? acc[u] : mine;
   const int k = k0 + l;
-  for (int i = ib_stop; 2 * i < k; ++i) mine = mac<W32>(Pp[i], Pp[k - i], mine);
+  {  // the terms left all lie in the block ib_stop .. ib_stop + kTile - 1
+    const u32x4* pa = (const u32x4*)(Pp + ib_stop);
+    const u32x4 w0 = pa[0], w1 = pa[1];
+    const uint32_t a[kTile] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    const int lim = k - 2 * ib_stop;  // term ib_stop + q belongs to output k when 2 q < lim
+#pragma unroll
+    for (int q = 0; q < kTile; ++q) {
+      const uint32_t t = mac<W32>(a[q], Pp[k - ib_stop - q], mine);
+      mine = 2 * q < lim ? t : mine;
+    }
+  }
   if (k < 2 * r - 1) {
     uint32_t v = mine << 1;
     if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
