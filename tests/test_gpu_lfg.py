@@ -215,3 +215,23 @@ def test_lfg_family_rejects_overflow():
     base = torch.zeros((1, 98), dtype=torch.int32, device=dev())
     with pytest.raises(R.RanmarError):
         R.ranmar_lfg_jump_family(p, base, 1 << 127, 3)
+
+
+def test_lfg_family_large_equals_ranmar_family(orc):
+    """At RANMAR's parameters, a 2^20-start general family (1,023 shared
+    polynomials) equals, whole array, the RANMAR family of the same base
+    (int8 matrix-core products: an independent route), and sampled rows
+    equal the oracle."""
+    n, delta = 1 << 20, (1 << 40) + 9
+    base = orc.state_from_seed(4711)
+    say(f"lfg family vs ranmar family n={n}")
+    p = R.lfg_params(*orc.RANMAR_PARAMS)
+    d_base = _states_t(base[None, :])
+    gen = R.ranmar_lfg_jump_family(p, d_base, delta, n)
+    spec = torch.empty_like(gen)
+    R.ranmar_jump_family(d_base, delta, n, out=spec)
+    torch.cuda.synchronize()
+    assert torch.equal(gen, spec)
+    rows = [0, 1, 1023, 1024, 1025, n - 1] + [int(x) for x in synth.rng(40).integers(0, n, 4)]
+    for k in rows:
+        assert np.array_equal(u32(gen[k]), orc.jump(base, k * delta)), k
