@@ -235,3 +235,28 @@ def test_lfg_family_large_equals_ranmar_family(orc):
     rows = [0, 1, 1023, 1024, 1025, n - 1] + [int(x) for x in synth.rng(40).integers(0, n, 4)]
     for k in rows:
         assert np.array_equal(u32(gen[k]), orc.jump(base, k * delta)), k
+
+
+def test_lfg_full_size_equals_ranmar_kernels(orc):
+    """At RANMAR's parameters and full size, whole arrays: 16,384 general
+    jumps (uniform 120-bit J) equal the windowed RANMAR jump, and 65,536
+    streams x 4,096 general draws equal the RANMAR generator."""
+    p = R.lfg_params(*orc.RANMAR_PARAMS)
+    n = 16384
+    seeds = synth.seeds(n, offset=41)
+    lo, hi = synth.u128_uniform(synth.rng(42), n, 120)
+    jt = jumps_t(synth.u128_to_int(lo, hi))
+    say(f"lfg vs ranmar jump n={n}")
+    st = R.ranmar_seed_batch(torch.from_numpy(seeds.copy()).to(dev()))
+    gen = st.clone()
+    R.ranmar_lfg_jump(p, gen, jt)
+    R.ranmar_jump(st, jt)
+    torch.cuda.synchronize()
+    assert torch.equal(gen, st)
+    fam = synth.FAMILY_65K
+    say(f"lfg vs ranmar generate {fam['streams']} x {fam['draws']}")
+    starts = R.ranmar_rank_streams(fam["seed"], fam["spacing"], 0, fam["streams"], device=dev())
+    a = R.ranmar_lfg_generate(p, starts, fam["draws"], R.RANMAR_U24)
+    b = R.ranmar_generate(starts, fam["draws"], R.RANMAR_U24)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
