@@ -119,12 +119,19 @@ __device__ __forceinline__ uint32_t group8_sum(uint32_t v) {
   return v;
 }
 
-// One tile of the square, its term blocks split over the 8 lanes of a lane
-// group: lane l takes the blocks ib0 + kTile (l + 8 m) among those whose
-// every term has 2 i < k0, i.e. belongs to all kTile outputs of the tile, so
-// the blocks need no predicate.  After the group sum, lane l owns output
-// k0 + l; the terms ib_stop <= i < k - i that are left all lie in the one
-// block starting at ib_stop (k0 is a multiple of kTile), which lane l adds
+// Sum over the 4 lanes of an aligned quad, left in every lane of it.
+__device__ __forceinline__ uint32_t group4_sum(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+  return v;
+}
+
+// One tile of the square, its term blocks split over the 4 lanes of a quad:
+// lane l takes the blocks ib0 + kTile (l + 4 m) among those whose every term
+// has 2 i < k0, i.e. belongs to all kTile outputs of the tile, so the blocks
+// need no predicate.  After the quad sum, lane l owns outputs k0 + l and
+// k0 + l + 4; the terms ib_stop <= i < k - i left for each all lie in the one
+// block starting at ib_stop (k0 is a multiple of kTile), which the lane adds
 // with a predicate per term.
 template <bool W32>
 __device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int r, int k0, int l) {
@@ -135,7 +142,7 @@ __device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int
   const int ib0 = ilo & ~(kTile - 1);
   const int span = ((k0 - 1) >> 1) - ib0 + 1;  // terms ib0 .. (k0 - 1) / 2
   const int ib_stop = ib0 + (span >= kTile ? span / kTile * kTile : 0);
-  for (int ib = ib0 + kTile * l; ib < ib_stop; ib += 8 * kTile) {
+  for (int ib = ib0 + kTile * l; ib < ib_stop; ib += 4 * kTile) {
     uint32_t a[kTile], x[2 * kTile - 1];
     load_block(Pp, ib, k0, a, x);
 #pragma unroll
@@ -144,37 +151,38 @@ __device__ __forceinline__ void square_tile(const uint32_t* Pp, uint32_t* Q, int
       for (int u = 0; u < kTile; ++u) acc[u] = mac<W32>(a[q], x[u - q + kTile - 1], acc[u]);
   }
 #pragma unroll
-  for (int u = 0; u < kTile; ++u) acc[u] = group8_sum(acc[u]);
-  uint32_t mine = acc[0];
+  for (int u = 0; u < kTile; ++u) acc[u] = group4_sum(acc[u]);
+  const u32x4* pa = (const u32x4*)(Pp + ib_stop);
+  const u32x4 w0 = pa[0], w1 = pa[1];
+  const uint32_t a[kTile] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-  for (int u = 1; u < kTile; ++u) mine = l == u ? acc[u] : mine;
-  const int k = k0 + l;
-  {  // the terms left all lie in the block ib_stop .. ib_stop + kTile - 1
-    const u32x4* pa = (const u32x4*)(Pp + ib_stop);
-    const u32x4 w0 = pa[0], w1 = pa[1];
-    const uint32_t a[kTile] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+  for (int h = 0; h < 2; ++h) {
+    uint32_t mine = acc[4 * h];
+#pragma unroll
+    for (int u = 1; u < 4; ++u) mine = l == u ? acc[4 * h + u] : mine;
+    const int k = k0 + l + 4 * h;
     const int lim = k - 2 * ib_stop;  // term ib_stop + q belongs to output k when 2 q < lim
 #pragma unroll
     for (int q = 0; q < kTile; ++q) {
       const uint32_t t = mac<W32>(a[q], Pp[k - ib_stop - q], mine);
       mine = 2 * q < lim ? t : mine;
     }
-  }
-  if (k < 2 * r - 1) {
-    uint32_t v = mine << 1;
-    if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
-    Q[k] = v;
+    if (k < 2 * r - 1) {
+      uint32_t v = mine << 1;
+      if (!(k & 1)) v = mac<W32>(Pp[k >> 1], Pp[k >> 1], v);
+      Q[k] = v;
+    }
   }
 }
 
-// Threads of the jump workgroup: 8 lanes per tile of kTile outputs, up to 32
-// lane groups.  Group g squares the tiles c NG + g (c even) and
+// Threads of the jump workgroup: 4 lanes per tile of kTile outputs in the
+// square, up to 64 quads.  Quad g squares the tiles c NG + g (c even) and
 // (c + 1) NG - 1 - g (c odd) of the T = ceil((2r - 1) / kTile) tiles, NG the
-// number of groups: the sweep alternates direction, which balances the
-// triangular work profile across groups.
+// number of quads: the sweep alternates direction, which balances the
+// triangular work profile across quads.
 uint32_t jump_threads(uint32_t r) {
   const uint32_t tiles = (2 * r - 1 + kTile - 1) / kTile;
-  const uint32_t lanes = 8 * tiles;
+  const uint32_t lanes = 4 * tiles;
   return lanes >= 256 ? 256u : (lanes + 63) / 64 * 64;
 }
 
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(256) void k_lfg_jump(LfgDev g, const ranmar_u128* _
   const int tid = threadIdx.x, bs = blockDim.x;
   uint32_t* P = lds + kTile;  // P[-kTile .. r + 3 kTile - 1]; zero outside [0, r)
   uint32_t* Q = lds + q_off;
-  const int tiles = (2 * r - 1 + kTile - 1) / kTile, groups = bs / 8, grp = tid >> 3, gl = tid & 7;
+  const int tiles = (2 * r - 1 + kTile - 1) / kTile, groups = bs / 4, grp = tid >> 2, gl = tid & 3;
   for (uint64_t item = blockIdx.x; item < n; item += gridDim.x) {
     const ranmar_u128 J = Js[item];
     // Leading bits of J that form an exponent below r give a monomial start.
