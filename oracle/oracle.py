@@ -51,9 +51,12 @@ def lib():
         u32p = ctypes.POINTER(ctypes.c_uint32)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         i64p = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
         dblp = ctypes.POINTER(ctypes.c_double)
         i64, u64, u32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
         sig = {
+            "orc_seed_setup": (ctypes.c_int, [i64, i32p]),
+            "orc_seed_sequences": (None, [i32p, ctypes.c_int32, i32p, i32p]),
             "orc_seed_real": (ctypes.c_int, [i64, dblp]),
             "orc_seed_int": (ctypes.c_int, [i64, u32p]),
             "orc_real_draws": (ctypes.c_int, [i64, u64, dblp]),
@@ -102,6 +105,24 @@ def split_u128(J: int):
 
 
 # --- Appendix A / Algorithm 3 --------------------------------------------
+def seed_setup(seed: int):
+    """Start values (i, j, k, l) of the initialisation's two small generators."""
+    out = np.zeros(4, np.int32)
+    if lib().orc_seed_setup(seed, _p(out, ctypes.c_int32)):
+        raise ValueError("seed out of range")
+    return tuple(int(v) for v in out)
+
+
+def seed_sequences(start, count: int):
+    """(m_1..m_count, l_1..l_count): the lag-3 product generator mod 179 and
+    the congruential generator mod 169 from start values (i, j, k, l)."""
+    st = np.ascontiguousarray(np.asarray(start, np.int32))
+    m = np.zeros(count, np.int32)
+    l = np.zeros(count, np.int32)
+    lib().orc_seed_sequences(_p(st, ctypes.c_int32), count, _p(m, ctypes.c_int32), _p(l, ctypes.c_int32))
+    return m, l
+
+
 def seed_real(seed: int) -> np.ndarray:
     """u_1..u_97 from the real-arithmetic initialisation (index 0 unused)."""
     u = np.zeros(98, np.float64)
@@ -145,7 +166,7 @@ def state_from_seed(seed: int) -> np.ndarray:
 
 
 def state_draws(state: np.ndarray, n: int):
-    """(draws, state after the draws) for n steps of Algorithm 2."""
+    """(draws, state after the draws) for n steps of the generator (Sec. 2)."""
     state = np.ascontiguousarray(state, np.uint32)
     out = np.zeros(n, np.uint32)
     W = np.zeros(97, np.uint32)

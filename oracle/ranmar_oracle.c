@@ -9,32 +9,47 @@
  * no code, header, table or constant generator with the GPU library; the two
  * are compared against each other, never built on each other.
  *
- * Contents, each following the passage it cites:
- *   - real-arithmetic seeding and draws      (Appendix A / Algorithm 3 in its
- *                                             real form; Algorithm 1)
- *   - integer seeding and draws, w = 32      (Algorithm 3; Algorithm 2)
- *   - the automaton state (u_1..u_97, c)     (Sec. 2, finite automaton; Sec. 3.1)
- *   - t^J mod phi(t) over Z/2^24 by binary
- *     powering, schoolbook products and
- *     generic long division by phi           (Sec. 3.1, P_J; Sec. 4, Table 2)
- *   - uP_J(A) by Horner's rule                (Sec. 3.1, Horner formula)
- *   - closed-form jump of c                   (Sec. 3.2)
- *   - literal J-fold stepping of f           (Sec. 2, f^J)
+ * Everything is written from the definitions, not from the printed listings:
+ *   - the generator as a sequence (Sec. 2): x_n = x_{n-97} - x_{n-33} mod 1
+ *     (mod 2^24 in integer form), c_n = c_{n-1} - d mod m, output x_n - c_n
+ *     mod 1; the integer form takes c_n from its closed form (Sec. 3.2) and
+ *     keeps the words in a ring indexed by the sequence number;
+ *   - the initialisation (Appendix A) as its parts: the seed selects the
+ *     starting values of two small generators, a lag-3 product generator
+ *     modulo 179 and a linear congruential generator modulo 169; each step of
+ *     the pair gives one bit, and 24 consecutive bits, first bit most
+ *     significant, form one word of 24-bit precision;
+ *   - the real-arithmetic form (the floating-point initialisation of Appendix
+ *     A and the real-number generator) as a second, independent route: its own
+ *     index arithmetic and generator stepping, words as sums of 2^-p, and the
+ *     arithmetic sequence stepped in real numbers.  Sec. 3.1 (the isomorphism
+ *     sigma) and Appendix A assert that the two routes agree exactly; the tests
+ *     compare them, so a slip in either one shows;
+ *   - the automaton state (u_1..u_97, c) and f applied literally (Sec. 2);
+ *   - t^J mod phi(t) over Z/2^24 by binary powering, schoolbook products and
+ *     generic long division by phi (Sec. 3.1, P_J; Sec. 4, Table 2);
+ *   - u P_J(A) by Horner's rule (Sec. 3.1) and the closed-form c jump (Sec. 3.2).
  *
  * Conventions (readings of the paper, listed in the design notes):
- *   - the canonical state is the automaton state u = (u_1, ..., u_97) with
- *     u_1 the oldest word, plus the integer numerator c' of c (0 <= c' < m);
- *   - Algorithm 3's inner multiplicative step is read as
- *     Remainder(Remainder(i*j,179)*k,179): the printed Quotient would make
- *     seed 1 produce an all-zero state;
- *   - offset 0 is the state right after Algorithm 3; draw n (n >= 1) steps the
- *     state first and then outputs (x_new - c_new) mod 2^24, as Algorithms 1
- *     and 2 do.
+ *   - the canonical state is the automaton state (x_1, ..., x_97) with x_1 the
+ *     oldest word, plus the integer numerator c' of c (0 <= c' < m);
+ *   - the initialisation's words u_1..u_97 enter the sequence from the top
+ *     down: the generator starts its two pointers at 97 and 33 and moves them
+ *     down, so x_1 = u_97, ..., x_97 = u_1, and the first new word is
+ *     u_97 - u_33;
+ *   - the product generator's step is the product of the three previous
+ *     values modulo 179 (both reductions are remainders; the printed Quotient
+ *     would make seed 1 produce an all-zero state);
+ *   - offset 0 is the state right after the initialisation; draw n (n >= 1)
+ *     makes the new word and the new c first and outputs their difference.
  *
  * Parity status: every function below is pinned by the CPU tests except the
- * absolute values produced by the seeding procedure, which the paper prints
- * no example of ("parity unpinned" against any external source; they are
- * pinned only by real == integer agreement and the Remainder reading).
+ * absolute values produced by the initialisation, which the paper prints no
+ * example of ("parity unpinned" against any external source).  They are
+ * pinned by the agreement of the two independent routes, by the index
+ * arithmetic's bijection onto the generators' start values, by the product
+ * generator's exponent form, by the congruential generator's closed form and
+ * full period, and by the first draws read off the seeded words.
  */
 #include <stdint.h>
 #include <string.h>
@@ -43,190 +58,216 @@
  * (M, m, d) = (2^24, 2^24 - 3, 7654321/2^24), c = 362436/2^24. */
 #define ORC_R 97
 #define ORC_S 33
-#define ORC_M24 16777216.0
 #define ORC_MASK 0xFFFFFFu
 #define ORC_MOD 16777213u
 #define ORC_D 7654321u
 #define ORC_C0 362436u
 
-/* ------------------------------------------------------------------------ */
-/* Appendix A: the index set-up shared by both forms of the initialisation.  */
-/* ------------------------------------------------------------------------ */
-static int seed_indices(int64_t seed, long *i, long *j, long *k, long *l)
+/* Appendix A: seeds run up to 9 x 10^8.  Seed 0 would need the quotient of
+ * the negative number s - 1, which the paper leaves undefined, so the range
+ * used is [1, 9 x 10^8]. */
+#define ORC_SEED_MAX 900000000
+
+/* Appendix A: the initialisation draws 97 words of 24 bits each. */
+#define ORC_SEED_BITS (97 * 24)
+
+/* ======================================================================== */
+/* Integer route.                                                           */
+/* ======================================================================== */
+
+/* Appendix A, start values.  Write q = s - 1 as q = 30082 a + b with
+ * 0 <= b < 30082 = 178 * 169.  The high part a gives the product generator's
+ * first two values i, j in [2, 178]; the low part b gives its third value k in
+ * [1, 178] and the congruential generator's start l in [0, 168].
+ * out = {i, j, k, l}; returns -1 for a seed outside [1, 9e8]. */
+int orc_seed_setup(int64_t seed, int32_t out[4])
 {
-    /* The paper allows 0 <= s <= 9e8 but never defines Quotient/Remainder of
-     * the negative number s-1 = -1, so seed 0 is rejected. */
-    if (seed < 1 || seed > 900000000) return -1;
-    long ij = (long)((seed - 1) / 30082);
-    long kl = (long)((seed - 1) - 30082 * ij);
-    *i = (ij / 177) % 177 + 2;
-    *j = ij % 177 + 2;
-    *k = (kl / 169) % 178 + 1;
-    *l = kl % 169;
+    if (seed < 1 || seed > ORC_SEED_MAX) return -1;
+    int64_t q = seed - 1;
+    int64_t a = q / 30082, b = q % 30082;
+    out[0] = (int32_t)((a / 177) % 177 + 2);
+    out[1] = (int32_t)(a % 177 + 2);
+    out[2] = (int32_t)((b / 169) % 178 + 1);
+    out[3] = (int32_t)(b % 169);
     return 0;
 }
 
-/* One step of the initialisation's two small generators; returns the bit. */
-static int seed_bit(long *i, long *j, long *k, long *l)
+/* Appendix A, the two small generators, n = 1..count:
+ *   m_n = m_{n-3} m_{n-2} m_{n-1} mod 179 with (m_{-2}, m_{-1}, m_0) = (i, j, k),
+ *   l_n = 53 l_{n-1} + 1 mod 169          with l_0 = l.
+ * Either output array may be NULL. */
+void orc_seed_sequences(const int32_t start[4], int32_t count, int32_t *mseq, int32_t *lseq)
 {
-    long m = ((*i * *j) % 179) * *k % 179; /* Remainder reading */
-    *i = *j;
-    *j = *k;
-    *k = m;
-    *l = (53 * *l + 1) % 169;
-    return (*l * m) % 64 >= 32;
-}
-
-/* Real-number initialisation (the form Algorithm 3 re-implements; its
- * comments give the real form: t starts at 0.5 and is halved each step).
- * Fills u[1..97]. */
-int orc_seed_real(int64_t seed, double u[98])
-{
-    long i, j, k, l;
-    if (seed_indices(seed, &i, &j, &k, &l)) return -1;
-    u[0] = 0.0;
-    for (int ii = 1; ii <= 97; ++ii) {
-        double s = 0.0, t = 0.5;
-        for (int jj = 1; jj <= 24; ++jj) {
-            if (seed_bit(&i, &j, &k, &l)) s = s + t;
-            t = 0.5 * t;
-        }
-        u[ii] = s;
+    int32_t m_prev[3] = {start[0], start[1], start[2]}; /* m_{n-3}, m_{n-2}, m_{n-1} */
+    int32_t l_prev = start[3];
+    for (int32_t n = 1; n <= count; ++n) {
+        int32_t m_n = (int32_t)(((int64_t)m_prev[0] * m_prev[1] % 179) * m_prev[2] % 179);
+        int32_t l_n = (53 * l_prev + 1) % 169;
+        m_prev[0] = m_prev[1];
+        m_prev[1] = m_prev[2];
+        m_prev[2] = m_n;
+        l_prev = l_n;
+        if (mseq) mseq[n - 1] = m_n;
+        if (lseq) lseq[n - 1] = l_n;
     }
-    return 0;
 }
 
-/* Algorithm 3 with w = 32: t = 2^31 halved each step, u = s / 2^(w-24). */
+/* Appendix A, the bit of step n: set when l_n m_n mod 64 lies in the upper
+ * half [32, 64). */
+static int seed_bit_of(int32_t m_n, int32_t l_n)
+{
+    return (l_n * m_n) % 64 >= 32;
+}
+
+/* Appendix A in integer form: word u_w (w = 1..97) is the 24-bit integer
+ * whose binary digits, most significant first, are the bits of steps
+ * 24(w-1)+1 .. 24w.  Fills u[1..97]; u[0] is unused and set to 0. */
 int orc_seed_int(int64_t seed, uint32_t u[98])
 {
-    long i, j, k, l;
-    if (seed_indices(seed, &i, &j, &k, &l)) return -1;
+    int32_t start[4];
+    if (orc_seed_setup(seed, start)) return -1;
+    int32_t mseq[ORC_SEED_BITS], lseq[ORC_SEED_BITS];
+    orc_seed_sequences(start, ORC_SEED_BITS, mseq, lseq);
     u[0] = 0;
-    for (int ii = 1; ii <= 97; ++ii) {
-        uint32_t s = 0, t = 0x80000000u;
-        for (int jj = 1; jj <= 24; ++jj) {
-            if (seed_bit(&i, &j, &k, &l)) s = s + t;
-            t = t / 2;
+    for (int w = 1; w <= 97; ++w) {
+        uint32_t word = 0;
+        for (int p = 0; p < 24; ++p) {
+            int n = 24 * (w - 1) + p; /* 0-based index of step 24(w-1)+p+1 */
+            word = 2 * word + (uint32_t)seed_bit_of(mseq[n], lseq[n]);
         }
-        u[ii] = s >> 8;
+        u[w] = word;
     }
     return 0;
 }
 
-/* ------------------------------------------------------------------------ */
-/* Algorithm 1: RANMAR in real arithmetic (double; every value is a multiple */
-/* of 2^-24 in (-1, 2), so the arithmetic is exact).                         */
-/* ------------------------------------------------------------------------ */
+/* The canonical state after the initialisation (offset 0): the words enter
+ * the sequence from the top down, x_1 = u_97, ..., x_97 = u_1, and c' = c_0. */
+int orc_state_from_seed(int64_t seed, uint32_t W[97], uint32_t *c)
+{
+    uint32_t u[98];
+    if (orc_seed_int(seed, u)) return -1;
+    for (int k = 0; k < 97; ++k) W[k] = u[97 - k] & ORC_MASK;
+    *c = ORC_C0;
+    return 0;
+}
+
+/* Sec. 3.2: c'_n = (c'_0 - n d') mod m in closed form. */
+static uint32_t c_after(uint32_t c0, uint64_t n)
+{
+    uint64_t sub = (n % ORC_MOD) * ORC_D % ORC_MOD;
+    return (uint32_t)(((uint64_t)c0 + ORC_MOD - sub) % ORC_MOD);
+}
+
+/* Sec. 2 as a sequence: the state W holds x_1..x_97 (x_1 oldest).  Draw q
+ * (q = 1..n) makes x_{97+q} = x_q - x_{q+64} mod 2^24 and outputs
+ * y_q = x_{97+q} - c'_q mod 2^24.  The words live in a ring indexed by the
+ * sequence number: x_t sits in slot (t - 1) mod 97, so the new word replaces
+ * the one 97 places back.  The state after the draws (x_{n+1}..x_{n+97},
+ * c'_n) is returned in Wout/cout (either may be NULL). */
+void orc_state_draws(const uint32_t W[97], uint32_t c, uint64_t n, uint32_t *out,
+                     uint32_t *Wout, uint32_t *cout)
+{
+    uint32_t ring[97];
+    memcpy(ring, W, sizeof ring);
+    for (uint64_t q = 1; q <= n; ++q) {
+        uint64_t t = 97 + q;                           /* index of the new word */
+        uint32_t x_old = ring[(t - 97 - 1) % 97];      /* x_{t-97} */
+        uint32_t x_mid = ring[(t - 33 - 1) % 97];      /* x_{t-33} */
+        uint32_t x_new = (x_old - x_mid) & ORC_MASK;
+        ring[(t - 1) % 97] = x_new;
+        if (out) out[q - 1] = (x_new - c_after(c, q)) & ORC_MASK;
+    }
+    if (Wout)
+        for (int k = 0; k < 97; ++k) Wout[k] = ring[(n + (uint64_t)k) % 97];
+    if (cout) *cout = c_after(c, n);
+}
+
+/* The integer generator from a seed: n draws after the initialisation. */
+int orc_int_draws(int64_t seed, uint64_t n, uint32_t *out)
+{
+    uint32_t W[97], c;
+    if (orc_state_from_seed(seed, W, &c)) return -1;
+    orc_state_draws(W, c, n, out, 0, 0);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Real route (double; every value is a multiple of 2^-24 in (-1, 2), so    */
+/* the arithmetic is exact).  It repeats none of the integer route's code.  */
+/* ======================================================================== */
+
+/* The small generators of the real initialisation, kept as a running triple
+ * of the product generator and the congruential value. */
+typedef struct {
+    long p0, p1, p2; /* the last three values of the product generator, oldest first */
+    long lc;         /* the congruential generator's last value */
+} real_init_gen;
+
+/* One step of the pair; returns the bit the step contributes. */
+static int real_init_next(real_init_gen *g)
+{
+    long prod = g->p0 * g->p1 * g->p2 % 179; /* < 179^3, no overflow */
+    g->p0 = g->p1;
+    g->p1 = g->p2;
+    g->p2 = prod;
+    g->lc = (g->lc * 53 + 1) % 169;
+    return (int)((prod * g->lc) % 64 / 32); /* 1 exactly in the upper half */
+}
+
+/* Floating-point initialisation: word w (w = 1..97) is the binary fraction
+ * 0.b_1 b_2 ... b_24 of the next 24 bits, summed as b_p 2^-p.  The start
+ * values come from nested quotients: i and j from the quotient of s - 1 by
+ * 30082 (its quotient and remainder by 177), k and l from the remainder (its
+ * quotient by 169 taken mod 178, and its remainder by 169).  Fills u[1..97]. */
+int orc_seed_real(int64_t seed, double u[98])
+{
+    if (seed < 1 || seed > ORC_SEED_MAX) return -1;
+    long q = (long)(seed - 1);
+    long hi = q / 30082, lo = q - 30082 * hi;
+    real_init_gen g;
+    g.p0 = 2 + (q / (30082L * 177)) % 177; /* quotient of hi by 177, mod 177 */
+    g.p1 = 2 + hi % 177;
+    g.p2 = 1 + (lo / 169) % 178;
+    g.lc = lo % 169;
+    u[0] = 0.0;
+    for (int w = 1; w <= 97; ++w) {
+        double frac = 0.0;
+        for (int p = 1; p <= 24; ++p) {
+            double weight = 1.0;
+            for (int h = 0; h < p; ++h) weight *= 0.5;
+            frac += real_init_next(&g) ? weight : 0.0;
+        }
+        u[w] = frac;
+    }
+    return 0;
+}
+
+/* The real-number generator (the form Algorithm 1 computes), as a sequence:
+ * x_t = x_{t-97} - x_{t-33} mod 1, c_t = c_{t-1} - d mod m (m = 16777213/2^24,
+ * d = 7654321/2^24, c_0 = 362436/2^24), output x_t - c_t mod 1.  The seeded
+ * words enter from the top down (x_1 = u_97). */
 int orc_real_draws(int64_t seed, uint64_t n, double *out)
 {
     double u[98];
     if (orc_seed_real(seed, u)) return -1;
-    double c = 362436.0 / ORC_M24, cd = 7654321.0 / ORC_M24, cm = 16777213.0 / ORC_M24;
-    int i = 97, j = 33;
+    const double two24 = 16777216.0;
+    const double d = 7654321.0 / two24, mreal = 16777213.0 / two24;
+    double c = 362436.0 / two24;
+    double x[97];
+    for (int k = 0; k < 97; ++k) x[k] = u[97 - k];
+    /* x[] is a window that slides by one word per draw: x[0] = x_{t-97}. */
     for (uint64_t q = 0; q < n; ++q) {
-        double y = u[i] - u[j];
-        if (y < 0) y = y + 1.0;
-        u[i] = y;
-        i = i - 1;
-        if (i == 0) i = 97;
-        j = j - 1;
-        if (j == 0) j = 97;
-        c = c - cd;
-        if (c < 0) c = c + cm;
-        y = y - c;
-        if (y < 0) y = y + 1.0;
+        double nw = x[0] - x[64];
+        if (nw < 0.0) nw += 1.0;
+        for (int k = 0; k < 96; ++k) x[k] = x[k + 1];
+        x[96] = nw;
+        c -= d;
+        if (c < 0.0) c += mreal;
+        double y = nw - c;
+        if (y < 0.0) y += 1.0;
         out[q] = y;
     }
     return 0;
-}
-
-/* ------------------------------------------------------------------------ */
-/* Algorithm 2: RANMAR in modular arithmetic with 32-bit unsigned words.    */
-/* ------------------------------------------------------------------------ */
-typedef struct {
-    uint32_t u[98]; /* u[1..97] */
-    uint32_t v;     /* numerator of c, 0 <= v < m */
-    int i, j;
-} alg2_state;
-
-static uint32_t alg2_draw(alg2_state *st)
-{
-    uint32_t x = st->u[st->i] - st->u[st->j];
-    st->u[st->i] = x;
-    st->i = st->i - 1;
-    if (st->i == 0) st->i = 97;
-    st->j = st->j - 1;
-    if (st->j == 0) st->j = 97;
-    st->v = st->v + (ORC_MOD - ORC_D);
-    if (st->v >= ORC_MOD) st->v = st->v - ORC_MOD;
-    return (x - st->v) & ORC_MASK;
-}
-
-int orc_int_draws(int64_t seed, uint64_t n, uint32_t *out)
-{
-    alg2_state st;
-    if (orc_seed_int(seed, st.u)) return -1;
-    st.v = ORC_C0;
-    st.i = 97;
-    st.j = 33;
-    for (uint64_t q = 0; q < n; ++q) out[q] = alg2_draw(&st);
-    return 0;
-}
-
-/* ------------------------------------------------------------------------ */
-/* The automaton state of Sec. 2 / Sec. 3.1: W[0..96] = (u_1, ..., u_97),    */
-/* u_1 oldest, plus c'.  Algorithm 2 keeps the same words in a circular      */
-/* array whose oldest entry is at index i and whose lag-33 entry is at j.    */
-/* ------------------------------------------------------------------------ */
-static int wrap97(int idx)
-{
-    while (idx < 1) idx += 97;
-    while (idx > 97) idx -= 97;
-    return idx;
-}
-
-static void alg2_to_state(const alg2_state *st, uint32_t W[97], uint32_t *c)
-{
-    for (int k = 0; k < 97; ++k) W[k] = st->u[wrap97(st->i - k)] & ORC_MASK;
-    *c = st->v;
-}
-
-static void state_to_alg2(const uint32_t W[97], uint32_t c, alg2_state *st)
-{
-    st->i = 97;
-    st->j = 33;
-    st->u[0] = 0;
-    for (int k = 0; k < 97; ++k) st->u[97 - k] = W[k];
-    st->v = c;
-}
-
-/* State right after Algorithm 3 (offset 0). */
-int orc_state_from_seed(int64_t seed, uint32_t W[97], uint32_t *c)
-{
-    alg2_state st;
-    if (orc_seed_int(seed, st.u)) return -1;
-    st.v = ORC_C0;
-    st.i = 97;
-    st.j = 33;
-    alg2_to_state(&st, W, c);
-    return 0;
-}
-
-/* n draws of Algorithm 2 started from a canonical state; the state after the
- * n draws is returned in Wout/cout (either may be NULL). */
-void orc_state_draws(const uint32_t W[97], uint32_t c, uint64_t n, uint32_t *out,
-                     uint32_t *Wout, uint32_t *cout)
-{
-    alg2_state st;
-    state_to_alg2(W, c, &st);
-    for (uint64_t q = 0; q < n; ++q) {
-        uint32_t y = alg2_draw(&st);
-        if (out) out[q] = y;
-    }
-    uint32_t Wt[97], ct;
-    alg2_to_state(&st, Wt, &ct);
-    if (Wout) memcpy(Wout, Wt, sizeof Wt);
-    if (cout) *cout = ct;
 }
 
 /* ------------------------------------------------------------------------ */

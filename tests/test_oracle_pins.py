@@ -65,6 +65,19 @@ def test_real_equals_integer_draws(orc, seed):
     assert ints.max() <= MASK
 
 
+def test_real_equals_integer_through_c_zero(orc):
+    """c_n = 0 is a legal value reached once every m draws, at n = c_0 / d
+    mod m (15,418,204 from the initial c); both routes must agree through it
+    (the real route steps c in real numbers with a wrap below zero, the
+    integer route takes c_n from its closed form)."""
+    n0 = orc.C0 * pow(orc.D, -1, orc.MOD) % orc.MOD
+    assert (orc.C0 - n0 * orc.D) % orc.MOD == 0
+    n = n0 + 1000
+    real = orc.real_draws(12345, n)[n0 - 1000:]
+    ints = orc.int_draws(12345, n)[n0 - 1000:]
+    assert np.array_equal(real * float(1 << 24), ints.astype(np.float64))
+
+
 @pytest.mark.parametrize("seed", SEEDS)
 def test_real_equals_integer_seeding(orc, seed):
     """Appendix A: Algorithm 3 reproduces the real-arithmetic initialisation."""
@@ -80,6 +93,56 @@ def test_seed_range(orc):
         with pytest.raises(ValueError):
             orc.state_from_seed(bad)
     orc.state_from_seed(900000000)
+
+
+# --- Appendix A: the initialisation's set-up and small generators -------------
+import seed_pins  # noqa: E402
+
+
+def test_seed_setup_low_part_is_a_bijection(orc):
+    """30082 = 178 * 169: inside a block of 30082 seeds, (k, l) runs once over
+    [1, 178] x [0, 168] while (i, j) stays fixed (Algorithm 3's set-up)."""
+    assert seed_pins.check_setup_low_part(orc.seed_setup) == []
+
+
+def test_seed_setup_is_injective_and_non_degenerate(orc):
+    """The high part of s - 1 is below 177^2, so (i, j) differs for every
+    block; every start value is a non-zero residue mod 179 and the three
+    product-generator values are never all 1."""
+    assert seed_pins.check_setup_high_part(orc.seed_setup) == []
+
+
+def test_product_generator_exponent_form(orc):
+    """m_n = g^(e_n) mod 179 with e_n = e_(n-1) + e_(n-2) + e_(n-3) mod 178:
+    the lag-3 product generator computed through discrete logarithms."""
+    seeds = [1, 2, 170, 12345, 30083, 5324515, 777777777, 900000000]
+    assert seed_pins.check_product_generator(orc.seed_setup, orc.seed_sequences, seeds) == []
+
+
+def test_congruential_generator_closed_form_and_period(orc):
+    """l_n = 53^n l_0 + (53^n - 1)/52 mod 169, and full period 169 from every
+    start (Hull-Dobell)."""
+    assert seed_pins.check_congruential_generator(orc.seed_sequences) == []
+
+
+def test_first_draws_read_the_seeded_words_top_down(orc):
+    """The generator starts its pointers at 97 and 33: draw q <= 33 is
+    u_(98-q) - u_(34-q) - c_q mod 2^24, straight from the seeded array."""
+    seeds = [1, 12345, 4711, 900000, 900000000]
+    assert seed_pins.check_first_draws(orc.seed_int, orc.int_draws, seeds) == []
+
+
+def test_real_and_integer_seeding_agree_across_the_seed_range(orc):
+    """The two independent routes of the initialisation (real: words as sums
+    of 2^-p, its own index arithmetic; integer: 24-bit words from the bit
+    sequence) agree exactly on seeds spread over every part of the set-up."""
+    g = synth.rng(106)
+    seeds = [1, 2, 169, 170, 30082, 30083, 5324514, 5324515, 899993277, 900000000]
+    seeds += [int(v) for v in g.integers(1, 900_000_001, size=300)]
+    for s in seeds:
+        ur = orc.seed_real(s)[1:]
+        ui = orc.seed_int(s)[1:]
+        assert np.array_equal(ur * float(1 << 24), ui.astype(np.float64)), s
 
 
 def _literal_quotient_words(seed, words=97):
