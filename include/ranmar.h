@@ -70,7 +70,8 @@ typedef enum ranmar_status {
     RANMAR_EHIP = -4,      /* HIP runtime error (launch or queued work) */
     RANMAR_ENOENT = -5,    /* unknown ticket / handle */
     RANMAR_ETIMEDOUT = -6, /* wait timed out */
-    RANMAR_ENODEV = -7     /* no gfx950 device current */
+    RANMAR_ENODEV = -7,    /* no gfx950 device current */
+    RANMAR_ENOINIT = -8    /* per-device set-up (ranmar_init) not done */
 } ranmar_status;
 
 /* Output format of generated draws. */
@@ -91,8 +92,11 @@ const char *ranmar_strerror(int status);
 int ranmar_version(void);
 
 /* Checks that the current HIP device is a gfx950 and sets up per-device
- * tables.  Called implicitly by every device entry point; may be called
- * explicitly to surface RANMAR_ENODEV / RANMAR_EHIP early. */
+ * state: the 1.6 MB table of 8-bit jump digits and the address of the fixed
+ * scratch array of ranmar_jump_family_noalloc.  The check is made implicitly
+ * by every device entry point; the set-up (which allocates the table) only
+ * here, once per device.  Call it with each device current before using
+ * ranmar_jump_family_noalloc there. */
 int ranmar_init(void);
 
 /* ------------------------------------------------------------------------ */
@@ -158,6 +162,23 @@ int ranmar_seed_jump(const int32_t *d_seeds, const ranmar_u128 *d_offsets, uint6
  * stream-ordered device memory for the duration of the call. */
 int ranmar_jump_family(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n,
                        ranmar_state *d_out, void *stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ranmar_jump_family with the same result, bit for bit, that calls no
+ * allocating routine.  The product form keeps its factor sequences in a
+ * fixed array of RANMAR_NOALLOC_FAMILY_BYTES that each device the library
+ * runs on holds until the process ends; ranmar_init() must have been called
+ * with the device current (else RANMAR_ENOINIT, nothing launched).
+ * Limits: n <= RANMAR_NOALLOC_FAMILY_MAX_N and (n - 1) * delta < 2^128, else
+ * RANMAR_EINVAL (nothing launched).  All calls on one device share that array
+ * and leave their contents in it: calls that overlap in time on one device
+ * (on different streams, or from different host threads) race and must be
+ * ordered by the caller. */
+#define RANMAR_NOALLOC_FAMILY_MAX_N (1ull << 24)
+#define RANMAR_NOALLOC_FAMILY_BYTES (4096ull * 196 * 4)
+int ranmar_jump_family_noalloc(const ranmar_state *d_base, ranmar_u128 delta, uint64_t n, ranmar_state *d_out,
+                               void *stream);
 
 /* Per-rank streams of one seed (Sec. 1, block splitting, as a parallel code
  * uses it: rank p draws the block that starts at s_{p*J}): d_out[k] = state

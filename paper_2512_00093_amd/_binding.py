@@ -32,6 +32,8 @@ RANMAR_EHIP = -4
 RANMAR_ENOENT = -5
 RANMAR_ETIMEDOUT = -6
 RANMAR_ENODEV = -7
+RANMAR_ENOINIT = -8
+RANMAR_NOALLOC_FAMILY_MAX_N = 1 << 24
 RANMAR_U24 = 0
 RANMAR_F32 = 1
 RANMAR_U24_F32 = 2
@@ -99,6 +101,7 @@ _SIGS = {
     "ranmar_jump": (_int, [_vp, _vp, _u64, _vp]),
     "ranmar_seed_jump": (_int, [_vp, _vp, _u64, _vp, _vp]),
     "ranmar_jump_family": (_int, [_vp, ranmar_u128, _u64, _vp, _vp]),
+    "ranmar_jump_family_noalloc": (_int, [_vp, ranmar_u128, _u64, _vp, _vp]),
     "ranmar_rank_streams": (_int, [_i32, ranmar_u128, _u64, _u64, _int, _vp, _vp]),
     "ranmar_generate": (_int, [_vp, _vp, _u64, _u64, _int, _vp, _u64, _vp]),
     "ranmar_batch_create": (_int, [_u64, _u64, _u64, ctypes.POINTER(_vp)]),
@@ -240,6 +243,14 @@ def ranmar_jump_family(base, delta: int, n: int, out=None, stream=None):
         out = new_states(n, base.device)
     _check(lib().ranmar_jump_family(_ptr(base), _u128(delta), n, _ptr(out), _stream(stream)),
            "ranmar_jump_family")
+    return out
+
+
+def ranmar_jump_family_noalloc(base, delta: int, n: int, out, stream=None):
+    """ranmar_jump_family without any device allocation: `out` must be given
+    (n records) and ranmar_init() must have run on this device."""
+    _check(lib().ranmar_jump_family_noalloc(_ptr(base), _u128(delta), n, _ptr(out), _stream(stream)),
+           "ranmar_jump_family_noalloc")
     return out
 
 

@@ -89,13 +89,17 @@ const char* ranmar_strerror(int status) {
     case RANMAR_ENOENT: return "unknown ticket or handle";
     case RANMAR_ETIMEDOUT: return "timed out";
     case RANMAR_ENODEV: return "no gfx950 device";
+    case RANMAR_ENOINIT: return "ranmar_init has not been called on this device";
     default: return "unknown status";
   }
 }
 
 int ranmar_version(void) { return 10000; }
 
-int ranmar_init(void) { return ensure_init(); }
+int ranmar_init(void) {
+  const int rc = ensure_init();
+  return rc ? rc : noalloc_setup();
+}
 
 int ranmar_seed(int64_t seed, ranmar_state* out) {
   if (!out) return RANMAR_EINVAL;
@@ -164,6 +168,32 @@ int ranmar_jump_family(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n
   if (rc) return rc;
   return hip_status(launch_family_variant(family_variant_for(n), (const uint32_t*)d_base, delta, n, (uint32_t*)d_out,
                                           (hipStream_t)stream));
+}
+
+int ranmar_jump_family_noalloc(const ranmar_state* d_base, ranmar_u128 delta, uint64_t n, ranmar_state* d_out,
+                               void* stream) {
+  if (n == 0) return RANMAR_OK;
+  if (!d_base || !d_out || !aligned(d_base, 4) || !aligned(d_out, 4)) return RANMAR_EINVAL;
+  if (n > RANMAR_NOALLOC_FAMILY_MAX_N) return RANMAR_EINVAL;
+  // (n - 1) delta must fit in 128 bits: beyond it the family needs the
+  // polynomial path, which allocates.
+  const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
+  if (n > 1 && D > ~(unsigned __int128)0 / (n - 1)) return RANMAR_EINVAL;
+  if (d_base != d_out && overlap(d_base, sizeof(ranmar_state), d_out, sizeof(ranmar_state) * n))
+    return RANMAR_EINVAL;
+  int rc = ensure_init();
+  if (rc) return rc;
+  uint32_t* H = noalloc_scratch();
+  if (!H) return RANMAR_ENOINIT;
+  const hipStream_t st = (hipStream_t)stream;
+  const int v = family_variant_for(n);
+  hipError_t e = hipErrorInvalidValue;
+  if (v == FAMILY_GEMM || v == FAMILY_GEMM32)
+    e = launch_family_gemm_fixed((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, st, v == FAMILY_GEMM32 ? 32 : 16,
+                                 H);
+  // Too small for the product form: radix rounds of table factors (no scratch).
+  if (e == hipErrorInvalidValue) e = launch_family_window((const uint32_t*)d_base, delta, n, (uint32_t*)d_out, st);
+  return hip_status(e);
 }
 
 int ranmar_rank_streams(int32_t seed, ranmar_u128 J, uint64_t first_rank, uint64_t n_ranks, int discard_first,

@@ -36,7 +36,9 @@
 // combination wraps mod 2^32, then is masked.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "coop_dev.hpp"
@@ -490,8 +492,11 @@ __global__ __launch_bounds__(256, 2) void k_family_gemm32(uint32_t* out, const u
 // for the product form (n < 2 A), or E0 + (n - 1) delta needs more than 128
 // bits.  Starts from `base` (seed == 0, E0 == 0) or from the state of `seed`
 // at offset E0.
+// H_fixed, if not null, holds the factor sequences instead of stream-ordered
+// memory (room for h_cap factors; hipErrorInvalidValue if B - 1 exceeds it).
 static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n,
-                              uint32_t* out, hipStream_t st, uint32_t tr) {
+                              uint32_t* out, hipStream_t st, uint32_t tr, uint32_t* H_fixed = nullptr,
+                              uint64_t h_cap = 0) {
   const unsigned __int128 D = ((unsigned __int128)delta.hi << 64) | delta.lo;
   const unsigned __int128 E0 = ((unsigned __int128)e0.hi << 64) | e0.lo;
   const unsigned __int128 kMax = ~(unsigned __int128)0;
@@ -518,9 +523,11 @@ static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0
   if ((njobs + 7) / 8 > 0x7FFFFFFFull || gx > 0x7FFFFFFFull || B - 1 > 65535) return hipErrorInvalidValue;
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
+  if (H_fixed && B - 1 > h_cap) return hipErrorInvalidValue;
   const unsigned __int128 AD = D * A;  // < n delta, and A <= n - 1
-  uint32_t* H = nullptr;
-  hipError_t e = hipMallocAsync((void**)&H, sizeof(uint32_t) * kHWords * (B - 1), st);
+  uint32_t* H = H_fixed;
+  hipError_t e = hipSuccess;
+  if (!H_fixed) e = hipMallocAsync((void**)&H, sizeof(uint32_t) * kHWords * (B - 1), st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_family_l1, dim3((unsigned)((njobs + 7) / 8)), dim3(256), 0, st, base, out, H, T, A, njobs,
                      (uint64_t)D, (uint64_t)(D >> 64), (uint64_t)AD, (uint64_t)(AD >> 64),
@@ -535,13 +542,59 @@ static hipError_t family_gemm(const uint32_t* base, int32_t seed, ranmar_u128 e0
                          (uint32_t)(AD % kMod), tpw);
     e = hipGetLastError();
   }
-  const hipError_t f = hipFreeAsync(H, st);
+  const hipError_t f = H_fixed ? hipSuccess : hipFreeAsync(H, st);
   return e != hipSuccess ? e : f;
 }
 
 hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st,
                               uint32_t tile_rows) {
   return family_gemm(base, 0, ranmar_u128{0, 0}, delta, n, out, st, tile_rows == 32 ? 32u : 16u);
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation form, for callers that cannot allocate device memory.  The
+// factor sequences go to a fixed array instead of stream-ordered memory:
+// kHWords words per factor, room for kNoAllocFactors factors (3.2 MB), which
+// covers every family of up to 2^24 starts (A = B = 4096 at most).  The array
+// is held by each device the library runs on until the process ends; host
+// code uses only the address taken from it at set-up, never its name (which
+// on the host is a stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr uint64_t kNoAllocFactors = 4096;
+static __device__ __align__(256) uint32_t scratch[kHWords * kNoAllocFactors];
+static_assert(sizeof(uint32_t) * kHWords * kNoAllocFactors == RANMAR_NOALLOC_FAMILY_BYTES,
+              "the public size of the no-allocation scratch array");
+
+static std::mutex g_scratch_mu;
+static std::atomic<uint32_t*> g_scratch_ptr[64];  // per device, set once by noalloc_setup
+
+int noalloc_setup() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RANMAR_ENODEV;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev].load(std::memory_order_acquire)) return RANMAR_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return RANMAR_EHIP;
+  }
+  // The family's first launch reads the 8-bit window table: build it now, so
+  // that the no-allocation calls never have to.
+  if (!window_table()) return RANMAR_ENOMEM;
+  g_scratch_ptr[dev].store((uint32_t*)ptr, std::memory_order_release);
+  return RANMAR_OK;
+}
+
+uint32_t* noalloc_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  return g_scratch_ptr[dev].load(std::memory_order_acquire);
+}
+
+hipError_t launch_family_gemm_fixed(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out,
+                                    hipStream_t st, uint32_t tile_rows, uint32_t* H) {
+  return family_gemm(base, 0, ranmar_u128{0, 0}, delta, n, out, st, tile_rows == 32 ? 32u : 16u, H,
+                     kNoAllocFactors);
 }
 
 hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,

@@ -40,6 +40,14 @@ hipError_t launch_family_gemm(const uint32_t* base, ranmar_u128 delta, uint64_t 
 // seeding happens inside the first launch.
 hipError_t launch_family_gemm_seeded(int32_t seed, ranmar_u128 e0, ranmar_u128 delta, uint64_t n, uint32_t* out,
                                      hipStream_t st, uint32_t tile_rows);
+// No-allocation family: the product form's factor sequences in a fixed
+// per-device array.  noalloc_setup (from ranmar_init, device current) takes the
+// array's device address and builds the 8-bit window table; noalloc_scratch
+// returns that address for the current device, or nullptr before set-up.
+int noalloc_setup();
+uint32_t* noalloc_scratch();
+hipError_t launch_family_gemm_fixed(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out,
+                                    hipStream_t st, uint32_t tile_rows, uint32_t* H);
 // General lagged-Fibonacci generators (any r, s, e, m, d).
 int lfg_params_ok(const ranmar_lfg_params* p);
 uint32_t lfg_jump_threads(uint32_t r);

@@ -43,7 +43,7 @@ def test_binding_covers_every_symbol():
 def test_strerror_and_version(L):
     from paper_2512_00093_amd import _binding as B
     assert B.ranmar_version() >= 10000
-    for st in range(0, -8, -1):
+    for st in range(0, -9, -1):
         assert B.ranmar_strerror(st)
     assert B.ranmar_strerror(-99) == "unknown status"
 
