@@ -2,15 +2,19 @@
 """Benchmark of the RANMAR hot path on one MI355X.
 
 Workloads (all synthetic, seeded; see synth/):
-  family65k  (default) one step = seed 4711 on the GPU, 65,536 stream starts at
-             offsets k*2^40 by exact GPU jump-ahead, then 4,096 draws per stream
+  bulk1m     (default line) generation only: 2^20 streams at offsets k*2^100
+             already on the device, 1,024 float32 draws each (2^30 draws,
+             4 GiB per step); measured against HBM peak and against a plain
+             4 GiB store launch timed in the same process.
+  family65k  one step = seed 4711 on the GPU, 65,536 stream starts at offsets
+             k*2^40 by exact GPU jump-ahead, then 4,096 draws per stream
              written as uint32 and as float32 (2^28 draws per step).
-  bulk1m     generation only: 2^20 streams at offsets k*2^100 already on the
-             device, 1,024 float32 draws each (2^30 draws, 4 GiB per step).
   jumps1m    10^6 seed+jump requests, J uniform on [0, 2^120), one launch.
+  serve      200,000 served requests (Poisson arrivals, log-uniform counts),
+             continuous batching against one launch per request.
 
 Prints ONE JSON line for the chosen workload; the default run also measures
-bulk1m and jumps1m briefly and reports them under "also".
+the other workloads briefly and reports them, compactly, under "also".
 """
 from __future__ import annotations
 
@@ -36,7 +40,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 24-bit integer multiply-adds per se
 MACS_SQUARE = 97 * 98 // 2     # symmetric schoolbook squaring: 4753 multiply-adds
 MACS_APPLY = 97 * 97           # one application of a polynomial to a window: 9409 multiply-adds
 WIN_BITS = 20                  # bulk windowed jump: one table application per 20-bit digit of J
-SEED_OPS = 2328 * 12           # Algorithm 3: 97 x 24 steps of the small generators, ~12 lane-ops each
+SERVE_TICK = (160, 870_000)    # a serving launch at capacity: requests x draws each (the mean count)
 
 
 def _progress(msg):
@@ -78,12 +82,12 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="family65k",
+    ap.add_argument("--workload", default="bulk1m",
                     choices=["family65k", "bulk1m", "jumps1m", "serve", "lfg_gen", "lfg_jumps", "lfg_family"])
     ap.add_argument("--serve-requests", type=int, default=synth.SERVE["requests"])
-    ap.add_argument("--serve-qps", type=float, default=5e5)
-    ap.add_argument("--serve-light-qps", type=float, default=2e4)
-    ap.add_argument("--serve-baseline-requests", type=int, default=2000)
+    ap.add_argument("--serve-qps", type=float, default=2e4,
+                    help="--workload serve: offered load (requests/s) of the light-load comparison")
+    ap.add_argument("--serve-lanes", type=int, default=4, help="HIP streams of the server, both arms")
     ap.add_argument("--jump", default="family", choices=["family", "lanes"],
                     help="family65k: stream starts by prefix doubling or one jump per stream")
     ap.add_argument("--no-extras", action="store_true")
@@ -174,7 +178,53 @@ def cpu_baseline(kind: str, seconds: float):
     wall = max(r[1] for r in res)
     done = sum(r[2] for r in res)
     return {"value": units / wall, "unit": unit, "cores": workers, "kind": "oracle",
-            "sample": f"{done} {sample}, {workers} processes, {wall:.1f} s"}
+            "sample": f"{done} {sample}, {workers} processes, {wall:.1f} s", **host_info()}
+
+
+def host_info():
+    """The host's logical CPU count and model (the oracle's processes are
+    capped at 16, the CPU share of one GPU on the benchmark machines)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_nproc": os.cpu_count(), "host_cpu": model}
+
+
+def cpu_single_thread():
+    """The oracle on one core, on the paper's own workload shapes: Table 1
+    (one stream, real arithmetic as in Algorithm 1 against the integer form of
+    Algorithm 2; a 10^8-draw sample of the 10^9-draw shape, as ten calls of
+    10^7 from seeds 12345..12354) and Table 2 (t^J mod phi for the all-ones J
+    of 64 and 120 bits, by left-to-right binary powering with schoolbook
+    products; mean of 10 calls).  The paper's CPUs are quoted beside them."""
+    from oracle import oracle as O
+    n, calls = 10 ** 7, 10
+    t = {}
+    for name, fn in (("alg1_real", O.real_draws), ("alg2_integer", O.int_draws)):
+        t0 = time.perf_counter()
+        for k in range(calls):
+            fn(12345 + k, n)
+        t[name] = n * calls / (time.perf_counter() - t0)
+    jumps = {}
+    for J in synth.PAPER_TABLE2["jumps"]:
+        O.xpow(J)
+        t0 = time.perf_counter()
+        for _ in range(10):
+            O.xpow(J)
+        jumps[f"J=2^{J.bit_length()}-1"] = (time.perf_counter() - t0) / 10 * 1e6
+    return {"threads": 1, "table1_draws_per_s": {k: v for k, v in t.items()},
+            "table1_integer_over_real": t["alg2_integer"] / t["alg1_real"],
+            "table1_sample": f"{n * calls:.0e} draws (ten streams of 1e7)",
+            "table2_us": jumps,
+            "paper_table1_s_1e9": {"real": {"apple": 3.30, "arm": 16.60, "ryzen": 8.45, "intel": 3.31},
+                                   "integer": {"apple": 1.27, "arm": 6.14, "ryzen": 2.07, "intel": 1.01}},
+            "paper_table2_us_ntl": {"J=2^64-1": [946, 10395], "J=2^120-1": [1946, 21411]}}
 
 
 # ---------------------------------------------------------------------------
@@ -303,9 +353,9 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
     gen_bytes = 4 * draws + 2 * 392 * n          # float32 output + state read + state write-back
     res = {
         "metric": "draws/s", "value": draws / dt, "unit": "draws/s", "ms_per_step": dt * 1e3,
-        "dtype": "u24", "config": {"workload": f"family65k: 65,536 streams from seed 4711 at offsets k*2^40 "
-                                   f"({'per-rank streams: seeding and 65,536 starts as int8 MFMA products of shared factors, two launches' if jump_mode == 'family' else 'one jump per stream'}"
-                                   "), 4,096 draws each written as uint32 and as float32",
+        "dtype": "u24", "config": {"workload": "family65k: 65,536 streams from seed 4711 at offsets k*2^40 "
+                                   f"({'int8 MFMA family' if jump_mode == 'family' else 'one jump per stream'}), "
+                                   "4,096 draws each as uint32 and as float32",
                                    "streams": n, "draws_per_stream": cnt, "jump": jump_mode},
         "breakdown_ms": {k: tm.mean_ms(k) for k in ("starts", "gen_u24", "gen_f32")},
         "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": gen_bytes / (gen_ms * 1e-3) / 1e9,
@@ -375,21 +425,26 @@ def run_jumps1m(R, torch, steps, warmup):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ms = tm.mean_ms("jump")
-    # Algorithmic lane-ops of the launch: one 97 x 97 application (9409
-    # multiply-adds) per 20-bit digit of J up to the highest non-zero one, plus
-    # Algorithm 3's seeding (2328 generator steps of ~12 ops) per request.
-    bl = np.where(hi > 0, 64 + np.floor(np.log2(np.maximum(hi, 1).astype(np.float64))) + 1,
-                  np.where(lo > 0, np.floor(np.log2(np.maximum(lo, 1).astype(np.float64))) + 1, 0))
-    macs = float(np.ceil(bl / WIN_BITS).sum()) * MACS_APPLY + float(n) * SEED_OPS
+    # Algorithmic work of the launch: one 97 x 97 application (9409
+    # multiply-adds) per non-zero 20-bit digit of J (the windowed method of
+    # the tables t^(d 2^(20w)) mod phi).  Seeding (Appendix A, done in the
+    # same launch) is not counted; the committed instruction counters of this
+    # launch give its share.
+    Js = synth.u128_to_int(lo, hi)
+    digits = sum(sum(1 for w in range(7) if (J >> (WIN_BITS * w)) & ((1 << WIN_BITS) - 1)) for J in Js)
+    macs = float(digits) * MACS_APPLY
+    sqmul = sum(max(J.bit_length() - 1, 0) * MACS_SQUARE + max(bin(J).count("1") - 1, 0) * 2 for J in Js[:10000])
     ach = macs / (ms * 1e-3) / 1e12
     return {
         "metric": "jumps/s", "value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3, "dtype": "u24",
         "config": {"workload": "jumps1m: 10^6 seed+jump requests, seeds uniform on [1, 9e8], J uniform on "
                                "[0, 2^120), one launch", "requests": n},
         "roofline": {"bound": "alu", "kernel": "k_jump_grp<8,20,seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
-                     "unit": "T lane-ops/s (24-bit multiply-adds of the applications + seeding ops)",
-                     "frac": ach / VALU_PEAK_TOPS, "traffic": None,
-                     "ops_per_launch": float(macs), "launch_ms": ms},
+                     "unit": "T lane-ops/s", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                     "basis": "24-bit multiply-adds of the table applications, %.0f per jump (9409 per non-zero "
+                              "20-bit digit); seeding not counted; square-and-multiply would need %.3g per jump"
+                              % (macs / n, sqmul / min(n, 10000) + MACS_APPLY),
+                     "ops_per_launch": macs, "launch_ms": ms},
     }
 
 
@@ -656,39 +711,81 @@ def run_jumps1m_batched(R, torch, steps, warmup):
                                    "graph launch, host descriptor preparation reported separately"}}
 
 
-def run_serve(R, torch, n_req, qps, n_base):
-    """Open-loop serving: Poisson arrivals, log-uniform counts, 64 GiB budget."""
+def serve_arm(R, torch, tr, n, qps, lanes, unbatched, arena):
+    """One open-loop serving run: the first n requests of the trace `tr`
+    (arrival times rescaled to the offered rate `qps`), float32 output, every
+    request released as soon as it completes.  Returns a compact summary."""
     import numpy as np
-    tr = synth.serve_requests(n_req, qps=qps, offset=5)
-    dev = torch.device("cuda:0")
-    arena = torch.empty(synth.SERVE["budget_bytes"] // 4, dtype=torch.int32, device=dev)
-    out = {}
-    for mode, n in (("batched", n_req), ("one_launch_per_request", min(n_base, n_req))):
-        cfg = R.ranmar_serve_cfg()
-        cfg.queue_when_full = 1
-        cfg.lanes = 4 if mode == "batched" else 2
-        cfg.unbatched = 1 if mode != "batched" else 0
-        srv = R.ranmar_serve_create(arena, cfg)
-        try:
-            t0 = time.perf_counter()
-            lat = R.ranmar_serve_replay(srv, tr["arrival"][:n], tr["seeds"][:n], tr["off_lo"][:n], tr["off_hi"][:n],
-                                        tr["counts"][:n], R.RANMAR_F32)
-            wall = time.perf_counter() - t0
-            st = R.ranmar_serve_stats_get(srv)
-        finally:
-            R.ranmar_serve_destroy(srv)
-        draws = float(tr["counts"][:n].sum())
-        out[mode] = {"requests": n, "qps_offered": qps, "p50_ms": float(np.percentile(lat, 50)) / 1e6,
-                     "p99_ms": float(np.percentile(lat, 99)) / 1e6, "max_ms": float(lat.max()) / 1e6,
-                     "draws": draws, "draws_per_s": draws / wall, "wall_s": wall, "ticks": int(st.ticks),
-                     "arena_peak_GiB": st.bytes_peak / 2 ** 30}
+    cfg = R.ranmar_serve_cfg()
+    cfg.queue_when_full = 1
+    cfg.lanes = lanes
+    cfg.unbatched = 1 if unbatched else 0
+    arrival = tr["unit_arrival"][:n] / qps
+    srv = R.ranmar_serve_create(arena, cfg)
+    try:
+        t0 = time.perf_counter()
+        lat = R.ranmar_serve_replay(srv, arrival, tr["seeds"][:n], tr["off_lo"][:n], tr["off_hi"][:n],
+                                    tr["counts"][:n], R.RANMAR_F32)
+        wall = time.perf_counter() - t0
+        st = R.ranmar_serve_stats_get(srv)
+    finally:
+        R.ranmar_serve_destroy(srv)
+    draws = float(tr["counts"][:n].sum())
+    return {"req": n, "qps_offered": qps, "req_per_s": n / wall, "draws_per_s": draws / wall,
+            "p50_ms": float(np.percentile(lat, 50)) / 1e6, "p99_ms": float(np.percentile(lat, 99)) / 1e6,
+            "max_ms": float(lat.max()) / 1e6, "ticks": int(st.ticks), "wall_s": wall,
+            "arena_peak_GiB": st.bytes_peak / 2 ** 30}
+
+
+def run_serve(R, torch, n_req, light_qps, lanes):
+    """Serving (200,000 requests: Poisson arrivals, seed uniform on [1, 9e8],
+    offset uniform on [0, 2^120), count log-uniform on [1e2, 1e7], float32
+    output, 64 GiB budget), continuous batching against one launch per
+    request, both arms on the same requests with the same number of streams:
+      capacity   every request offered at once: the sustained rate;
+      light      both arms at the same stated rate (below either capacity);
+      NNpct      each arm at 50% and 80% of its own capacity (the one launch
+                 per request arm: 80% only, its 50% is about the light rate)."""
+    tr = synth.serve_requests(n_req, qps=1.0, offset=5)
+    tr["unit_arrival"] = tr["arrival"]          # arrival times at 1 request/s, rescaled per run
+    arena = torch.empty(synth.SERVE["budget_bytes"] // 4, dtype=torch.int32, device=torch.device("cuda:0"))
+    out = {"config": {"workload": f"serve: {n_req} requests, seed U[1,9e8], offset U[0,2^120), count "
+                                  "log-uniform [1e2,1e7] (total %.3g draws), float32, 64 GiB budget, %d streams; "
+                                  "arms on the same requests" % (float(tr["counts"].sum()), lanes)}}
+    for arm, ub in (("batched", False), ("one_launch_per_request", True)):
+        res = {}
+        cap = serve_arm(R, torch, tr, n_req, 1e12, lanes, ub, arena)
+        res["capacity"] = cap
+        _progress(f"serve {arm} capacity: {cap['req_per_s']:.4g} req/s")
+        res[f"light_{light_qps:g}qps"] = serve_arm(R, torch, tr, n_req, light_qps, lanes, ub, arena)
+        for frac in ((0.5, 0.8) if not ub else (0.8,)):
+            res[f"{int(frac * 100)}pct"] = serve_arm(R, torch, tr, n_req, frac * cap["req_per_s"], lanes, ub, arena)
+        out[arm] = res
+        _progress(f"serve {arm} done")
     del arena
     torch.cuda.synchronize()
-    return {"value": out["batched"]["draws_per_s"], "unit": "draws/s", "serve": out,
-            "config": {"workload": f"serve: {n_req} requests, Poisson arrivals at {qps:g}/s, seed uniform on "
-                                   "[1, 9e8], offset uniform on [0, 2^120), count log-uniform on [1e2, 1e7], "
-                                   "float32 output, 64 GiB budget; baseline = first "
-                                   f"{min(n_base, n_req)} requests served one launch per request"}}
+    return out
+
+
+def run_store_ceiling(torch, steps, warmup):
+    """A plain 4 GiB store (torch's fill of a float32 tensor, 16-byte stores
+    in address order), timed with HIP events like the generation launch: the
+    write rate this device reaches with no arithmetic and no reads."""
+    buf = torch.empty(1 << 30, dtype=torch.float32, device=torch.device("cuda:0"))
+    tm = Timer(torch)
+    for _ in range(warmup):
+        buf.fill_(0.5)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        a, b = tm.span("fill")
+        a.record()
+        buf.fill_(0.5)
+        b.record()
+    torch.cuda.synchronize()
+    ms = tm.mean_ms("fill")
+    del buf
+    gbs = 4.0 * (1 << 30) / (ms * 1e-3) / 1e9
+    return {"kernel": "torch fill, 4 GiB float32", "launch_ms": ms, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
 def autotune(R, workload, extras):
@@ -696,18 +793,47 @@ def autotune(R, workload, extras):
     workloads use; later calls with those shapes take the fastest variant.
     Returns {shape: variant name}."""
     shapes = []
-    if workload == "family65k":
+    if workload == "family65k" or extras:
         shapes += [(R.RANMAR_K_FAMILY, synth.FAMILY_65K["streams"], 40),
                    (R.RANMAR_K_GENERATE, synth.FAMILY_65K["streams"], synth.FAMILY_65K["draws"])]
     if workload == "bulk1m" or extras:
         shapes.append((R.RANMAR_K_GENERATE, synth.BULK_1M["streams"], synth.BULK_1M["draws"]))
     if workload == "jumps1m" or extras:
         shapes.append((R.RANMAR_K_JUMP, synth.BATCH_JUMPS["requests"], 120))
-    names = {R.RANMAR_K_GENERATE: "generate", R.RANMAR_K_JUMP: "jump", R.RANMAR_K_FAMILY: "family"}
+    if extras or workload == "serve":
+        # The batch executor: the jump-only batch of the 10^6-request workload,
+        # and a serving tick at capacity (about 160 requests of the mean count,
+        # 8.7e5 draws): chunk length first, then the mapping for it.
+        shapes += [(R.RANMAR_K_BATCH, synth.BATCH_JUMPS["requests"], 0),
+                   (R.RANMAR_K_CHUNK, SERVE_TICK[0], SERVE_TICK[1]),
+                   (R.RANMAR_K_BATCH, SERVE_TICK[0], SERVE_TICK[1])]
+    names = {R.RANMAR_K_GENERATE: "generate", R.RANMAR_K_JUMP: "jump", R.RANMAR_K_FAMILY: "family",
+             R.RANMAR_K_BATCH: "batch", R.RANMAR_K_CHUNK: "chunk"}
     out = {}
     for k, n, c in shapes:
         best, _ = R.ranmar_tune_run(k, n, c)
         out[f"{names[k]} {n}x{c}"] = R.ranmar_tune_variant_name(k, best)
+    return out
+
+
+def _c(x):
+    """Rounds floats to 4 significant digits, recursively (keeps the one
+    JSON line short enough to be read whole)."""
+    if isinstance(x, float):
+        return float(f"{x:.4g}")
+    if isinstance(x, dict):
+        return {k: _c(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_c(v) for v in x]
+    return x
+
+
+def _brief(res, keys=("value", "unit", "ms_per_step")):
+    out = {k: res[k] for k in keys if k in res}
+    rf = res.get("roofline")
+    if rf:
+        out["roofline"] = {k: rf[k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac", "traffic",
+                                               "launch_ms", "basis") if k in rf}
     return out
 
 
@@ -729,28 +855,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tuned = {} if a.no_tune else autotune(R, a.workload, not a.no_extras and a.workload == "family65k")
+    extras = not a.no_extras and a.workload == "bulk1m"
+    tuned = {} if a.no_tune else autotune(R, a.workload, extras)
     if tuned:
         _progress("autotuned: " + json.dumps(tuned))
-    if a.workload == "family65k":
-        res = run_family65k(R, torch, a.steps, a.warmup, a.jump)
-        _progress("family65k done")
-    elif a.workload == "bulk1m":
-        res = run_bulk1m(R, torch, a.steps, a.warmup)
-    elif a.workload == "serve":
-        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_baseline_requests)
-        print(json.dumps({"metric": "served draws/s (p50/p99 latency)", "value": r["value"], "unit": r["unit"],
-                          "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "config": r["config"],
-                          "serve": r["serve"]}), flush=True)
+    if a.workload == "serve":
+        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_lanes)
+        print(json.dumps(_c({"metric": "served draws/s (p50/p99 latency)",
+                             "value": r["batched"]["capacity"]["draws_per_s"], "unit": "draws/s", "n_gpus": 1,
+                             "higher_is_better": True, "data": "synthetic", **r})), flush=True)
         return
-    elif a.workload == "lfg_gen":
-        res = run_lfg_gen(R, torch, a.steps, a.warmup)
-    elif a.workload == "lfg_jumps":
-        res = run_lfg_jumps(R, torch, a.steps, a.warmup)
-    elif a.workload == "lfg_family":
-        res = run_lfg_family(R, torch, a.steps, a.warmup)
-    else:
-        res = run_jumps1m(R, torch, a.steps, a.warmup)
+    runners = {"family65k": lambda: run_family65k(R, torch, a.steps, a.warmup, a.jump),
+               "bulk1m": lambda: run_bulk1m(R, torch, a.steps, a.warmup),
+               "lfg_gen": lambda: run_lfg_gen(R, torch, a.steps, a.warmup),
+               "lfg_jumps": lambda: run_lfg_jumps(R, torch, a.steps, a.warmup),
+               "lfg_family": lambda: run_lfg_family(R, torch, a.steps, a.warmup),
+               "jumps1m": lambda: run_jumps1m(R, torch, a.steps, a.warmup)}
+    res = runners[a.workload]()
+    _progress(f"{a.workload} done")
     line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"], "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": res["dtype"], "data": "synthetic", "config": res["config"],
@@ -758,49 +880,50 @@ def main():
     for k in ("breakdown_ms", "output_write_GBps", "output_write_frac"):
         if k in res:
             line[k] = res[k]
+    if a.workload == "bulk1m":
+        ceil = run_store_ceiling(torch, a.steps, a.warmup)
+        line["store_ceiling"] = ceil
+        line["output_write_frac_of_store_ceiling"] = res["output_write_GBps"] / ceil["GBps"]
+        _progress("store ceiling done")
     line["tuned"] = tuned
-    if not a.no_extras and a.workload == "family65k":
+    if extras:
         also = {}
-        for name, fn in (("bulk1m", run_bulk1m), ("jumps1m", run_jumps1m)):
-            r = fn(R, torch, 10, 2)
-            also[name] = {k: r[k] for k in r if k not in ("metric",)}
-            _progress(f"{name} done")
-        also["jumps1m_batched"] = run_jumps1m_batched(R, torch, 5, 1)
+        r = run_family65k(R, torch, 10, 2, a.jump)
+        also["family65k"] = {**_brief(r), "breakdown_ms": r["breakdown_ms"]}
+        _progress("family65k done")
+        r = run_jumps1m(R, torch, 10, 2)
+        also["jumps1m"] = _brief(r)
+        _progress("jumps1m done")
+        r = run_jumps1m_batched(R, torch, 5, 1)
+        also["jumps1m_batched"] = {k: r[k] for k in ("value", "unit", "launch_ms", "host_prepare_ms",
+                                                      "end_to_end_jumps_per_s",
+                                                      "end_to_end_two_batches_in_turn_jumps_per_s")}
         _progress("jumps1m_batched done")
-        for name, fn, st_, wu_ in (("lfg_gen", run_lfg_gen, 20, 5), ("lfg_jumps", run_lfg_jumps, 5, 1)):
+        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_lanes)
+        also["serve"] = r
+        for name, fn, st_, wu_ in (("lfg_gen", run_lfg_gen, 20, 5), ("lfg_jumps", run_lfg_jumps, 5, 1),
+                                   ("lfg_family", run_lfg_family, 5, 1)):
             r = fn(R, torch, st_, wu_)
-            also[name] = {k: r[k] for k in r if k not in ("metric",)}
-            if not a.no_cpu:
-                also[name]["cpu_baseline"] = cpu_baseline(name, min(a.cpu_seconds, 3.0))
+            also[name] = _brief(r)
             _progress(f"{name} done")
-        r = run_lfg_family(R, torch, 5, 1)
-        also["lfg_family"] = {k: r[k] for k in r if k not in ("metric",)}
-        if not a.no_cpu:
-            also["lfg_family"]["cpu_baseline"] = cpu_baseline("lfg_family", min(a.cpu_seconds, 3.0))
-        _progress("lfg_family done")
-        also["paper_table1"] = run_paper_table1(R, torch, 5, 1)
-        also["paper_table2"] = run_paper_table2(R, torch)
+        r = run_paper_table1(R, torch, 5, 1)
+        also["paper_table1"] = {"value": r["value"], "unit": r["unit"], "s_for_1e9_draws": r["seconds_for_1e9_draws"]}
+        r = run_paper_table2(R, torch)
+        also["paper_table2_us"] = {k: v for k, v in r.items() if k.startswith("J=")}
         _progress("paper tables done")
-        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_baseline_requests)
-        also["serve"] = {"config": r["config"], **r["serve"]}
-        _progress("serve done")
-        r = run_serve(R, torch, a.serve_requests, a.serve_light_qps, a.serve_baseline_requests)
-        also["serve_light"] = {"config": r["config"], **r["serve"]}
-        _progress("serve_light done")
-        # Saturation (every request arrives at once), then 50% and 80% of the
-        # request rate the batched server sustained there.
-        r = run_serve(R, torch, a.serve_requests, 1e9, a.serve_baseline_requests)
-        also["serve_saturation"] = {"config": r["config"], **r["serve"]}
-        sat_qps = a.serve_requests / r["serve"]["batched"]["wall_s"]
-        for frac in (0.5, 0.8):
-            r = run_serve(R, torch, a.serve_requests, frac * sat_qps, a.serve_baseline_requests)
-            also[f"serve_{int(frac * 100)}pct_of_saturation"] = {"config": r["config"], **r["serve"]}
-        _progress("serve saturation sweep done")
         line["also"] = also
+    # The oracle's CPU baselines run last: they fork worker processes, and the
+    # GPU timings are taken before that.
     if not a.no_cpu and a.workload not in ("lfg_gen", "lfg_jumps", "lfg_family"):
         _progress("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
-    print(json.dumps(line), flush=True)
+        if extras:
+            line["cpu_baseline"]["single_thread"] = cpu_single_thread()
+    if extras and not a.no_cpu:
+        for name in ("family65k", "lfg_gen", "lfg_jumps", "lfg_family"):
+            cb = cpu_baseline(name, min(a.cpu_seconds, 3.0))
+            line["also"][name]["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "sample")}
+    print(json.dumps(_c(line)), flush=True)
 
 
 if __name__ == "__main__":

@@ -235,14 +235,17 @@ typedef struct ranmar_batch ranmar_batch;
 /* Creates a reusable batch executor able to take up to max_requests
  * requests and max_chunks chunks per run.  It owns device descriptor
  * buffers of fixed size (allocated here, once) and a captured hipGraph of
- * the persistent launch, re-played by every run.  chunk_draws = 0 picks the
- * tuned default.  *out receives the handle. */
+ * the persistent launch, re-played by every run.  chunk_draws = 0 takes the
+ * RANMAR_K_CHUNK tuner's pick (16384 if nothing was tuned).  Each run's
+ * mapping (bins, items per dequeue, jump width) comes from the
+ * RANMAR_K_BATCH tuner's table for its shape.  *out receives the handle. */
 int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chunk_draws,
                         ranmar_batch **out);
 
 /* Runs n requests (host array) in one graph launch on `stream`.  Returns
  * RANMAR_EINVAL for bad requests (bad seed, NULL output with count > 0,
- * bad fmt) and RANMAR_ENOMEM if n or the chunk total exceed the capacity.
+ * bad fmt, offset + count - 1 beyond 2^128 - 1) and RANMAR_ENOMEM if n or
+ * the chunk total exceed the capacity.
  * The batch may be reused once the stream has passed this run. */
 int ranmar_batch_run(ranmar_batch *b, const ranmar_request *reqs, uint64_t n, void *stream);
 
@@ -268,7 +271,8 @@ int ranmar_batch_destroy(ranmar_batch *b);
 
 typedef struct ranmar_serve_cfg {
     uint64_t max_inflight;   /* requests admitted but not released (0 = 65536) */
-    uint64_t chunk_draws;    /* draws per chunk (0 = 8192) */
+    uint64_t chunk_draws;    /* draws per chunk (0 = the RANMAR_K_CHUNK tuner's
+                                pick, else 8192) */
     uint64_t max_tick_chunks;/* chunks per launch (0 = 16384) */
     uint32_t lanes;          /* concurrent HIP streams for ticks (1..8, 0 = 2) */
     uint32_t queue_when_full;/* 1: over-budget requests wait; 0: EAGAIN */
@@ -301,7 +305,8 @@ int ranmar_serve_create(void *d_arena, uint64_t arena_bytes, const ranmar_serve_
 /* Queues a request; *ticket identifies it.  RANMAR_ENOMEM if its output can
  * never fit the arena, RANMAR_EAGAIN if the budget or in-flight limit is
  * full and the server was configured not to queue, RANMAR_EINVAL for a bad
- * seed or format.  t_arrival_ns (CLOCK_MONOTONIC, 0 = now) is the time from
+ * seed or format or when offset + count - 1 passes 2^128 - 1 (the server
+ * cuts requests into parts that start at 128-bit offsets of their own).  t_arrival_ns (CLOCK_MONOTONIC, 0 = now) is the time from
  * which its latency is measured. */
 int ranmar_serve_submit(ranmar_server *s, int32_t seed, ranmar_u128 offset, uint64_t count,
                         int fmt, uint64_t t_arrival_ns, uint64_t *ticket);
@@ -407,8 +412,17 @@ int ranmar_lfg_generate(const ranmar_lfg_params *p, const uint32_t *d_in, uint32
 typedef enum ranmar_kernel {
     RANMAR_K_GENERATE = 0,
     RANMAR_K_JUMP = 1,
-    RANMAR_K_FAMILY = 2   /* ranmar_jump_family: radix rounds on the VALU, or
+    RANMAR_K_FAMILY = 2,  /* ranmar_jump_family: radix rounds on the VALU, or
                              a matrix product on the matrix cores (MFMA) */
+    RANMAR_K_BATCH = 3,   /* the batch executor's tile and lane mapping, chosen
+                             by ranmar_batch_prepare per shape: bins, jump
+                             items per dequeue, and 8- or 32-lane jumps for
+                             requests without draws.  Shape: n requests of
+                             `count` draws each (0: jumps only). */
+    RANMAR_K_CHUNK = 4    /* draws per chunk of the batch executor (4096 <<
+                             variant), taken by ranmar_batch_create and
+                             ranmar_serve_create when they are given 0.  Same
+                             shape as RANMAR_K_BATCH. */
 } ranmar_kernel;
 
 /* Number of variants of a kernel, and a short name for each. */
@@ -420,13 +434,20 @@ int ranmar_tune_set(int kernel, int variant);
 
 /* Times every variant of `kernel` on synthetic data of the given shape
  * (n streams/requests; count = draws, jump bits, or for RANMAR_K_FAMILY
- * log2 of the spacing delta) on `stream`, stores the
+ * log2 of the spacing delta; for RANMAR_K_BATCH and RANMAR_K_CHUNK, draws
+ * per request of a batch of n requests at uniform 120-bit offsets, each
+ * launch timed alone on the device) on `stream`, stores the
  * winner for the shape bucket (log2 n, log2 count) and writes the per-variant
  * time (ms per launch, the best of several passes over all variants) to
  * ms_out[variant] (host, ranmar_tune_variants() entries, may be NULL).
  * Returns the winning variant index, or a negative status.  Allocates its
  * own synthetic inputs and outputs for the duration of the call. */
 int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double *ms_out, void *stream);
+
+/* Forgets what the tuner recorded for `kernel` (every shape; -1: every
+ * kernel), so that later calls take the built-in defaults again.  Forced
+ * variants (ranmar_tune_set) are not affected. */
+int ranmar_tune_clear(int kernel);
 
 /* Saves / loads the tuned table (text file, one line per bucket). */
 int ranmar_tune_save(const char *path);

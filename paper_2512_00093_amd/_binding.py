@@ -40,6 +40,8 @@ RANMAR_U24_F32 = 2
 RANMAR_K_GENERATE = 0
 RANMAR_K_JUMP = 1
 RANMAR_K_FAMILY = 2
+RANMAR_K_BATCH = 3
+RANMAR_K_CHUNK = 4
 STATE_WORDS = 98
 
 
@@ -128,6 +130,7 @@ _SIGS = {
     "ranmar_tune_variant_name": (ctypes.c_char_p, [_int, _int]),
     "ranmar_tune_set": (_int, [_int, _int]),
     "ranmar_tune_run": (_int, [_int, _u64, _u64, ctypes.POINTER(ctypes.c_double), _vp]),
+    "ranmar_tune_clear": (_int, [_int]),
     "ranmar_tune_save": (_int, [ctypes.c_char_p]),
     "ranmar_tune_load": (_int, [ctypes.c_char_p]),
 }
@@ -451,6 +454,10 @@ def ranmar_tune_run(kernel: int, n: int, count: int, stream=None):
     ms = (ctypes.c_double * nv)()
     best = _check(lib().ranmar_tune_run(kernel, n, count, ms, _stream(stream)), "ranmar_tune_run")
     return best, list(ms)
+
+
+def ranmar_tune_clear(kernel: int = -1):
+    return _check(lib().ranmar_tune_clear(kernel), "ranmar_tune_clear")
 
 
 def ranmar_tune_save(path: str):

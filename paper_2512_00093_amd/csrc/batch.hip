@@ -73,6 +73,10 @@ static int check_request(const ranmar_request& q, uint32_t L, uint64_t* nq) {
   if (q.fmt != RANMAR_U24 && q.fmt != RANMAR_F32) return RANMAR_EINVAL;
   if (q.count > 0 && (!q.d_out || ((uintptr_t)q.d_out & 3))) return RANMAR_EINVAL;
   if (q.d_state && ((uintptr_t)q.d_state & 3)) return RANMAR_EINVAL;
+  // Parts of a request cut at chunk boundaries start at offset + d (d <
+  // count) as 128-bit offsets of their own: the last must not pass 2^128 - 1.
+  const unsigned __int128 off = ((unsigned __int128)q.offset.hi << 64) | q.offset.lo;
+  if (q.count > 0 && off > ~(unsigned __int128)0 - (q.count - 1)) return RANMAR_EINVAL;
   *nq = (q.count + L - 1) / L;
   return RANMAR_OK;
 }
@@ -138,6 +142,7 @@ struct ranmar_batch {
   bool tried_wtab = false;  // the 20-bit window table was asked for
   uint8_t* kdesc = nullptr;   // kernel argument storage for the graph node
   void* kargs[2] = {nullptr, nullptr};
+  int variant = -1;           // mapping (BatchVariant); -1: the tuner's table
 };
 
 static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned grid) {
@@ -176,6 +181,10 @@ static uint64_t chunk_offset(uint64_t n, uint32_t nb) {
 }
 
 namespace ranmar {
+void batch_set_variant(ranmar_batch* b, int v) {
+  if (b) b->variant = (v >= 0 && v < BATCH_NUM_VARIANTS) ? v : -1;
+}
+
 void batch_use_wide_windows(ranmar_batch* b) {
   if (!b) return;
   b->tried_wtab = true;
@@ -198,7 +207,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   b->max_req = max_requests;
   b->max_chunks = max_chunks ? max_chunks : 1;
   b->max_slices = b->max_req + kMaxBins;  // each bin boundary splits at most one request
-  b->L = chunk_draws ? (uint32_t)chunk_draws : kDefaultChunk;
+  b->L = chunk_draws ? (uint32_t)chunk_draws : chunk_draws_default(kDefaultChunk);
   b->desc_cap = chunk_offset(b->max_req, kMaxBins) + sizeof(BChunk) * b->max_chunks;
   b->workers_max = std::max<unsigned>(persistent_grid((const void*)k_batch_tables, 64), kMaxBins);
   const uint64_t nflags = b->max_slices + 1;  // slice flags + the spare
@@ -255,10 +264,10 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   if (n == 0) return RANMAR_OK;
   // Validation and counts, in parts (large batches on several threads).
   const uint32_t parts = host_parts(n);
-  std::vector<uint64_t> p_total(parts, 0), p_jo(parts, 0);
+  std::vector<uint64_t> p_total(parts, 0), p_jo(parts, 0), p_draws(parts, 0);
   std::vector<int> p_rc(parts, RANMAR_OK);
   parallel_parts(n, parts, [&](uint64_t lo, uint64_t hi, uint32_t t) {
-    uint64_t tot = 0, jo = 0;
+    uint64_t tot = 0, jo = 0, dr = 0;
     for (uint64_t r = lo; r < hi; ++r) {
       uint64_t nq = 0;
       const int rc = check_request(reqs[r], b->L, &nq);
@@ -268,16 +277,24 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
       }
       tot += nq;
       jo += nq == 0;
+      dr += reqs[r].count;
     }
     p_total[t] = tot;
     p_jo[t] = jo;
+    p_draws[t] = dr;
   });
-  uint64_t total = 0, n_jo = 0;  // chunks; requests without draws
+  uint64_t total = 0, n_jo = 0, draws = 0;  // chunks; requests without draws; draws
   for (uint32_t t = 0; t < parts; ++t) {
     if (p_rc[t]) return p_rc[t];
     total += p_total[t];
     n_jo += p_jo[t];
+    draws += p_draws[t];
   }
+  // The mapping: forced on this batch (the tuner), else the tuned table's
+  // pick for this shape.
+  const int bv = b->variant >= 0 ? b->variant : batch_variant_for(n, draws / n);
+  const bool fine = bv == BATCH_FINE || bv == BATCH_BINS16_FINE;
+  const uint32_t max_bins = (bv == BATCH_BINS16 || bv == BATCH_BINS16_FINE) ? 16u : kMaxBins;
   if (total > b->max_chunks) return RANMAR_ENOMEM;
   // Many requests without draws: jump them with 20-bit windows (the 2.4 GB
   // table is built once per device, on first use; if it cannot be, the 8-bit
@@ -289,7 +306,7 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   }
   // Bins: about 4 units of work (jumps + chunks) per bin at least, at most 64.
   const uint64_t cost = n + total;
-  const uint32_t nb = (uint32_t)std::min<uint64_t>(kMaxBins, std::max<uint64_t>(1, cost / 4));
+  const uint32_t nb = (uint32_t)std::min<uint64_t>(max_bins, std::max<uint64_t>(1, cost / 4));
   const uint64_t req_off = req_offset(nb), chunk_off = chunk_offset(n, nb);
   // The staging buffer may still be read by the previous run's copy.
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
@@ -350,8 +367,15 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   }
   // Slice table: per bin, its slices with draws, then its share of the
   // requests without draws (an equal split, in order).
-  const bool octets = b->B.wtab20 != nullptr;
+  const bool octets = b->B.wtab20 != nullptr && bv != BATCH_PAIRS;
   const uint32_t wpb_max = std::max<uint32_t>(1, b->workers_max / nb);
+  // Jump items per dequeue: enough that each of the bin's workgroups takes
+  // about two, at most 8 (16 coarse), or one each (fine).
+  auto per_item = [&](uint32_t jobs) -> uint32_t {
+    if (fine) return 1u;
+    const uint32_t g = std::min<uint32_t>(8, std::max<uint32_t>(1, jobs / (2 * wpb_max)));
+    return bv == BATCH_COARSE ? std::min<uint32_t>(16, 2 * g) : g;
+  };
   uint64_t ns = 0, ti = 0, k0 = 0;
   uint32_t wpb = 1;
   for (uint32_t i = 0; i < nb; ++i) {
@@ -366,10 +390,10 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     k0 += nkb[i];
     // Jump pairs and octets are taken several at a time when a bin has many.
     const uint32_t n_jg = (bn.nsc + 1) / 2, n_jq = (bn.ns - bn.nsc + 7) / 8;
-    bn.g = std::min<uint32_t>(8, std::max<uint32_t>(1, n_jg / (2 * wpb_max)));
+    bn.g = per_item(n_jg);
     bn.n_ju = (n_jg + bn.g - 1) / bn.g;
     bn.n_cg = (bn.nk + 1) / 2;
-    bn.gq = std::min<uint32_t>(8, std::max<uint32_t>(1, n_jq / (2 * wpb_max)));
+    bn.gq = per_item(n_jq);
     bn.n_qi = (n_jq + bn.gq - 1) / bn.gq;
     // Workgroups per bin: as many as the fullest bin has items, within the device.
     wpb = std::max(wpb, std::min(wpb_max, bn.n_ju + bn.n_cg + bn.n_qi));

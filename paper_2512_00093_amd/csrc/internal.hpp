@@ -110,6 +110,26 @@ hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uin
 // Stream family by prefix doubling: out[k] = f^(k*delta)(base), k < n.
 hipError_t launch_family(const uint32_t* base, ranmar_u128 delta, uint64_t n, uint32_t* out, hipStream_t st);
 
+// Batch executor mappings (all bit-identical): how prepare cuts the work
+// into bins and items.  Picked per (requests, draws per request) bucket.
+enum BatchVariant : int {
+  BATCH_AUTO = 0,         // up to 64 bins; jump pairs / octets per dequeue from the bin's fill
+  BATCH_FINE = 1,         // one jump pair / octet per dequeue (finest balance)
+  BATCH_COARSE = 2,       // twice BATCH_AUTO's items per dequeue (fewer dequeues)
+  BATCH_BINS16 = 3,       // at most 16 bins (more workgroups per bin)
+  BATCH_BINS16_FINE = 4,  // both
+  BATCH_PAIRS = 5,        // slices without draws by pair items (32 lanes each) instead of octets (8 lanes)
+  BATCH_NUM_VARIANTS = 6
+};
+int batch_variant_for(uint64_t n, uint64_t draws_per_request);
+void batch_set_variant(ranmar_batch* b, int v);  // -1: from the table
+// Chunk lengths the tuner chooses among (create time): 4096 << v draws.
+constexpr int kChunkVariants = 4;
+inline uint32_t chunk_variant_draws(int v) { return 4096u << v; }
+// Chunk length for a batch or server created with chunk_draws = 0: the
+// forced or tuned pick, else `fallback`.
+uint32_t chunk_draws_default(uint32_t fallback);
+
 // Library-wide state.
 int ensure_init();          // RANMAR_OK / RANMAR_ENODEV / RANMAR_EHIP
 int gen_variant_for(uint64_t n, uint64_t count);   // tuned or default

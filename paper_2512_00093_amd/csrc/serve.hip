@@ -262,6 +262,10 @@ struct ranmar_server {
 int ranmar_server::submit_locked(int32_t seed, ranmar_u128 offset, uint64_t count, int fmt, uint64_t t_arrival_ns,
                                  uint64_t tag, uint64_t* ticket) {
   if (seed < 1 || seed > 900000000 || (fmt != RANMAR_U24 && fmt != RANMAR_F32)) return RANMAR_EINVAL;
+  // A request is cut into slices that start at offset + d (d < count) as
+  // 128-bit offsets of their own: the last one must not pass 2^128 - 1.
+  const unsigned __int128 off = ((unsigned __int128)offset.hi << 64) | offset.lo;
+  if (count > 0 && off > ~(unsigned __int128)0 - (count - 1)) return RANMAR_EINVAL;
   if (count > (UINT64_MAX - kAlign) / 4) return RANMAR_ENOMEM;
   const uint64_t nbytes = (4 * count + kAlign - 1) & ~(kAlign - 1);
   if (nbytes > arena_bytes) {
@@ -314,7 +318,7 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
   if (!s->cfg.max_inflight) s->cfg.max_inflight = 65536;
   // 8192: measured lower p50/p99 than 16384 at 2e4 and 5e5 requests/s (more
   // chunks of a request run at once), at the same throughput.
-  if (!s->cfg.chunk_draws) s->cfg.chunk_draws = 8192;
+  if (!s->cfg.chunk_draws) s->cfg.chunk_draws = ranmar::chunk_draws_default(8192);
   if (!s->cfg.max_tick_chunks) s->cfg.max_tick_chunks = 16384;
   if (!s->cfg.lanes) s->cfg.lanes = 2;
   if (s->cfg.lanes > 8 || s->cfg.chunk_draws > (1u << 24) || s->cfg.max_tick_chunks > (1u << 22)) {

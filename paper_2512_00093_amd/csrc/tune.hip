@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -20,7 +21,8 @@ namespace ranmar {
 
 namespace {
 std::mutex g_mu;
-int g_forced[3] = {-1, -1, -1};
+int g_forced[5] = {-1, -1, -1, -1, -1};
+int g_chunk_pick = -1;  // last tuned or loaded RANMAR_K_CHUNK variant
 std::map<std::tuple<int, int, int>, int> g_table;  // (kernel, log2 n, log2 count) -> variant
 
 int ilog2(uint64_t v) {
@@ -59,6 +61,20 @@ int family_variant_for(uint64_t n) {
   // holds two waves per SIMD, the 16-row one four).
   if (n < 32768) return FAMILY_RADIX;
   return n < 524288 ? FAMILY_GEMM32 : FAMILY_GEMM;
+}
+
+int batch_variant_for(uint64_t n, uint64_t draws_per_request) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (g_forced[RANMAR_K_BATCH] >= 0) return g_forced[RANMAR_K_BATCH];
+  auto it = g_table.find({RANMAR_K_BATCH, ilog2(n), ilog2(draws_per_request + 1)});
+  if (it != g_table.end()) return it->second;
+  return BATCH_AUTO;
+}
+
+uint32_t chunk_draws_default(uint32_t fallback) {
+  std::lock_guard<std::mutex> g(g_mu);
+  const int v = g_forced[RANMAR_K_CHUNK] >= 0 ? g_forced[RANMAR_K_CHUNK] : g_chunk_pick;
+  return v >= 0 ? chunk_variant_draws(v) : fallback;
 }
 
 int gen_variant_for(uint64_t n, uint64_t count) {
@@ -188,6 +204,142 @@ done:
   return rc;
 }
 
+// A batch of n requests of `count` draws each (uniform 120-bit offsets,
+// pseudo-random seeds; every request also returns its final state), for the
+// batch and chunk tuners.  Owns its device buffers.
+struct TuneBatch {
+  std::vector<ranmar_request> reqs;
+  uint8_t* d_out = nullptr;
+  uint32_t* d_states = nullptr;
+  bool ok = false;
+  TuneBatch(uint64_t n, uint64_t count) : reqs(n) {
+    if (hipMalloc(&d_states, sizeof(ranmar_state) * n) != hipSuccess) return;
+    if (count && hipMalloc(&d_out, 4 * n * count) != hipSuccess) return;
+    uint64_t x = 0x2545F4914F6CDD1Dull;
+    auto next = [&x] {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      return x;
+    };
+    for (uint64_t i = 0; i < n; ++i) {
+      ranmar_request& q = reqs[i];
+      q.seed = (int32_t)(1 + next() % 900000000ull);
+      q.fmt = RANMAR_F32;
+      q.offset.lo = next();
+      q.offset.hi = next() & ((1ull << 56) - 1);
+      q.count = count;
+      q.d_out = count ? d_out + 4 * i * count : nullptr;
+      q.d_state = (ranmar_state*)(d_states + (uint64_t)kWords * i);
+    }
+    ok = true;
+  }
+  ~TuneBatch() {
+    hipDeviceSynchronize();
+    if (d_out) hipFree(d_out);
+    if (d_states) hipFree(d_states);
+  }
+};
+
+// Device time of one prepared launch of `b` (ms), the best of `rounds`
+// passes of `reps` launches after one untimed launch; each launch is timed
+// alone (its host preparation is outside the events).
+static double time_batch(ranmar_batch* b, const TuneBatch& tb, hipEvent_t e0, hipEvent_t e1, hipStream_t st,
+                         int reps) {
+  double sum = 0;
+  for (int r = -1; r < reps; ++r) {
+    if (ranmar_batch_prepare(b, tb.reqs.data(), tb.reqs.size()) != RANMAR_OK) return -1;
+    if (hipEventRecord(e0, st) != hipSuccess) return -1;
+    if (ranmar_batch_launch(b, st) != RANMAR_OK) return -1;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (r >= 0) sum += ms;
+  }
+  return sum / reps;
+}
+
+static bool batch_shape_ok(uint64_t n, uint64_t count) {
+  return n >= 1 && n <= (1ull << 22) && count <= (1ull << 24) && n * count <= (1ull << 31);
+}
+
+// Times the batch executor's mappings on one batch of the given shape.
+static int tune_batch(uint64_t n, uint64_t count, double* ms_out, hipStream_t st) {
+  if (!batch_shape_ok(n, count)) return RANMAR_EINVAL;
+  TuneBatch tb(n, count);
+  if (!tb.ok) return RANMAR_ENOMEM;
+  const uint32_t L = chunk_draws_default(16384);
+  ranmar_batch* b = nullptr;
+  int rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<double> best(BATCH_NUM_VARIANTS, 1e30);
+  rc = RANMAR_EHIP;
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    rc = RANMAR_OK;
+    for (int rd = 0; rd < 2 && rc == RANMAR_OK; ++rd)
+      for (int v = 0; v < BATCH_NUM_VARIANTS; ++v) {
+        batch_set_variant(b, v);
+        const double ms = time_batch(b, tb, e0, e1, st, 2);
+        if (ms < 0) {
+          rc = RANMAR_EHIP;
+          break;
+        }
+        best[v] = std::min(best[v], ms);
+      }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  ranmar_batch_destroy(b);
+  if (rc) return rc;
+  int bv = 0;
+  for (int v = 0; v < BATCH_NUM_VARIANTS; ++v) {
+    if (ms_out) ms_out[v] = best[v];
+    if (best[v] < best[bv]) bv = v;
+  }
+  std::lock_guard<std::mutex> g(g_mu);
+  g_table[{RANMAR_K_BATCH, ilog2(n), ilog2(count + 1)}] = bv;
+  return bv;
+}
+
+// Times the chunk lengths: one batch executor per length, each running the
+// same batch with its own tuned (or default) mapping.
+static int tune_chunk(uint64_t n, uint64_t count, double* ms_out, hipStream_t st) {
+  if (!batch_shape_ok(n, count) || count == 0) return RANMAR_EINVAL;
+  TuneBatch tb(n, count);
+  if (!tb.ok) return RANMAR_ENOMEM;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return RANMAR_EHIP;
+  }
+  std::vector<double> best(kChunkVariants, 1e30);
+  int rc = RANMAR_OK;
+  for (int rd = 0; rd < 2 && rc == RANMAR_OK; ++rd)
+    for (int v = 0; v < kChunkVariants && rc == RANMAR_OK; ++v) {
+      const uint32_t L = chunk_variant_draws(v);
+      ranmar_batch* b = nullptr;
+      rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b);
+      if (rc) break;
+      const double ms = time_batch(b, tb, e0, e1, st, 2);
+      ranmar_batch_destroy(b);
+      if (ms < 0) rc = RANMAR_EHIP;
+      else best[v] = std::min(best[v], ms);
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  int bv = 0;
+  for (int v = 0; v < kChunkVariants; ++v) {
+    if (ms_out) ms_out[v] = best[v];
+    if (best[v] < best[bv]) bv = v;
+  }
+  std::lock_guard<std::mutex> g(g_mu);
+  g_table[{RANMAR_K_CHUNK, ilog2(n), ilog2(count + 1)}] = bv;
+  g_chunk_pick = bv;
+  return bv;
+}
+
 }  // namespace ranmar
 
 using namespace ranmar;
@@ -198,6 +350,8 @@ int ranmar_tune_variants(int kernel) {
   if (kernel == RANMAR_K_GENERATE) return GEN_NUM_VARIANTS;
   if (kernel == RANMAR_K_JUMP) return kJumpVariants;
   if (kernel == RANMAR_K_FAMILY) return FAMILY_NUM_VARIANTS;
+  if (kernel == RANMAR_K_BATCH) return BATCH_NUM_VARIANTS;
+  if (kernel == RANMAR_K_CHUNK) return kChunkVariants;
   return RANMAR_EINVAL;
 }
 
@@ -212,6 +366,11 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_RADIX) return "radix256_valu";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM) return "product_mfma_i8";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM32) return "product_mfma32_i8";
+  static const char* const kBatchNames[BATCH_NUM_VARIANTS] = {"bins64_auto", "bins64_fine", "bins64_coarse",
+                                                               "bins16_auto", "bins16_fine", "bins64_pairs"};
+  if (kernel == RANMAR_K_BATCH && variant >= 0 && variant < BATCH_NUM_VARIANTS) return kBatchNames[variant];
+  static const char* const kChunkNames[kChunkVariants] = {"chunk4096", "chunk8192", "chunk16384", "chunk32768"};
+  if (kernel == RANMAR_K_CHUNK && variant >= 0 && variant < kChunkVariants) return kChunkNames[variant];
   return nullptr;
 }
 
@@ -231,6 +390,8 @@ int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void
   hipStream_t st = (hipStream_t)stream;
   if (kernel == RANMAR_K_JUMP) return tune_jump(n, count ? (int)count : 120, ms_out, st);
   if (kernel == RANMAR_K_FAMILY) return tune_family(n, count ? (int)count : 40, ms_out, st);
+  if (kernel == RANMAR_K_BATCH) return tune_batch(n, count, ms_out, st);
+  if (kernel == RANMAR_K_CHUNK) return tune_chunk(n, count, ms_out, st);
   if (count == 0 || n > (1ull << 24) || count > (1ull << 24) || n * count > (1ull << 31)) return RANMAR_EINVAL;
   // Synthetic states: seeds 1..n at offset 0.
   int32_t* d_seeds = nullptr;
@@ -266,6 +427,15 @@ done:
   return rc;
 }
 
+int ranmar_tune_clear(int kernel) {
+  if (kernel != -1 && ranmar_tune_variants(kernel) < 0) return RANMAR_EINVAL;
+  std::lock_guard<std::mutex> g(g_mu);
+  for (auto it = g_table.begin(); it != g_table.end();)
+    it = (kernel == -1 || std::get<0>(it->first) == kernel) ? g_table.erase(it) : std::next(it);
+  if (kernel == -1 || kernel == RANMAR_K_CHUNK) g_chunk_pick = -1;
+  return RANMAR_OK;
+}
+
 int ranmar_tune_save(const char* path) {
   if (!path) return RANMAR_EINVAL;
   FILE* f = std::fopen(path, "w");
@@ -284,6 +454,7 @@ int ranmar_tune_load(const char* path) {
   if (!f) return RANMAR_ENOENT;
   char line[256];
   std::map<std::tuple<int, int, int>, int> t;
+  int chunk = -1;
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
     int k, a, b, v;
@@ -294,11 +465,13 @@ int ranmar_tune_load(const char* path) {
         return RANMAR_EINVAL;
       }
       t[{k, a, b}] = v;
+      if (k == RANMAR_K_CHUNK) chunk = v;  // the last chunk line is the pick
     }
   }
   std::fclose(f);
   std::lock_guard<std::mutex> g(g_mu);
   for (auto& kv : t) g_table[kv.first] = kv.second;
+  if (chunk >= 0) g_chunk_pick = chunk;
   return RANMAR_OK;
 }
 

@@ -375,3 +375,106 @@ def test_batch_large_prepare_in_parts(orc):
     idx = [0, 29_999, 30_000, 70_000, 70_001, n - 1]
     assert np.array_equal(w[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
     _check(orc, drawn)
+
+
+# --- tuner over the batch executor --------------------------------------------
+@pytest.mark.parametrize("variant", range(6))
+def test_batch_every_mapping_bit_identical(orc, variant):
+    """Every mapping the batch tuner can pick (bins, jump items per dequeue,
+    8- or 32-lane jumps for requests without draws) on one batch that mixes
+    20,000 jump-only requests (octet items from 16,384 on), requests with
+    draws and one long request split over bins: the same bits as
+    ranmar_seed_jump and the oracle."""
+    n = 20000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=24)
+    states = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+    items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                  state=states[i]) for i in range(n)]
+    drawn = _mixed_requests(12, 70 + variant, max_count=70_000, with_zero=False)
+    drawn[2]["count"] = 1_500_007
+    _alloc(drawn)
+    mixed = items[:7000] + drawn + items[7000:]
+    R.ranmar_tune_set(R.RANMAR_K_BATCH, variant)
+    b = R.ranmar_batch_create(len(mixed), 256)
+    try:
+        say(f"batch mapping {R.ranmar_tune_variant_name(R.RANMAR_K_BATCH, variant)} n={len(mixed)}")
+        R.ranmar_batch_run(b, R.make_requests(mixed))
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+        R.ranmar_tune_set(R.RANMAR_K_BATCH, -1)
+    direct = R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev()))
+    assert torch.equal(states, direct)
+    idx = [0, 6999, 7000, n - 1]
+    assert np.array_equal(u32(states)[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
+    _check(orc, drawn)
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_batch_every_chunk_length_bit_identical(orc, variant):
+    """Every chunk length the chunk tuner can pick (4,096 << variant draws),
+    taken by a batch created with chunk_draws = 0: requests whose counts
+    straddle chunk boundaries give the oracle's draws and final states."""
+    items = _alloc(_mixed_requests(24, 80 + variant, max_count=200_000))
+    items[4]["count"] = 4096 * 5 + 1
+    items[4]["out"] = torch.full((items[4]["count"],), -3, dtype=torch.float32 if items[4]["fmt"] else torch.int32,
+                                 device=dev())
+    R.ranmar_tune_set(R.RANMAR_K_CHUNK, variant)
+    try:
+        b = R.ranmar_batch_create(32, 4096, 0)
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_CHUNK, -1)
+    try:
+        say(f"batch chunk length {R.ranmar_tune_variant_name(R.RANMAR_K_CHUNK, variant)}")
+        R.ranmar_batch_run(b, R.make_requests(items))
+        torch.cuda.synchronize()
+        _check(orc, items)
+    finally:
+        R.ranmar_batch_destroy(b)
+
+
+def test_batch_and_chunk_tuners_pick_a_variant():
+    """The tuner times every mapping and every chunk length on the device at
+    a given shape and records a pick that later batches use."""
+    try:
+        best, ms = R.ranmar_tune_run(R.RANMAR_K_BATCH, 4096, 0)
+        assert 0 <= best < 6 and np.all(np.asarray(ms) > 0)
+        best_c, ms_c = R.ranmar_tune_run(R.RANMAR_K_CHUNK, 64, 100_000)
+        assert 0 <= best_c < 4 and np.all(np.asarray(ms_c) > 0)
+        best_b2, _ = R.ranmar_tune_run(R.RANMAR_K_BATCH, 64, 100_000)
+        assert 0 <= best_b2 < 6
+    finally:  # later tests get the built-in defaults again
+        R.ranmar_tune_clear(R.RANMAR_K_BATCH)
+        R.ranmar_tune_clear(R.RANMAR_K_CHUNK)
+
+
+def test_requests_ending_at_the_top_of_the_offset_range(orc):
+    """A request is cut into parts that start at offset + d as 128-bit
+    offsets of their own, so offset + count - 1 must stay below 2^128: a
+    request whose parts would pass it is refused (batch and server) instead
+    of restarting near offset 0; one that ends exactly at 2^128 - 1 runs and
+    gives the oracle's draws."""
+    top = (1 << 128) - 5
+    b = R.ranmar_batch_create(4, 64, 1024)
+    srv, arena = _server(64 << 20, lanes=1, chunk_draws=1024)
+    try:
+        out = torch.zeros(4 * 1024, dtype=torch.int32, device=dev())
+        bad = dict(seed=5, offset=top, count=3 * 1024, fmt=0, out=out, state=None)
+        with pytest.raises(R.RanmarError) as e:
+            R.ranmar_batch_run(b, R.make_requests([bad]))
+        assert e.value.status == R.RANMAR_EINVAL
+        st, _ = R.ranmar_serve_submit(srv, 5, top, 3 * 1024, 0)
+        assert st == R.RANMAR_EINVAL
+        items = _alloc([dict(seed=5, offset=top, count=5, fmt=0)])
+        say("batch request ending at 2^128 - 1")
+        R.ranmar_batch_run(b, R.make_requests(items))
+        torch.cuda.synchronize()
+        _check(orc, items)
+        st, t = R.ranmar_serve_submit(srv, 5, top, 5, 0)
+        assert st == 0 and R.ranmar_serve_wait(srv, t, 10_000_000_000) == 0
+        assert np.array_equal(_result(srv, arena, t, 0), u32(items[0]["out"])[:5])
+        R.ranmar_serve_release(srv, t)
+    finally:
+        R.ranmar_batch_destroy(b)
+        R.ranmar_serve_destroy(srv)
