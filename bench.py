@@ -88,6 +88,8 @@ def _parse():
     ap.add_argument("--serve-qps", type=float, default=2e4,
                     help="--workload serve: offered load (requests/s) of the light-load comparison")
     ap.add_argument("--serve-lanes", type=int, default=4, help="HIP streams of the server, both arms")
+    ap.add_argument("--serve-capacity-only", action="store_true",
+                    help="--workload serve: only the batched arm at capacity (for profiling)")
     ap.add_argument("--jump", default="family", choices=["family", "lanes"],
                     help="family65k: stream starts by prefix doubling or one jump per stream")
     ap.add_argument("--no-extras", action="store_true")
@@ -425,6 +427,18 @@ def run_jumps1m(R, torch, steps, warmup):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ms = tm.mean_ms("jump")
+    # The same jumps on states already seeded (ranmar_jump, no seeding in the
+    # launch): the difference is what seeding costs inside the launch.
+    st0 = R.ranmar_seed_batch(seeds)
+    R.ranmar_jump(st0, offs)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        a, b = tm.span("jump_only")
+        a.record()
+        R.ranmar_jump(st0, offs)
+        b.record()
+    torch.cuda.synchronize()
+    ms_jump_only = tm.mean_ms("jump_only")
     # Algorithmic work of the launch: one 97 x 97 application (9409
     # multiply-adds) per non-zero 20-bit digit of J (the windowed method of
     # the tables t^(d 2^(20w)) mod phi).  Seeding (Appendix A, done in the
@@ -445,6 +459,7 @@ def run_jumps1m(R, torch, steps, warmup):
                               "20-bit digit); seeding not counted; square-and-multiply would need %.3g per jump"
                               % (macs / n, sqmul / min(n, 10000) + MACS_APPLY),
                      "ops_per_launch": macs, "launch_ms": ms},
+        "jump_only_launch_ms": ms_jump_only,
     }
 
 
@@ -737,7 +752,7 @@ def serve_arm(R, torch, tr, n, qps, lanes, unbatched, arena):
             "arena_peak_GiB": st.bytes_peak / 2 ** 30}
 
 
-def run_serve(R, torch, n_req, light_qps, lanes):
+def run_serve(R, torch, n_req, light_qps, lanes, capacity_only=False):
     """Serving (200,000 requests: Poisson arrivals, seed uniform on [1, 9e8],
     offset uniform on [0, 2^120), count log-uniform on [1e2, 1e7], float32
     output, 64 GiB budget), continuous batching against one launch per
@@ -757,6 +772,9 @@ def run_serve(R, torch, n_req, light_qps, lanes):
         cap = serve_arm(R, torch, tr, n_req, 1e12, lanes, ub, arena)
         res["capacity"] = cap
         _progress(f"serve {arm} capacity: {cap['req_per_s']:.4g} req/s")
+        if capacity_only:
+            out[arm] = res
+            break
         res[f"light_{light_qps:g}qps"] = serve_arm(R, torch, tr, n_req, light_qps, lanes, ub, arena)
         for frac in ((0.5, 0.8) if not ub else (0.8,)):
             res[f"{int(frac * 100)}pct"] = serve_arm(R, torch, tr, n_req, frac * cap["req_per_s"], lanes, ub, arena)
@@ -860,7 +878,7 @@ def main():
     if tuned:
         _progress("autotuned: " + json.dumps(tuned))
     if a.workload == "serve":
-        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_lanes)
+        r = run_serve(R, torch, a.serve_requests, a.serve_qps, a.serve_lanes, a.serve_capacity_only)
         print(json.dumps(_c({"metric": "served draws/s (p50/p99 latency)",
                              "value": r["batched"]["capacity"]["draws_per_s"], "unit": "draws/s", "n_gpus": 1,
                              "higher_is_better": True, "data": "synthetic", **r})), flush=True)
@@ -892,7 +910,7 @@ def main():
         also["family65k"] = {**_brief(r), "breakdown_ms": r["breakdown_ms"]}
         _progress("family65k done")
         r = run_jumps1m(R, torch, 10, 2)
-        also["jumps1m"] = _brief(r)
+        also["jumps1m"] = {**_brief(r), "jump_only_launch_ms": r["jump_only_launch_ms"]}
         _progress("jumps1m done")
         r = run_jumps1m_batched(R, torch, 5, 1)
         also["jumps1m_batched"] = {k: r[k] for k in ("value", "unit", "launch_ms", "host_prepare_ms",

@@ -30,7 +30,7 @@
 
 namespace ranmar {
 
-__global__ __launch_bounds__(64) void k_batch_tables(uint8_t* desc, BatchBuffers B) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tables(uint8_t* desc, BatchBuffers B) {
   batch_persistent(TableDesc{desc}, B);
 }
 

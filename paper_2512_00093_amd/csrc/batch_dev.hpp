@@ -185,7 +185,7 @@ __device__ __forceinline__ void publish_wait() {
 
 template <class Desc>
 __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h, const BatchBuffers& B,
-                                                const BinInfo& bn, uint32_t p, uint32_t* lds) {
+                                                const BinInfo& bn, uint32_t p, uint32_t* lds, const SeedLds<false>& stab) {
   const uint32_t lane = threadIdx.x;
   const uint32_t half = lane >> 5, l = lane & 31u;
   const uint32_t rl = 2u * p + half;
@@ -195,7 +195,7 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   uint32_t* Bp = X + 193;
   BReq q{};
   if (active) q = D.req(h, r);
-  const bool valid = active && seed_half(q.seed, X, l);
+  const bool valid = active && seed_group_tab<32, 4, false>(q.seed, X, l, stab);
   if (!valid) X[l] = X[l + 32] = X[l + 64] = X[97] = 0;
   wave_sync();
   const uint32_t c = X[97];
@@ -292,7 +292,7 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
 // caller's record, if it asked for one.
 template <class Desc>
 __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, const BatchBuffers& B,
-                                               const BinInfo& bn, uint32_t qi, uint32_t* lds) {
+                                               const BinInfo& bn, uint32_t qi, uint32_t* lds, const SeedLds<false>& stab) {
   const uint32_t lane = threadIdx.x;
   const uint32_t grp = lane >> 3, l = lane & 7u;
   const uint32_t rl = bn.nsc + 8u * qi + grp;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
   uint32_t* Bp = X + 193;
   BReq q{};
   if (active) q = D.req(h, bn.s0 + rl);
-  const bool valid = active && seed_group<8>(q.seed, X, l);
+  const bool valid = active && seed_group_tab<8, 4, false>(q.seed, X, l, stab);
   if (!valid) {
 #pragma unroll
     for (int k = 0; k < 96; k += 8) X[l + k] = 0;
@@ -331,7 +331,10 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
   const BHeader h = D.header();
   const uint32_t lane = threadIdx.x;
   __shared__ uint32_t lds[kWaveLds];
-  if (blockIdx.x >= h.n_workers) return;
+  __shared__ SeedLds<false> seed_tab;
+  if (blockIdx.x >= h.n_workers) return;  // whole workgroups leave together
+  seed_lds_fill(seed_tab, lane, 64);
+  __syncthreads();
   const uint32_t x = blockIdx.x % h.n_bins;
   const BinInfo bn = D.bin(x);
   uint32_t* ctr = D.counter(x, B.queue);
@@ -347,13 +350,13 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
     const uint32_t item = __builtin_amdgcn_readfirstlane(got);
     if (item < bn.n_ju) {
       const uint32_t p1 = (item + 1) * bn.g < n_jg ? (item + 1) * bn.g : n_jg;
-      for (uint32_t p = item * bn.g; p < p1; ++p) batch_jump_pair(D, h, B, bn, p, lds);
+      for (uint32_t p = item * bn.g; p < p1; ++p) batch_jump_pair(D, h, B, bn, p, lds, seed_tab);
     } else if (item < bn.n_ju + bn.n_cg) {
       batch_chunk_pair(D, h, B, bn, item - bn.n_ju, lds);
     } else if (item < bn.n_ju + bn.n_cg + bn.n_qi) {
       const uint32_t it = item - bn.n_ju - bn.n_cg;
       const uint32_t p1 = (it + 1) * bn.gq < n_jq ? (it + 1) * bn.gq : n_jq;
-      for (uint32_t p = it * bn.gq; p < p1; ++p) batch_jump_oct(D, h, B, bn, p, lds);
+      for (uint32_t p = it * bn.gq; p < p1; ++p) batch_jump_oct(D, h, B, bn, p, lds, seed_tab);
     } else {
       break;
     }

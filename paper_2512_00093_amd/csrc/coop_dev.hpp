@@ -25,6 +25,8 @@
 // multiply-add costs half an LDS read.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "seed_dev.hpp"
 
@@ -277,6 +279,143 @@ __device__ __forceinline__ bool seed_group(int32_t seed, uint32_t* X, uint32_t l
     X[0] = seed_word_at(96, a0, b0, c0, l0);
     X[97] = kC0;
   }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Seeding by table steps (the same bits as seed_group, fewer instructions)
+// ---------------------------------------------------------------------------
+// Step n of the initialisation needs only m_n mod 64 and l_n mod 64: the bit
+// is bit 5 of l_n m_n mod 64.  In the exponent form m_n = 2^(e_n) mod 179 with
+// e_n = e_(n-3) + e_(n-2) + e_(n-1) mod 178, so a step is one table lookup
+// indexed by that sum x < 534: entry x holds m mod 64 in bits 0..5 and
+// x mod 178 from bit 8 on (bit 10 in the 32-bit table).  Adding three entries
+// adds both fields without carries between them (3 * 63 < 256), so the sum
+// shifted right by 8 is the next entry's byte offset in the 32-bit table (in
+// the 16-bit one: half of it), and the low field never matters for the bit
+// (its multiples of 256 vanish mod 64).  The congruential generator has full
+// period 169, so l_n = C[(pos(l_0) + n) mod 169] with its cycle C from 0; a
+// word's 24 steps read 24 consecutive entries of the cycle (repeated past 169
+// so that no step wraps).
+struct SeedStepTables {
+  uint32_t emt[534];   // (x mod 178) << 10 | (2^(x mod 178) mod 179) mod 64
+  uint8_t l64[192];    // C[i mod 169] mod 64
+  uint8_t pos[169];    // pos(l): C[pos(l)] = l
+};
+
+constexpr SeedStepTables make_seed_step_tables() {
+  SeedStepTables t{};
+  uint32_t p2[178] = {};
+  uint32_t v = 1;
+  for (int e = 0; e < 178; ++e) {
+    p2[e] = v;
+    v = v * 2 % 179;
+  }
+  for (int x = 0; x < 534; ++x) t.emt[x] = (uint32_t)(x % 178) << 10 | (p2[x % 178] % 64);
+  uint32_t cyc[169] = {};
+  uint32_t c = 0;
+  for (int p = 0; p < 169; ++p) {
+    cyc[p] = c;
+    t.pos[c] = (uint8_t)p;
+    c = (53 * c + 1) % 169;
+  }
+  for (int i = 0; i < 192; ++i) t.l64[i] = (uint8_t)(cyc[i % 169] % 64);
+  return t;
+}
+
+static __constant__ const SeedStepTables kSeedStep = make_seed_step_tables();
+
+// The step tables in LDS, filled by the nthreads threads of a workgroup
+// (followed by a workgroup barrier in the caller).  WIDE: 32-bit entries (one
+// shift per step); otherwise 16-bit entries holding x mod 178 from bit 8 on
+// (half the LDS, one more shift per step).
+template <bool WIDE>
+struct SeedLds {
+  typedef typename std::conditional<WIDE, uint32_t, uint16_t>::type entry;
+  entry emt[534];
+  uint8_t l64[192];
+  static constexpr int kShift = WIDE ? 10 : 8;  // bit of the x field in an entry
+};
+
+template <bool WIDE>
+__device__ __forceinline__ void seed_lds_fill(SeedLds<WIDE>& s, uint32_t t, uint32_t nthreads) {
+  for (uint32_t i = t; i < 534; i += nthreads)
+    s.emt[i] = (typename SeedLds<WIDE>::entry)(WIDE ? kSeedStep.emt[i] : (kSeedStep.emt[i] >> 10) << 8 | (kSeedStep.emt[i] & 63u));
+  for (uint32_t i = t; i < 192; i += nthreads) s.l64[i] = kSeedStep.l64[i];
+}
+
+// Words k0 .. k0 + P - 1 of lane l's list (word k of the list is l + k G for
+// k < 96 / G, and word 96 after them), stepped together so that their
+// lookups overlap.
+template <int G, int K0, int P, bool WIDE>
+__device__ __forceinline__ void seed_words_tab(uint32_t* X, uint32_t l, const SeedLds<WIDE>& tab, uint32_t a0,
+                                               uint32_t b0, uint32_t c0, uint32_t p0) {
+  constexpr int W = 96 / G;
+  const uint8_t* emt = (const uint8_t*)tab.emt;
+  uint32_t ta[P], tb[P], tc[P], pw[P], acc[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int k = K0 + i;
+    const uint32_t w = k < W ? l + (uint32_t)(k * G) : 96u;
+    const uint8_t* M = kSeedTab.m[w];
+    const uint32_t a = (M[0] * a0 + M[1] * b0 + M[2] * c0) % 178u;
+    const uint32_t b = (M[3] * a0 + M[4] * b0 + M[5] * c0) % 178u;
+    const uint32_t c = (M[6] * a0 + M[7] * b0 + M[8] * c0) % 178u;
+    ta[i] = tab.emt[a];
+    tb[i] = tab.emt[b];
+    tc[i] = tab.emt[c];
+    pw[i] = (p0 + 24u * w + 1u) % 169u;  // cycle position of the word's first step
+    acc[i] = 0;
+  }
+#pragma unroll
+  for (int bit = 0; bit < 24; ++bit)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const uint32_t sum = ta[i] + tb[i] + tc[i];
+      const uint32_t tn = WIDE ? *(const uint32_t*)(emt + (sum >> 8))
+                               : (uint32_t) * (const uint16_t*)(emt + ((sum >> 8) << 1));
+      const uint32_t lv = tab.l64[pw[i] + bit];
+      acc[i] = (acc[i] << 1) | __builtin_amdgcn_ubfe(mul24(lv, tn), 5u, 1u);
+      ta[i] = tb[i];
+      tb[i] = tc[i];
+      tc[i] = tn;
+    }
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int k = K0 + i;
+    if (k < W)
+      X[96 - (l + (uint32_t)(k * G))] = acc[i];
+    else if (l == 0)
+      X[0] = acc[i];  // word 96 (the other lanes made a spare copy)
+  }
+}
+
+// Words k0 .. N - 1 of the lane's list in passes of at most PMAX.
+template <int G, int K0, int N, int PMAX, bool WIDE>
+__device__ __forceinline__ void seed_passes_tab(uint32_t* X, uint32_t l, const SeedLds<WIDE>& tab, uint32_t a0,
+                                                uint32_t b0, uint32_t c0, uint32_t p0) {
+  constexpr int P = N - K0 < PMAX ? N - K0 : PMAX;
+  seed_words_tab<G, K0, P, WIDE>(X, l, tab, a0, b0, c0, p0);
+  if constexpr (K0 + P < N) seed_passes_tab<G, K0 + P, N, PMAX, WIDE>(X, l, tab, a0, b0, c0, p0);
+}
+
+// seed_group's result with the step tables: lane l of the G-lane group makes
+// words l, l + G, ... and word 96, at most PMAX of them at a time (more
+// overlap the lookups better, fewer need fewer registers).
+template <int G, int PMAX, bool WIDE>
+__device__ __forceinline__ bool seed_group_tab(int32_t seed, uint32_t* X, uint32_t l, const SeedLds<WIDE>& tab) {
+  if (seed < 1 || seed > 900000000) return false;
+  constexpr int N = 96 / G + 1;  // words per lane, word 96 included
+  constexpr int PM = N <= PMAX ? N : (N + (N + PMAX - 1) / PMAX - 1) / ((N + PMAX - 1) / PMAX);  // even passes
+  const uint32_t s1 = (uint32_t)seed - 1u;
+  const uint32_t ij = s1 / 30082u;
+  const uint32_t kl = s1 - 30082u * ij;
+  const uint32_t a0 = kSeedTab.log2[(ij / 177u) % 177u + 2u];
+  const uint32_t b0 = kSeedTab.log2[ij % 177u + 2u];
+  const uint32_t c0 = kSeedTab.log2[(kl / 169u) % 178u + 1u];
+  const uint32_t p0 = kSeedStep.pos[kl % 169u];
+  seed_passes_tab<G, 0, N, PM, WIDE>(X, l, tab, a0, b0, c0, p0);
+  if (l == 0) X[97] = kC0;
   return true;
 }
 

@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void k_jump_grp(uint32_t* __restrict__ states,
                                                   const uint32_t* __restrict__ T) {
   constexpr uint32_t kPerWg = 256 / G;
   __shared__ uint32_t lds[kPerWg * kGroupStride];
+  __shared__ SeedLds<true> seed_tab;
   const uint32_t q = threadIdx.x / G, l = threadIdx.x % G;
   const uint64_t r = (uint64_t)blockIdx.x * kPerWg + q;
   const bool active = r < n;
@@ -87,7 +88,9 @@ __global__ __launch_bounds__(256) void k_jump_grp(uint32_t* __restrict__ states,
   bool valid = active;
   uint32_t c = 0;
   if (SEED) {
-    if (active) valid = seed_group<G>(seeds[r], X, l);
+    seed_lds_fill(seed_tab, threadIdx.x, 256);
+    __syncthreads();  // every thread of the workgroup reaches it
+    if (active) valid = seed_group_tab<G, 7, true>(seeds[r], X, l, seed_tab);
     wave_sync();
     c = X[97];
   } else if (active) {
