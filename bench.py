@@ -87,7 +87,7 @@ def _parse():
     ap.add_argument("--serve-requests", type=int, default=synth.SERVE["requests"])
     ap.add_argument("--serve-qps", type=float, default=2e4,
                     help="--workload serve: offered load (requests/s) of the light-load comparison")
-    ap.add_argument("--serve-lanes", type=int, default=4, help="HIP streams of the server, both arms")
+    ap.add_argument("--serve-lanes", type=int, default=8, help="HIP streams of the server, both arms")
     ap.add_argument("--serve-capacity-only", action="store_true",
                     help="--workload serve: only the batched arm at capacity (for profiling)")
     ap.add_argument("--jump", default="family", choices=["family", "lanes"],
@@ -895,7 +895,7 @@ def main():
             "warmup": a.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": res["dtype"], "data": "synthetic", "config": res["config"],
             "roofline": res["roofline"]}
-    for k in ("breakdown_ms", "output_write_GBps", "output_write_frac"):
+    for k in ("breakdown_ms", "output_write_GBps", "output_write_frac", "jump_only_launch_ms"):
         if k in res:
             line[k] = res[k]
     if a.workload == "bulk1m":

@@ -368,7 +368,9 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   // Slice table: per bin, its slices with draws, then its share of the
   // requests without draws (an equal split, in order).
   const bool octets = b->B.wtab20 != nullptr && bv != BATCH_PAIRS;
-  const uint32_t wpb_max = std::max<uint32_t>(1, b->workers_max / nb);
+  const uint32_t grid_cap = bv == BATCH_HALF_GRID ? b->workers_max / 2 : bv == BATCH_QUARTER_GRID ? b->workers_max / 4
+                                                                                                   : b->workers_max;
+  const uint32_t wpb_max = std::max<uint32_t>(1, grid_cap / nb);
   // Jump items per dequeue: enough that each of the bin's workgroups takes
   // about two, at most 8 (16 coarse), or one each (fine).
   auto per_item = [&](uint32_t jobs) -> uint32_t {

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <iterator>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <vector>
@@ -259,19 +260,68 @@ static double time_batch(ranmar_batch* b, const TuneBatch& tb, hipEvent_t e0, hi
   return sum / reps;
 }
 
+// Two prepared launches, of b1 on st and of b2 on st2, started together and
+// timed to the end of both: half of that is the time per batch when a
+// server's launches overlap on several streams.  Best of `rounds`, each
+// after the untimed first; ms per batch.
+static double time_batch_pair(ranmar_batch* b1, ranmar_batch* b2, const TuneBatch& t1, const TuneBatch& t2,
+                              hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipStream_t st, hipStream_t st2,
+                              int reps) {
+  double sum = 0;
+  for (int r = -1; r < reps; ++r) {
+    if (ranmar_batch_prepare(b1, t1.reqs.data(), t1.reqs.size()) != RANMAR_OK ||
+        ranmar_batch_prepare(b2, t2.reqs.data(), t2.reqs.size()) != RANMAR_OK)
+      return -1;
+    if (hipEventRecord(e0, st) != hipSuccess || hipStreamWaitEvent(st2, e0, 0) != hipSuccess) return -1;
+    if (ranmar_batch_launch(b1, st) != RANMAR_OK || ranmar_batch_launch(b2, st2) != RANMAR_OK) return -1;
+    if (hipEventRecord(e2, st2) != hipSuccess || hipStreamWaitEvent(st, e2, 0) != hipSuccess) return -1;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (r >= 0) sum += ms / 2;
+  }
+  return sum / reps;
+}
+
+// A second stream and event for the overlapped timing (default priority).
+struct PairTiming {
+  hipStream_t st2 = nullptr;
+  hipEvent_t e2 = nullptr;
+  bool ok = false;
+  PairTiming() {
+    ok = hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e2) == hipSuccess;
+  }
+  ~PairTiming() {
+    if (st2) hipStreamSynchronize(st2);
+    if (e2) hipEventDestroy(e2);
+    if (st2) hipStreamDestroy(st2);
+  }
+};
+
 static bool batch_shape_ok(uint64_t n, uint64_t count) {
   return n >= 1 && n <= (1ull << 22) && count <= (1ull << 24) && n * count <= (1ull << 31);
 }
 
-// Times the batch executor's mappings on one batch of the given shape.
+// Times the batch executor's mappings on a batch of the given shape.  A
+// batch with draws (a server's launch) is timed as two launches overlapping
+// on two streams, as a server's launches do; jumps only, alone.
 static int tune_batch(uint64_t n, uint64_t count, double* ms_out, hipStream_t st) {
   if (!batch_shape_ok(n, count)) return RANMAR_EINVAL;
+  const bool pair = count > 0;
   TuneBatch tb(n, count);
   if (!tb.ok) return RANMAR_ENOMEM;
+  std::unique_ptr<TuneBatch> tb2(pair ? new TuneBatch(n, count) : nullptr);
+  if (pair && !tb2->ok) return RANMAR_ENOMEM;
+  PairTiming pt;
+  if (!pt.ok) return RANMAR_EHIP;
   const uint32_t L = chunk_draws_default(16384);
-  ranmar_batch* b = nullptr;
+  ranmar_batch *b = nullptr, *b2 = nullptr;
   int rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b);
   if (rc) return rc;
+  if (pair && (rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b2)) != RANMAR_OK) {
+    ranmar_batch_destroy(b);
+    return rc;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<double> best(BATCH_NUM_VARIANTS, 1e30);
   rc = RANMAR_EHIP;
@@ -280,7 +330,9 @@ static int tune_batch(uint64_t n, uint64_t count, double* ms_out, hipStream_t st
     for (int rd = 0; rd < 2 && rc == RANMAR_OK; ++rd)
       for (int v = 0; v < BATCH_NUM_VARIANTS; ++v) {
         batch_set_variant(b, v);
-        const double ms = time_batch(b, tb, e0, e1, st, 2);
+        batch_set_variant(b2, v);
+        const double ms = pair ? time_batch_pair(b, b2, tb, *tb2, e0, e1, pt.e2, st, pt.st2, 2)
+                               : time_batch(b, tb, e0, e1, st, 2);
         if (ms < 0) {
           rc = RANMAR_EHIP;
           break;
@@ -291,6 +343,7 @@ static int tune_batch(uint64_t n, uint64_t count, double* ms_out, hipStream_t st
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
   ranmar_batch_destroy(b);
+  if (b2) ranmar_batch_destroy(b2);
   if (rc) return rc;
   int bv = 0;
   for (int v = 0; v < BATCH_NUM_VARIANTS; ++v) {
@@ -302,8 +355,9 @@ static int tune_batch(uint64_t n, uint64_t count, double* ms_out, hipStream_t st
   return bv;
 }
 
-// Times the chunk lengths: one batch executor per length, each running the
-// same batch with its own tuned (or default) mapping.
+// Times the chunk lengths: batch executors of each length, each running the
+// batch with its tuned (or default) mapping, two launches overlapping on two
+// streams as a server's do.
 static int tune_chunk(uint64_t n, uint64_t count, double* ms_out, hipStream_t st) {
   if (!batch_shape_ok(n, count) || count == 0) return RANMAR_EINVAL;
   TuneBatch tb(n, count);
@@ -314,15 +368,23 @@ static int tune_chunk(uint64_t n, uint64_t count, double* ms_out, hipStream_t st
     return RANMAR_EHIP;
   }
   std::vector<double> best(kChunkVariants, 1e30);
-  int rc = RANMAR_OK;
+  TuneBatch tb2(n, count);
+  PairTiming pt;
+  int rc = (tb2.ok && pt.ok) ? RANMAR_OK : RANMAR_ENOMEM;
   for (int rd = 0; rd < 2 && rc == RANMAR_OK; ++rd)
     for (int v = 0; v < kChunkVariants && rc == RANMAR_OK; ++v) {
       const uint32_t L = chunk_variant_draws(v);
-      ranmar_batch* b = nullptr;
+      ranmar_batch *b = nullptr, *b2 = nullptr;
       rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b);
       if (rc) break;
-      const double ms = time_batch(b, tb, e0, e1, st, 2);
+      rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b2);
+      if (rc) {
+        ranmar_batch_destroy(b);
+        break;
+      }
+      const double ms = time_batch_pair(b, b2, tb, tb2, e0, e1, pt.e2, st, pt.st2, 2);
       ranmar_batch_destroy(b);
+      ranmar_batch_destroy(b2);
       if (ms < 0) rc = RANMAR_EHIP;
       else best[v] = std::min(best[v], ms);
     }
@@ -366,8 +428,9 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_RADIX) return "radix256_valu";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM) return "product_mfma_i8";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM32) return "product_mfma32_i8";
-  static const char* const kBatchNames[BATCH_NUM_VARIANTS] = {"bins64_auto", "bins64_fine", "bins64_coarse",
-                                                               "bins16_auto", "bins16_fine", "bins64_pairs"};
+  static const char* const kBatchNames[BATCH_NUM_VARIANTS] = {"bins64_auto", "bins64_fine",    "bins64_coarse",
+                                                               "bins16_auto", "bins16_fine",    "bins64_pairs",
+                                                               "half_grid",   "quarter_grid"};
   if (kernel == RANMAR_K_BATCH && variant >= 0 && variant < BATCH_NUM_VARIANTS) return kBatchNames[variant];
   static const char* const kChunkNames[kChunkVariants] = {"chunk4096", "chunk8192", "chunk16384", "chunk32768"};
   if (kernel == RANMAR_K_CHUNK && variant >= 0 && variant < kChunkVariants) return kChunkNames[variant];

@@ -378,7 +378,7 @@ def test_batch_large_prepare_in_parts(orc):
 
 
 # --- tuner over the batch executor --------------------------------------------
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(8))
 def test_batch_every_mapping_bit_identical(orc, variant):
     """Every mapping the batch tuner can pick (bins, jump items per dequeue,
     8- or 32-lane jumps for requests without draws) on one batch that mixes
@@ -439,11 +439,11 @@ def test_batch_and_chunk_tuners_pick_a_variant():
     a given shape and records a pick that later batches use."""
     try:
         best, ms = R.ranmar_tune_run(R.RANMAR_K_BATCH, 4096, 0)
-        assert 0 <= best < 6 and np.all(np.asarray(ms) > 0)
+        assert 0 <= best < 8 and len(ms) == 8 and np.all(np.asarray(ms) > 0)
         best_c, ms_c = R.ranmar_tune_run(R.RANMAR_K_CHUNK, 64, 100_000)
         assert 0 <= best_c < 4 and np.all(np.asarray(ms_c) > 0)
         best_b2, _ = R.ranmar_tune_run(R.RANMAR_K_BATCH, 64, 100_000)
-        assert 0 <= best_b2 < 6
+        assert 0 <= best_b2 < 8
     finally:  # later tests get the built-in defaults again
         R.ranmar_tune_clear(R.RANMAR_K_BATCH)
         R.ranmar_tune_clear(R.RANMAR_K_CHUNK)
