@@ -819,11 +819,11 @@ def autotune(R, workload, extras):
     if workload == "jumps1m" or extras:
         shapes.append((R.RANMAR_K_JUMP, synth.BATCH_JUMPS["requests"], 120))
     if extras or workload == "serve":
-        # The batch executor: the jump-only batch of the 10^6-request workload,
-        # and a serving tick at capacity (about 160 requests of the mean count,
-        # 8.7e5 draws): chunk length first, then the mapping for it.
+        # The batch executor's mapping: for the jump-only batch of the
+        # 10^6-request workload, and for a serving launch at capacity (about
+        # 160 requests of the mean count, 8.7e5 draws; the server's chunks of
+        # 8,192 draws).
         shapes += [(R.RANMAR_K_BATCH, synth.BATCH_JUMPS["requests"], 0),
-                   (R.RANMAR_K_CHUNK, SERVE_TICK[0], SERVE_TICK[1]),
                    (R.RANMAR_K_BATCH, SERVE_TICK[0], SERVE_TICK[1])]
     names = {R.RANMAR_K_GENERATE: "generate", R.RANMAR_K_JUMP: "jump", R.RANMAR_K_FAMILY: "family",
              R.RANMAR_K_BATCH: "batch", R.RANMAR_K_CHUNK: "chunk"}

@@ -271,9 +271,11 @@ int ranmar_batch_destroy(ranmar_batch *b);
 
 typedef struct ranmar_serve_cfg {
     uint64_t max_inflight;   /* requests admitted but not released (0 = 65536) */
-    uint64_t chunk_draws;    /* draws per chunk (0 = the RANMAR_K_CHUNK tuner's
-                                pick, else 8192) */
-    uint64_t max_tick_chunks;/* chunks per launch (0 = 16384) */
+    uint64_t chunk_draws;    /* draws per chunk (0 = 8192; longer chunks serve
+                                more at capacity, shorter ones give large
+                                requests more lanes at light load) */
+    uint64_t max_tick_chunks;/* chunks per launch (0: 2^27 draws' worth, at
+                                least 1024; 16384 chunks of 8192) */
     uint32_t lanes;          /* concurrent HIP streams for ticks (1..8, 0 = 2) */
     uint32_t queue_when_full;/* 1: over-budget requests wait; 0: EAGAIN */
     uint32_t unbatched;      /* 1: no batching -- each request is one launch of
@@ -420,9 +422,8 @@ typedef enum ranmar_kernel {
                              requests without draws.  Shape: n requests of
                              `count` draws each (0: jumps only). */
     RANMAR_K_CHUNK = 4    /* draws per chunk of the batch executor (4096 <<
-                             variant), taken by ranmar_batch_create and
-                             ranmar_serve_create when they are given 0.  Same
-                             shape as RANMAR_K_BATCH. */
+                             variant), taken by ranmar_batch_create when it is
+                             given 0.  Same shape as RANMAR_K_BATCH. */
 } ranmar_kernel;
 
 /* Number of variants of a kernel, and a short name for each. */

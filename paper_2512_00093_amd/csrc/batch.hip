@@ -2,14 +2,18 @@
 //
 // ranmar_batch_prepare cuts the requests into slices and chunks, spreads them
 // over up to 64 bins of about equal work (one jump counted as one chunk) and
-// writes the header, bin, slice and chunk tables to a pinned host staging
+// writes the header, bin, chunk and slice tables to a pinned host staging
 // buffer.  A request that straddles two bins is split at a chunk boundary; the
 // second part is a request of its own (offset + first draw), so the draws are
 // unchanged.  ranmar_batch_launch is one launch of a captured graph
 //     [memcpy staging -> device tables]  ->  [persistent kernel]
 // whose memcpy size and grid are set per launch (the grid: as many workgroups
 // per bin as the bin has items, up to what the device holds at once).  The
-// copy also zeroes the bins' queue counters.
+// copy takes the header, the bins (zeroing their queue counters), the chunks
+// and the slices with draws; the slices without draws (jumps only: 48 bytes
+// per request, most of a large batch of jumps) stay in the staging buffer,
+// which is coherent host memory mapped for the device, and the kernel reads
+// each as it takes it, while other waves compute.
 //
 // ranmar_run_unbatched: the same kernel launched once per request with the
 // request passed by value (no tables, no graph): the baseline the batched path
@@ -30,8 +34,10 @@
 
 namespace ranmar {
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tables(uint8_t* desc, BatchBuffers B) {
-  batch_persistent(TableDesc{desc}, B);
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tables(uint8_t* desc,
+                                                                                             const uint8_t* hdesc,
+                                                                                             BatchBuffers B) {
+  batch_persistent(TableDesc{desc, hdesc}, B);
 }
 
 __global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers B) { batch_persistent(d, B); }
@@ -122,9 +128,11 @@ using namespace ranmar;
 struct ranmar_batch {
   uint64_t max_req = 0, max_chunks = 0, max_slices = 0;
   uint32_t L = kDefaultChunk;
-  size_t desc_cap = 0;
+  size_t desc_cap = 0;        // device copy: header, bins, chunks, slices with draws
+  size_t host_cap = 0;        // staging buffer: the same and the slices without draws
   uint8_t* d_desc = nullptr;
   uint8_t* h_desc = nullptr;
+  uint8_t* h_desc_dev = nullptr;  // h_desc as the device addresses it
   uint32_t *d_req_states = nullptr, *d_done = nullptr, *d_queue = nullptr, *d_ptab = nullptr;
   int* h_err = nullptr;
   uint32_t epoch = 0;
@@ -141,14 +149,16 @@ struct ranmar_batch {
   std::vector<BReq> tmp;      // prepare: slices with draws, before the final layout
   bool tried_wtab = false;  // the 20-bit window table was asked for
   uint8_t* kdesc = nullptr;   // kernel argument storage for the graph node
-  void* kargs[2] = {nullptr, nullptr};
+  const uint8_t* khdesc = nullptr;
+  void* kargs[3] = {nullptr, nullptr, nullptr};
   int variant = -1;           // mapping (BatchVariant); -1: the tuner's table
 };
 
 static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned grid) {
   hipKernelNodeParams kp{};
   b->kargs[0] = (void*)&b->kdesc;
-  b->kargs[1] = (void*)&b->B;
+  b->kargs[1] = (void*)&b->khdesc;
+  b->kargs[2] = (void*)&b->B;
   kp.func = (void*)k_batch_tables;
   kp.gridDim = dim3(grid);
   kp.blockDim = dim3(64);
@@ -174,11 +184,12 @@ static void batch_free(ranmar_batch* b) {
   delete b;
 }
 
-// Byte offsets of the slice and chunk tables for n requests in nb bins.
-static uint64_t req_offset(uint32_t nb) { return 64 + sizeof(BBin) * (uint64_t)nb; }
-static uint64_t chunk_offset(uint64_t n, uint32_t nb) {
-  return (req_offset(nb) + sizeof(BReq) * (n + nb) + 15) & ~15ull;
-}
+// Layout of the staging buffer: header, bins, chunk table, the slices with
+// draws (these four are copied to the device before each launch), then the
+// slices without draws, which the kernel reads from the staging buffer itself
+// (a batch of jumps copies only its header and bins).
+static uint64_t chunk_offset(uint32_t nb) { return 64 + sizeof(BBin) * (uint64_t)nb; }
+static uint64_t align16(uint64_t v) { return (v + 15) & ~15ull; }
 
 namespace ranmar {
 void batch_set_variant(ranmar_batch* b, int v) {
@@ -208,12 +219,17 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   b->max_chunks = max_chunks ? max_chunks : 1;
   b->max_slices = b->max_req + kMaxBins;  // each bin boundary splits at most one request
   b->L = chunk_draws ? (uint32_t)chunk_draws : chunk_draws_default(kDefaultChunk);
-  b->desc_cap = chunk_offset(b->max_req, kMaxBins) + sizeof(BChunk) * b->max_chunks;
+  // Slices: each request once, plus at most one extra part per bin boundary.
+  b->desc_cap = align16(chunk_offset(kMaxBins) + sizeof(BChunk) * b->max_chunks) + sizeof(BReq) * b->max_slices;
+  b->host_cap = align16(b->desc_cap) + sizeof(BReq) * b->max_req;
   b->workers_max = std::max<unsigned>(persistent_grid((const void*)k_batch_tables, 64), kMaxBins);
   const uint64_t nflags = b->max_slices + 1;  // slice flags + the spare
   hipStream_t st = nullptr;
+  // The staging buffer is coherent host memory: the kernel reads the slices
+  // without draws from it, and every launch must see what the host wrote last.
   bool ok = hipMalloc(&b->d_desc, b->desc_cap) == hipSuccess &&
-            hipHostMalloc(&b->h_desc, b->desc_cap, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_desc, b->host_cap, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+            hipHostGetDevicePointer((void**)&b->h_desc_dev, b->h_desc, 0) == hipSuccess &&
             hipHostMalloc(&b->h_err, sizeof(int), hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
             hipMalloc(&b->d_req_states, 4 * kWords * b->max_slices) == hipSuccess &&
             hipMalloc(&b->d_done, 4 * nflags) == hipSuccess && hipMalloc(&b->d_queue, 8) == hipSuccess &&
@@ -238,6 +254,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   }
   if (ok) {
     b->kdesc = b->d_desc;
+    b->khdesc = b->h_desc_dev;
     ok = hipGraphCreate(&b->graph, 0) == hipSuccess &&
          hipGraphAddMemcpyNode1D(&b->cpy, b->graph, nullptr, 0, b->d_desc, b->h_desc, b->desc_cap,
                                  hipMemcpyHostToDevice) == hipSuccess;
@@ -307,14 +324,14 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   // Bins: about 4 units of work (jumps + chunks) per bin at least, at most 64.
   const uint64_t cost = n + total;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(max_bins, std::max<uint64_t>(1, cost / 4));
-  const uint64_t req_off = req_offset(nb), chunk_off = chunk_offset(n, nb);
-  // The staging buffer may still be read by the previous run's copy.
+  const uint64_t chunk_off = chunk_offset(nb), req_off = align16(chunk_off + sizeof(BChunk) * total);
+  // The staging buffer may still be read by the previous run's copy and kernel.
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
   BHeader* h = (BHeader*)b->h_desc;
   BBin* bins = (BBin*)(b->h_desc + 64);
-  BReq* sl = (BReq*)(b->h_desc + req_off);
+  BReq* sl = (BReq*)(b->h_desc + req_off);  // slices with draws
   BChunk* ch = (BChunk*)(b->h_desc + chunk_off);
-  std::memset(b->h_desc, 0, req_off);
+  std::memset(b->h_desc, 0, chunk_off);  // header and bins (the bins' queue counters start at 0)
   const uint64_t L = b->L;
 
   // Requests with draws, in order, fill the bins one after the other with
@@ -383,7 +400,11 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   for (uint32_t i = 0; i < nb; ++i) {
     BBin& bn = bins[i];
     bn.s0 = (uint32_t)ns;
-    for (uint32_t k = 0; k < nsc[i]; ++k) sl[ns++] = tmp[ti++];
+    bn.a0 = (uint32_t)ti;
+    bn.na = nsc[i];
+    bn.b0 = (uint32_t)(n_jo * i / nb);
+    for (uint32_t k = 0; k < nsc[i]; ++k, ++ti) sl[ti] = tmp[ti];  // the table holds tmp in order
+    ns += nsc[i];
     ns += n_jo * (i + 1) / nb - n_jo * i / nb;  // filled below
     bn.ns = (uint32_t)(ns - bn.s0);
     bn.nsc = octets ? nsc[i] : bn.ns;  // without the 20-bit table, pair items take every slice
@@ -400,23 +421,19 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     // Workgroups per bin: as many as the fullest bin has items, within the device.
     wpb = std::max(wpb, std::min(wpb_max, bn.n_ju + bn.n_cg + bn.n_qi));
   }
-  // Requests without draws, k-th of them (in order) into bin i with
-  // n_jo i / nb <= k < n_jo (i + 1) / nb, after that bin's other slices.
+  // Requests without draws: the k-th of them (in order) is entry k of their
+  // table and belongs to bin i with n_jo i / nb <= k < n_jo (i + 1) / nb,
+  // after that bin's slices with draws.
+  const uint64_t jo_off = align16(req_off + sizeof(BReq) * ti);
+  BReq* jo = (BReq*)(b->h_desc + jo_off);
   if (n_jo) {
     std::vector<uint64_t> jo_before(parts, 0);
     for (uint32_t t = 1; t < parts; ++t) jo_before[t] = jo_before[t - 1] + p_jo[t - 1];
     parallel_parts(n, parts, [&](uint64_t lo, uint64_t hi, uint32_t t) {
       uint64_t k = jo_before[t];
-      if (k >= n_jo) return;
-      auto start = [&](uint32_t i) { return n_jo * i / nb; };
-      uint32_t i = (uint32_t)std::min<uint64_t>(nb - 1, k * nb / n_jo);
-      while (i > 0 && start(i) > k) --i;
-      while (i + 1 < nb && start(i + 1) <= k) ++i;
-      for (uint64_t r = lo; r < hi; ++r) {
+      for (uint64_t r = lo; r < hi && k < n_jo; ++r) {
         if (reqs[r].count != 0) continue;
-        while (i + 1 < nb && start(i + 1) <= k) ++i;
-        sl[bins[i].s0 + nsc[i] + (k - start(i))] = to_breq(reqs[r]);
-        ++k;
+        jo[k++] = to_breq(reqs[r]);
       }
     });
   }
@@ -426,8 +443,9 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   h->L = b->L;
   h->req_off = req_off;
   h->chunk_off = chunk_off;
+  h->jo_off = jo_off;
   b->grid_prepared = h->n_workers;
-  b->prepared_bytes = chunk_off + sizeof(BChunk) * total;
+  b->prepared_bytes = req_off + sizeof(BReq) * ti;  // the device copy: all but the slices without draws
   return RANMAR_OK;
 }
 

@@ -41,9 +41,10 @@ namespace ranmar {
 
 struct BHeader {        // 64 bytes
   uint32_t n_bins, n_workers, epoch, L;  // n_workers: one-wave workgroups launched
-  uint64_t req_off;     // byte offset of the slice table from the header
-  uint64_t chunk_off;   // byte offset of the chunk table from the header
-  uint64_t pad[4];
+  uint64_t req_off;     // byte offset of the table of slices with draws (copied to the device)
+  uint64_t chunk_off;   // byte offset of the chunk table (copied to the device)
+  uint64_t jo_off;      // byte offset of the table of slices without draws (read from host memory)
+  uint64_t pad[3];
 };
 struct BBin {           // 256 bytes: the counter alone on its line
   uint32_t ctr;         // next item (0 at launch: the descriptor copy resets it)
@@ -52,7 +53,9 @@ struct BBin {           // 256 bytes: the counter alone on its line
   uint32_t g, n_ju;     // jump pairs (slices with draws) per pair item, pair items
   uint32_t n_cg;        // chunk pairs
   uint32_t gq, n_qi;    // jump octets (slices without draws) per octet item, octet items
-  uint32_t pad[53];
+  uint32_t a0, na;      // the bin's slices with draws: entries [a0, a0 + na) of their table
+  uint32_t b0;          // the bin's slices without draws: entries b0 .. of theirs
+  uint32_t pad[50];
 };
 struct BReq {           // 48 bytes
   int32_t seed;
@@ -71,7 +74,7 @@ constexpr uint32_t kMaxBins = 64;
 
 // A bin's ranges, as held in registers (the counter is only touched atomically).
 struct BinInfo {
-  uint32_t s0, ns, nsc, k0, nk, g, n_ju, n_cg, gq, n_qi;
+  uint32_t s0, ns, nsc, k0, nk, g, n_ju, n_cg, gq, n_qi, a0, na, b0;
 };
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // x ~100 cycles per sleep: about 0.2 s
@@ -79,15 +82,20 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // x ~100 cycles per sleep: about 0.2
 // Descriptor access: either tables in device memory, or a single request
 // passed by value (the one-launch-per-request path).
 struct TableDesc {
-  uint8_t* desc;
+  uint8_t* desc;          // device copy: header, bins, chunks, slices with draws
+  const uint8_t* hdesc;   // the host staging buffer as the device sees it (slices without draws)
   __device__ __forceinline__ BHeader header() const { return *(const BHeader*)desc; }
   __device__ __forceinline__ BinInfo bin(uint32_t x) const {
     const BBin* b = (const BBin*)(desc + 64) + x;
-    return BinInfo{b->s0, b->ns, b->nsc, b->k0, b->nk, b->g, b->n_ju, b->n_cg, b->gq, b->n_qi};
+    return BinInfo{b->s0, b->ns, b->nsc, b->k0, b->nk, b->g, b->n_ju, b->n_cg, b->gq, b->n_qi, b->a0, b->na, b->b0};
   }
   __device__ __forceinline__ uint32_t* counter(uint32_t x, uint32_t*) const { return &((BBin*)(desc + 64))[x].ctr; }
-  __device__ __forceinline__ BReq req(const BHeader& h, uint32_t r) const {
-    return ((const BReq*)(desc + h.req_off))[r];
+  // Slice rl of a bin: its slices with draws first (device table), then
+  // those without (read from host memory, where the host wrote them: a
+  // batch of jumps copies no slice table before its launch).
+  __device__ __forceinline__ BReq req(const BHeader& h, const BinInfo& bn, uint32_t rl) const {
+    if (rl < bn.na) return ((const BReq*)(desc + h.req_off))[bn.a0 + rl];
+    return ((const BReq*)(hdesc + h.jo_off))[bn.b0 + (rl - bn.na)];
   }
   __device__ __forceinline__ BChunk chunk(const BHeader& h, uint32_t j) const {
     return ((const BChunk*)(desc + h.chunk_off))[j];
@@ -119,10 +127,13 @@ struct SingleDesc {
     b.n_cg = (uint32_t)((nq + 1) / 2);
     b.gq = 1;
     b.n_qi = 0;
+    b.a0 = 0;
+    b.na = 1;
+    b.b0 = 0;
     return b;
   }
   __device__ __forceinline__ uint32_t* counter(uint32_t, uint32_t* queue) const { return queue; }
-  __device__ __forceinline__ BReq req(const BHeader&, uint32_t) const { return r0; }
+  __device__ __forceinline__ BReq req(const BHeader&, const BinInfo&, uint32_t) const { return r0; }
   __device__ __forceinline__ BChunk chunk(const BHeader& h, uint32_t j) const {
     BChunk c;
     c.req = 0;
@@ -194,7 +205,7 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   uint32_t* X = lds + half * kHalfLds;
   uint32_t* Bp = X + 193;
   BReq q{};
-  if (active) q = D.req(h, r);
+  if (active) q = D.req(h, bn, rl);
   const bool valid = active && seed_group_tab<32, 4, false>(q.seed, X, l, stab);
   if (!valid) X[l] = X[l + 32] = X[l + 64] = X[97] = 0;
   wave_sync();
@@ -248,7 +259,7 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   const uint32_t* P = B.ptab + (uint64_t)ch.q * 97u;
   const uint32_t p0 = P[l], p1 = P[l + 32], p2 = P[l + 64], p3 = P[96];
   if (active) {
-    rq = D.req(h, r);
+    rq = D.req(h, bn, ch.req);
     uint32_t it = 0;
     while (__hip_atomic_load(&B.done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != h.epoch) {
       __builtin_amdgcn_s_sleep(2);
@@ -300,7 +311,7 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
   uint32_t* X = lds + grp * kOctStride;
   uint32_t* Bp = X + 193;
   BReq q{};
-  if (active) q = D.req(h, bn.s0 + rl);
+  if (active) q = D.req(h, bn, rl);
   const bool valid = active && seed_group_tab<8, 4, false>(q.seed, X, l, stab);
   if (!valid) {
 #pragma unroll

@@ -317,9 +317,14 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
   if (cfg) s->cfg = *cfg;
   if (!s->cfg.max_inflight) s->cfg.max_inflight = 65536;
   // 8192: measured lower p50/p99 than 16384 at 2e4 and 5e5 requests/s (more
-  // chunks of a request run at once), at the same throughput.
-  if (!s->cfg.chunk_draws) s->cfg.chunk_draws = ranmar::chunk_draws_default(8192);
-  if (!s->cfg.max_tick_chunks) s->cfg.max_tick_chunks = 16384;
+  // chunks of a request run at once).  Longer chunks can serve more at
+  // capacity (fewer chunk starts) but a large request alone then runs on fewer
+  // lanes, so the server does not take the chunk tuner's pick by itself.
+  if (!s->cfg.chunk_draws) s->cfg.chunk_draws = 8192;
+  // A launch carries about 2^27 draws (16,384 chunks of 8,192) whatever the
+  // chunk length, so that longer chunks make fewer chunks, not larger launches.
+  if (!s->cfg.max_tick_chunks)
+    s->cfg.max_tick_chunks = std::max<uint64_t>(1024, (16384ull * 8192ull) / std::max<uint64_t>(1, s->cfg.chunk_draws));
   if (!s->cfg.lanes) s->cfg.lanes = 2;
   if (s->cfg.lanes > 8 || s->cfg.chunk_draws > (1u << 24) || s->cfg.max_tick_chunks > (1u << 22)) {
     delete s;

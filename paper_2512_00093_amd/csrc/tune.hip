@@ -314,7 +314,7 @@ static int tune_batch(uint64_t n, uint64_t count, double* ms_out, hipStream_t st
   if (pair && !tb2->ok) return RANMAR_ENOMEM;
   PairTiming pt;
   if (!pt.ok) return RANMAR_EHIP;
-  const uint32_t L = chunk_draws_default(16384);
+  const uint32_t L = 8192;  // the server's chunk length (the mapping hardly depends on it)
   ranmar_batch *b = nullptr, *b2 = nullptr;
   int rc = ranmar_batch_create(n, n * ((count + L - 1) / L) + 1, L, &b);
   if (rc) return rc;
