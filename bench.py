@@ -47,11 +47,32 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_digest():
-    """Digest of the kernel sources (library and public header)."""
+def _include_closure(src):
+    """`src` (a file of the kernel sources) and every header it includes,
+    directly or not, by quoted #include."""
+    seen, todo = [], [os.path.normpath(os.path.join(ROOT, "paper_2512_00093_amd", "csrc", src))]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.append(f)
+        with open(f) as fh:
+            for line in fh:
+                m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+                if m:
+                    todo.append(os.path.normpath(os.path.join(os.path.dirname(f), m.group(1))))
+    return sorted(seen)
+
+
+def source_digest(src=None):
+    """Digest of the kernel sources: of `src` and the headers it includes, or
+    of every source file and the public header."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2512_00093_amd", "csrc", "*"))) + \
-        sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
+    if src:
+        files = _include_closure(src)
+    else:
+        files = sorted(glob.glob(os.path.join(ROOT, "paper_2512_00093_amd", "csrc", "*"))) + \
+            sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -59,11 +80,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel, grid):
+def profiled_traffic(kernel, grid, src):
     """HBM bytes (fetched + written) per dispatch of `kernel` at `grid` threads
     from the committed rocprofv3 counter summaries, or None when no summary was
-    taken from the current kernel sources."""
-    digest = source_digest()
+    taken from the current sources of that kernel (`src` and its includes)."""
+    digest = source_digest(src)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
         with open(path) as fh:
             text = fh.read()
@@ -363,7 +384,7 @@ def run_family65k(R, torch, steps, warmup, jump_mode):
         "roofline": {"bound": "hbm", "kernel": "k_gen32<f32>", "achieved": gen_bytes / (gen_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gen_bytes / (gen_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_gen32<1, true>", n // 8 * 256),
+                     "traffic": profiled_traffic("k_gen32<1, true>", n // 8 * 256, "generate.hip"),
                      "bytes_per_launch": gen_bytes, "launch_ms": gen_ms},
     }
     return res
@@ -401,7 +422,7 @@ def run_bulk1m(R, torch, steps, warmup):
         "output_write_frac": 4 * draws / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "k_gen32_wide<f32>", "achieved": algo / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_gen32_wide<1, true>", n // 8 * 256),
+                     "traffic": profiled_traffic("k_gen32_wide<1, true>", n // 8 * 256, "generate.hip"),
                      "bytes_per_launch": algo, "launch_ms": ms},
     }
 
@@ -503,7 +524,7 @@ def run_lfg_gen(R, torch, steps, warmup):
                    "draws": count},
         "roofline": {"bound": "hbm", "kernel": "k_lfg_gen<0, 4>", "achieved": algo / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_lfg_gen<0, 4>", n // 4 * 4 * lanes),
+                     "traffic": profiled_traffic("k_lfg_gen<0, 4>", n // 4 * 4 * lanes, "lfg.hip"),
                      "bytes_per_launch": algo, "launch_ms": ms},
     }
 
