@@ -234,6 +234,19 @@ def cpu_single_thread():
         for k in range(calls):
             fn(12345 + k, n)
         t[name] = n * calls / (time.perf_counter() - t0)
+    # The single-stream workload (seed 12345, 10^6 draws, one jump of 2^20
+    # checked against as many single steps): seconds on one core.
+    c1 = synth.SINGLE_STREAM
+    t0 = time.perf_counter()
+    st = O.state_from_seed(c1["seed"])
+    O.state_draws(st, c1["draws"])
+    t_draws = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.jump(st, c1["jump"])
+    t_jump = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.step(st, c1["jump"])
+    t_step = time.perf_counter() - t0
     jumps = {}
     for J in synth.PAPER_TABLE2["jumps"]:
         O.xpow(J)
@@ -245,6 +258,7 @@ def cpu_single_thread():
             "table1_integer_over_real": t["alg2_integer"] / t["alg1_real"],
             "table1_sample": f"{n * calls:.0e} draws (ten streams of 1e7)",
             "table2_us": jumps,
+            "single_stream_s": {"seed_and_1e6_draws": t_draws, "jump_2^20": t_jump, "2^20_single_steps": t_step},
             "paper_table1_s_1e9": {"real": {"apple": 3.30, "arm": 16.60, "ryzen": 8.45, "intel": 3.31},
                                    "integer": {"apple": 1.27, "arm": 6.14, "ryzen": 2.07, "intel": 1.01}},
             "paper_table2_us_ntl": {"J=2^64-1": [946, 10395], "J=2^120-1": [1946, 21411]}}
@@ -959,7 +973,7 @@ def main():
         if extras:
             line["cpu_baseline"]["single_thread"] = cpu_single_thread()
     if extras and not a.no_cpu:
-        for name in ("family65k", "lfg_gen", "lfg_jumps", "lfg_family"):
+        for name in ("family65k", "jumps1m", "lfg_gen", "lfg_jumps", "lfg_family"):
             cb = cpu_baseline(name, min(a.cpu_seconds, 3.0))
             line["also"][name]["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "sample")}
     print(json.dumps(_c(line)), flush=True)

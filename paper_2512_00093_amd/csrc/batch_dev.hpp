@@ -312,7 +312,7 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
   uint32_t* Bp = X + 193;
   BReq q{};
   if (active) q = D.req(h, bn, rl);
-  const bool valid = active && seed_group_tab<8, 4, false>(q.seed, X, l, stab);
+  const bool valid = active && seed_group_tab<8, 5, false>(q.seed, X, l, stab);
   if (!valid) {
 #pragma unroll
     for (int k = 0; k < 96; k += 8) X[l + k] = 0;
