@@ -7,10 +7,10 @@
 // second part is a request of its own (offset + first draw), so the draws are
 // unchanged.  ranmar_batch_launch is one launch of a captured graph
 //     [memcpy staging -> device tables]  ->  [persistent kernel]
-// whose memcpy size and grid are set per launch (the grid: as many workgroups
-// per bin as the bin has items, up to what the device holds at once).  The
+// whose memcpy size and grid are set per launch (the grid: as many one-wave
+// workers per bin as the bin has items, up to what the device holds at once).  The
 // copy takes the header, the bins (zeroing their queue counters), the chunks
-// and the slices with draws; the slices without draws (jumps only: 48 bytes
+// and the slices with draws; the slices without draws (jumps only: 32 bytes
 // per request, most of a large batch of jumps) stay in the staging buffer,
 // which is coherent host memory mapped for the device, and the kernel reads
 // each as it takes it, while other waves compute.
@@ -34,13 +34,18 @@
 
 namespace ranmar {
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tables(uint8_t* desc,
-                                                                                             const uint8_t* hdesc,
-                                                                                             BatchBuffers B) {
-  batch_persistent(TableDesc{desc, hdesc}, B);
+// Four one-wave workers per workgroup: one copy of the seeding table per four
+// waves keeps the LDS of 16 waves within a CU's 160 KB.
+constexpr uint32_t kBatchWpg = 4;
+
+__global__ __launch_bounds__(64 * kBatchWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tables(
+    uint8_t* desc, const uint8_t* hdesc, BatchBuffers B, DirectJumps dj) {
+  batch_persistent<kBatchWpg>(TableDesc{desc, hdesc}, B, dj);
 }
 
-__global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers B) { batch_persistent(d, B); }
+__global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers B) {
+  batch_persistent<1>(d, B, DirectJumps{nullptr, 0u, 0u});
+}
 
 constexpr uint32_t kDefaultChunk = 16384;
 constexpr uint32_t kMaxChunkDraws = 1u << 24;
@@ -109,6 +114,15 @@ static uint32_t host_parts(uint64_t n) {
   return std::max(1u, std::min(8u, hw ? hw : 1u));
 }
 
+static BJump to_bjump(const ranmar_request& q) {
+  BJump b{};
+  b.seed = q.seed;
+  b.off_lo = q.offset.lo;
+  b.off_hi = q.offset.hi;
+  b.state = (uint64_t)(uintptr_t)q.d_state;
+  return b;
+}
+
 static BReq to_breq(const ranmar_request& q) {
   BReq b{};
   b.seed = q.seed;
@@ -136,11 +150,17 @@ struct ranmar_batch {
   uint32_t *d_req_states = nullptr, *d_done = nullptr, *d_queue = nullptr, *d_ptab = nullptr;
   int* h_err = nullptr;
   uint32_t epoch = 0;
-  unsigned workers_max = 0;   // one-wave workgroups the device holds at once
-  unsigned grid_node = 0;     // workgroups of the graph's kernel node now
-  unsigned grid_prepared = 0; // workgroups for the prepared tables
+  unsigned workers_max = 0;   // one-wave workers the device holds at once (kBatchWpg per workgroup)
+  unsigned grid_node = 0;     // workers of the graph's kernel node now
+  unsigned grid_dnode = 0;    // the same for the direct graph (0: its arguments must be set)
+  unsigned grid_prepared = 0; // workers for the prepared tables
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // A batch of jumps only under the direct mapping reads no descriptor: it is
+  // launched from a second graph that holds the kernel node alone.
+  hipGraph_t graph_d = nullptr;
+  hipGraphExec_t exec_d = nullptr;
+  hipGraphNode_t kern_d = nullptr;
   hipGraphNode_t cpy = nullptr, kern = nullptr;
   hipEvent_t last = nullptr;
   bool launched = false;
@@ -150,18 +170,22 @@ struct ranmar_batch {
   bool tried_wtab = false;  // the 20-bit window table was asked for
   uint8_t* kdesc = nullptr;   // kernel argument storage for the graph node
   const uint8_t* khdesc = nullptr;
-  void* kargs[3] = {nullptr, nullptr, nullptr};
+  DirectJumps kdirect{nullptr, 0u, 0u};      // kernel argument storage (copied when a node's arguments are set)
+  DirectJumps kdirect_d{nullptr, 0u, 0u};    // the direct graph's node now
+  DirectJumps dj_prepared{nullptr, 0u, 0u};  // the prepared batch's (n = 0: not direct)
+  void* kargs[4] = {nullptr, nullptr, nullptr, nullptr};
   int variant = -1;           // mapping (BatchVariant); -1: the tuner's table
 };
 
-static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned grid) {
+static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned workers) {
   hipKernelNodeParams kp{};
   b->kargs[0] = (void*)&b->kdesc;
   b->kargs[1] = (void*)&b->khdesc;
   b->kargs[2] = (void*)&b->B;
+  b->kargs[3] = (void*)&b->kdirect;
   kp.func = (void*)k_batch_tables;
-  kp.gridDim = dim3(grid);
-  kp.blockDim = dim3(64);
+  kp.gridDim = dim3((workers + kBatchWpg - 1) / kBatchWpg);
+  kp.blockDim = dim3(64 * kBatchWpg);
   kp.sharedMemBytes = 0;
   kp.kernelParams = b->kargs;
   kp.extra = nullptr;
@@ -173,6 +197,8 @@ static void batch_free(ranmar_batch* b) {
   if (b->last) hipEventSynchronize(b->last);
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec_d) hipGraphExecDestroy(b->exec_d);
+  if (b->graph_d) hipGraphDestroy(b->graph_d);
   if (b->last) hipEventDestroy(b->last);
   hipFree(b->d_desc);
   hipFree(b->d_req_states);
@@ -202,7 +228,7 @@ void batch_use_wide_windows(ranmar_batch* b) {
   const uint32_t* T = window20_table();
   if (T && b->B.wtab20 != T) {
     b->B.wtab20 = T;
-    b->grid_node = 0;  // the kernel node takes the pointer at the next launch
+    b->grid_node = b->grid_dnode = 0;  // the kernel nodes take the pointer at the next launch
   }
 }
 }  // namespace ranmar
@@ -221,8 +247,9 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
   b->L = chunk_draws ? (uint32_t)chunk_draws : chunk_draws_default(kDefaultChunk);
   // Slices: each request once, plus at most one extra part per bin boundary.
   b->desc_cap = align16(chunk_offset(kMaxBins) + sizeof(BChunk) * b->max_chunks) + sizeof(BReq) * b->max_slices;
-  b->host_cap = align16(b->desc_cap) + sizeof(BReq) * b->max_req;
-  b->workers_max = std::max<unsigned>(persistent_grid((const void*)k_batch_tables, 64), kMaxBins);
+  b->host_cap = align16(b->desc_cap) + sizeof(BJump) * b->max_req;
+  b->workers_max =
+      std::max<unsigned>(kBatchWpg * persistent_grid((const void*)k_batch_tables, 64 * kBatchWpg), kMaxBins);
   const uint64_t nflags = b->max_slices + 1;  // slice flags + the spare
   hipStream_t st = nullptr;
   // The staging buffer is coherent host memory: the kernel reads the slices
@@ -259,11 +286,15 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
          hipGraphAddMemcpyNode1D(&b->cpy, b->graph, nullptr, 0, b->d_desc, b->h_desc, b->desc_cap,
                                  hipMemcpyHostToDevice) == hipSuccess;
     if (ok) {
-      const unsigned grid = b->workers_max;
+      const unsigned grid = b->workers_max;  // workers
       const hipKernelNodeParams kp = kernel_params(b, grid);
       ok = hipGraphAddKernelNode(&b->kern, b->graph, &b->cpy, 1, &kp) == hipSuccess &&
-           hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+           hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess &&
+           hipGraphCreate(&b->graph_d, 0) == hipSuccess &&
+           hipGraphAddKernelNode(&b->kern_d, b->graph_d, nullptr, 0, &kp) == hipSuccess &&
+           hipGraphInstantiate(&b->exec_d, b->graph_d, nullptr, nullptr, 0) == hipSuccess;
       b->grid_node = grid;
+      b->grid_dnode = 0;
     }
   }
   if (!ok) {
@@ -310,8 +341,6 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   // The mapping: forced on this batch (the tuner), else the tuned table's
   // pick for this shape.
   const int bv = b->variant >= 0 ? b->variant : batch_variant_for(n, draws / n);
-  const bool fine = bv == BATCH_FINE || bv == BATCH_BINS16_FINE;
-  const uint32_t max_bins = (bv == BATCH_BINS16 || bv == BATCH_BINS16_FINE) ? 16u : kMaxBins;
   if (total > b->max_chunks) return RANMAR_ENOMEM;
   // Many requests without draws: jump them with 20-bit windows (the 2.4 GB
   // table is built once per device, on first use; if it cannot be, the 8-bit
@@ -319,8 +348,13 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   if (n_jo >= 16384 && !b->B.wtab20 && !b->tried_wtab) {
     b->tried_wtab = true;
     b->B.wtab20 = window20_table();
-    b->grid_node = 0;  // forces the kernel node's arguments to be set again
+    b->grid_node = b->grid_dnode = 0;  // forces the kernel nodes' arguments to be set again
   }
+  // The direct mapping applies to batches of jumps only, as octets (else the
+  // default mapping serves): one bin, and a grid of one worker per octet.
+  const bool direct = bv == BATCH_DIRECT && n_jo == n && b->B.wtab20 != nullptr;
+  const bool fine = bv == BATCH_FINE || bv == BATCH_BINS16_FINE || direct;
+  const uint32_t max_bins = direct ? 1u : (bv == BATCH_BINS16 || bv == BATCH_BINS16_FINE) ? 16u : kMaxBins;
   // Bins: about 4 units of work (jumps + chunks) per bin at least, at most 64.
   const uint64_t cost = n + total;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(max_bins, std::max<uint64_t>(1, cost / 4));
@@ -388,7 +422,7 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   const uint32_t grid_cap = bv == BATCH_HALF_GRID ? b->workers_max / 2 : bv == BATCH_QUARTER_GRID ? b->workers_max / 4
                                                                                                    : b->workers_max;
   const uint32_t wpb_max = std::max<uint32_t>(1, grid_cap / nb);
-  // Jump items per dequeue: enough that each of the bin's workgroups takes
+  // Jump items per dequeue: enough that each of the bin's workers takes
   // about two, at most 8 (16 coarse), or one each (fine).
   auto per_item = [&](uint32_t jobs) -> uint32_t {
     if (fine) return 1u;
@@ -425,7 +459,7 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   // table and belongs to bin i with n_jo i / nb <= k < n_jo (i + 1) / nb,
   // after that bin's slices with draws.
   const uint64_t jo_off = align16(req_off + sizeof(BReq) * ti);
-  BReq* jo = (BReq*)(b->h_desc + jo_off);
+  BJump* jo = (BJump*)(b->h_desc + jo_off);
   if (n_jo) {
     std::vector<uint64_t> jo_before(parts, 0);
     for (uint32_t t = 1; t < parts; ++t) jo_before[t] = jo_before[t - 1] + p_jo[t - 1];
@@ -433,12 +467,13 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
       uint64_t k = jo_before[t];
       for (uint64_t r = lo; r < hi && k < n_jo; ++r) {
         if (reqs[r].count != 0) continue;
-        jo[k++] = to_breq(reqs[r]);
+        jo[k++] = to_bjump(reqs[r]);
       }
     });
   }
   h->n_bins = nb;
-  h->n_workers = nb * wpb;
+  h->n_workers = direct ? bins[0].n_qi : nb * wpb;
+  b->dj_prepared = direct ? DirectJumps{b->h_desc_dev + jo_off, (uint32_t)n, 0u} : DirectJumps{nullptr, 0u, 0u};
   h->epoch = ++b->epoch;
   h->L = b->L;
   h->req_off = req_off;
@@ -458,15 +493,29 @@ int ranmar_batch_launch(ranmar_batch* b, void* stream) {
   }
   const size_t bytes = b->prepared_bytes;
   b->prepared_bytes = 0;
-  if (hipGraphExecMemcpyNodeSetParams1D(b->exec, b->cpy, b->d_desc, b->h_desc, bytes, hipMemcpyHostToDevice) !=
-      hipSuccess)
-    return RANMAR_EHIP;
-  if (b->grid_prepared != b->grid_node) {
-    const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared);
-    if (hipGraphExecKernelNodeSetParams(b->exec, b->kern, &kp) != hipSuccess) return RANMAR_EHIP;
-    b->grid_node = b->grid_prepared;
+  if (b->dj_prepared.n) {
+    // Direct mapping: the kernel node alone, its arguments set when they change.
+    if (b->grid_prepared != b->grid_dnode || b->dj_prepared.recs != b->kdirect_d.recs ||
+        b->dj_prepared.n != b->kdirect_d.n) {
+      b->kdirect = b->dj_prepared;
+      const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared);
+      if (hipGraphExecKernelNodeSetParams(b->exec_d, b->kern_d, &kp) != hipSuccess) return RANMAR_EHIP;
+      b->kdirect_d = b->dj_prepared;
+      b->grid_dnode = b->grid_prepared;
+    }
+    if (hipGraphLaunch(b->exec_d, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
+  } else {
+    if (hipGraphExecMemcpyNodeSetParams1D(b->exec, b->cpy, b->d_desc, b->h_desc, bytes, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return RANMAR_EHIP;
+    if (b->grid_prepared != b->grid_node) {
+      b->kdirect = DirectJumps{nullptr, 0u, 0u};
+      const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared);
+      if (hipGraphExecKernelNodeSetParams(b->exec, b->kern, &kp) != hipSuccess) return RANMAR_EHIP;
+      b->grid_node = b->grid_prepared;
+    }
+    if (hipGraphLaunch(b->exec, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
   }
-  if (hipGraphLaunch(b->exec, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
   if (hipEventRecord(b->last, (hipStream_t)stream) != hipSuccess) return RANMAR_EHIP;
   b->launched = true;
   return RANMAR_OK;

@@ -43,7 +43,7 @@ struct BHeader {        // 64 bytes
   uint32_t n_bins, n_workers, epoch, L;  // n_workers: one-wave workgroups launched
   uint64_t req_off;     // byte offset of the table of slices with draws (copied to the device)
   uint64_t chunk_off;   // byte offset of the chunk table (copied to the device)
-  uint64_t jo_off;      // byte offset of the table of slices without draws (read from host memory)
+  uint64_t jo_off;      // byte offset of the table of slices without draws (BJump, read from host memory)
   uint64_t pad[3];
 };
 struct BBin {           // 256 bytes: the counter alone on its line
@@ -65,10 +65,31 @@ struct BReq {           // 48 bytes
   uint64_t out;
   uint64_t state;
 };
+struct BJump {          // 32 bytes: a slice without draws (no format, count or output)
+  int32_t seed;
+  uint32_t pad;
+  uint64_t off_lo, off_hi;
+  uint64_t state;
+};
+// The nv (<= 8) consecutive BJump records at `recs` as the whole wave reads
+// them at once: lane 2i holds bytes 0..15 of record i and lane 2i + 1 bytes
+// 16..31 (zeros past nv).  One coalesced read of host memory per octet
+// instead of one per field and lane.
+__device__ __forceinline__ uint4 octet_load(const uint8_t* recs, uint32_t nv, uint32_t lane) {
+  return lane < 2u * nv ? ((const uint4*)recs)[lane] : make_uint4(0u, 0u, 0u, 0u);
+}
+// A batch of jumps only under the direct mapping (n = 0 otherwise): worker w
+// takes requests 8w .. 8w + 7, with no bins and no queue.
+struct DirectJumps {
+  const uint8_t* recs;  // its BJump records, as the device addresses them
+  uint32_t n;           // requests
+  uint32_t pad;
+};
 struct BChunk {         // 16 bytes
   uint32_t req, q, draws, last;  // slice (index within its bin), chunk index in the slice, draws, last of the slice
 };
-static_assert(sizeof(BHeader) == 64 && sizeof(BBin) == 256 && sizeof(BReq) == 48 && sizeof(BChunk) == 16,
+static_assert(sizeof(BHeader) == 64 && sizeof(BBin) == 256 && sizeof(BReq) == 48 && sizeof(BJump) == 32 &&
+                  sizeof(BChunk) == 16,
               "descriptor layout");
 constexpr uint32_t kMaxBins = 64;
 
@@ -95,7 +116,18 @@ struct TableDesc {
   // batch of jumps copies no slice table before its launch).
   __device__ __forceinline__ BReq req(const BHeader& h, const BinInfo& bn, uint32_t rl) const {
     if (rl < bn.na) return ((const BReq*)(desc + h.req_off))[bn.a0 + rl];
-    return ((const BReq*)(hdesc + h.jo_off))[bn.b0 + (rl - bn.na)];
+    const BJump j = ((const BJump*)(hdesc + h.jo_off))[bn.b0 + (rl - bn.na)];
+    BReq q{};
+    q.seed = j.seed;
+    q.off_lo = j.off_lo;
+    q.off_hi = j.off_hi;
+    q.state = j.state;
+    return q;
+  }
+  // The records of the slices rl0 .. rl0 + nv - 1 without draws (rl0 >= na).
+  __device__ __forceinline__ uint4 octet_raw(const BHeader& h, const BinInfo& bn, uint32_t rl0, uint32_t nv,
+                                             uint32_t lane) const {
+    return octet_load(hdesc + h.jo_off + 32ull * (bn.b0 + (rl0 - bn.na)), nv, lane);
   }
   __device__ __forceinline__ BChunk chunk(const BHeader& h, uint32_t j) const {
     return ((const BChunk*)(desc + h.chunk_off))[j];
@@ -134,6 +166,10 @@ struct SingleDesc {
   }
   __device__ __forceinline__ uint32_t* counter(uint32_t, uint32_t* queue) const { return queue; }
   __device__ __forceinline__ BReq req(const BHeader&, const BinInfo&, uint32_t) const { return r0; }
+  // A single request has no octet items (n_qi = 0).
+  __device__ __forceinline__ uint4 octet_raw(const BHeader&, const BinInfo&, uint32_t, uint32_t, uint32_t) const {
+    return make_uint4(0u, 0u, 0u, 0u);
+  }
   __device__ __forceinline__ BChunk chunk(const BHeader& h, uint32_t j) const {
     BChunk c;
     c.req = 0;
@@ -194,10 +230,21 @@ __device__ __forceinline__ void publish_wait() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps the flag store after it in program order
 }
 
+// The lane within the wave, opaque to the optimiser: the item functions run
+// inside the persistent loop, and without this the compiler hoists every
+// lane-derived address and constant-table read of the seeding out of the loop
+// and keeps them in registers across items (135 VGPRs for the octet path
+// against 97).
+__device__ __forceinline__ uint32_t item_lane() {
+  uint32_t lane = threadIdx.x & 63u;
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
+
 template <class Desc>
 __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h, const BatchBuffers& B,
-                                                const BinInfo& bn, uint32_t p, uint32_t* lds, const SeedLds<false>& stab) {
-  const uint32_t lane = threadIdx.x;
+                                                const BinInfo& bn, uint32_t p, uint32_t* lds, const SeedLds<true>& stab) {
+  const uint32_t lane = item_lane();
   const uint32_t half = lane >> 5, l = lane & 31u;
   const uint32_t rl = 2u * p + half;
   const bool active = rl < bn.nsc;
@@ -206,7 +253,7 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   uint32_t* Bp = X + 193;
   BReq q{};
   if (active) q = D.req(h, bn, rl);
-  const bool valid = active && seed_group_tab<32, 4, false>(q.seed, X, l, stab);
+  const bool valid = active && seed_group_tab<32, 4, true>(q.seed, X, l, stab);
   if (!valid) X[l] = X[l + 32] = X[l + 64] = X[97] = 0;
   wave_sync();
   const uint32_t c = X[97];
@@ -244,7 +291,7 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
 template <class Desc>
 __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h, const BatchBuffers& B,
                                                  const BinInfo& bn, uint32_t cp, uint32_t* lds) {
-  const uint32_t lane = threadIdx.x;
+  const uint32_t lane = item_lane();
   const uint32_t half = lane >> 5, l = lane & 31u;
   const uint32_t jl = 2u * cp + half;
   const bool active = jl < bn.nk;
@@ -297,22 +344,30 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   wave_sync();
 }
 
-// Eight slices without draws per wave, 8 lanes each (seed_group / jump_group
-// of coop_dev.hpp, 20-bit windows; the host makes octet items only when that
-// table exists).  Nothing waits for them: the state goes straight to the
-// caller's record, if it asked for one.
-template <class Desc>
-__device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, const BatchBuffers& B,
-                                               const BinInfo& bn, uint32_t qi, uint32_t* lds, const SeedLds<false>& stab) {
-  const uint32_t lane = threadIdx.x;
+// Seeds and jumps the nv (<= 8) slices without draws of one octet, 8 lanes
+// each (seed_group / jump_group of coop_dev.hpp, 20-bit windows; octets are
+// made only when that table exists), from their records as octet_load reads
+// them.  Nothing waits for them: the state goes straight to the caller's
+// record, if it asked for one.  `issued` runs inside the jump, once its first
+// factor is being fetched (see jump_group).
+template <class Hook>
+__device__ __forceinline__ void jump_octet(uint4 raw, uint32_t nv, uint32_t lane, uint32_t* lds,
+                                           const SeedLds<true>& stab, const uint32_t* wtab20, Hook issued) {
   const uint32_t grp = lane >> 3, l = lane & 7u;
-  const uint32_t rl = bn.nsc + 8u * qi + grp;
-  const bool active = rl < bn.ns;
+  const bool active = grp < nv;
   uint32_t* X = lds + grp * kOctStride;
   uint32_t* Bp = X + 193;
-  BReq q{};
-  if (active) q = D.req(h, bn, rl);
-  const bool valid = active && seed_group_tab<8, 5, false>(q.seed, X, l, stab);
+  // The group's record from lanes 2 grp (seed, offset low) and 2 grp + 1
+  // (offset high, state pointer).
+  const int s0 = (int)(grp * 8u), s1 = s0 + 4;  // ds_bpermute byte addresses of lanes 2 grp, 2 grp + 1
+  const int32_t seed = __builtin_amdgcn_ds_bpermute(s0, (int)raw.x);
+  const uint32_t j0 = (uint32_t)__builtin_amdgcn_ds_bpermute(s0, (int)raw.z);
+  const uint32_t j1 = (uint32_t)__builtin_amdgcn_ds_bpermute(s0, (int)raw.w);
+  const uint32_t j2 = (uint32_t)__builtin_amdgcn_ds_bpermute(s1, (int)raw.x);
+  const uint32_t j3 = (uint32_t)__builtin_amdgcn_ds_bpermute(s1, (int)raw.y);
+  const uint64_t st = (uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(s1, (int)raw.z) |
+                      (uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(s1, (int)raw.w) << 32;
+  const bool valid = active && seed_group_tab<8, 7, true>(seed, X, l, stab);
   if (!valid) {
 #pragma unroll
     for (int k = 0; k < 96; k += 8) X[l + k] = 0;
@@ -320,54 +375,95 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
   }
   wave_sync();
   const uint32_t c = X[97];
-  const uint32_t j0 = valid ? (uint32_t)q.off_lo : 0u, j1 = valid ? (uint32_t)(q.off_lo >> 32) : 0u;
-  const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
-  jump_group<8, 20>(X, Bp, B.wtab20, j0, j1, j2, j3, wave_windows<20>(j0, j1, j2, j3), l);
-  if (active && q.state) {
-    uint32_t* dst = (uint32_t*)q.state;
+  const uint32_t e0 = valid ? j0 : 0u, e1 = valid ? j1 : 0u, e2 = valid ? j2 : 0u, e3 = valid ? j3 : 0u;
+  jump_group<8, 20>(X, Bp, wtab20, e0, e1, e2, e3, wave_windows<20>(e0, e1, e2, e3), l, issued);
+  if (active && st) {
+    gu32* dst = gptr((void*)(uintptr_t)st);
 #pragma unroll
     for (int k = 0; k < 96; k += 8) dst[l + k] = valid ? X[l + k] : 0u;
     if (l == 0) {
       dst[96] = valid ? X[96] : 0u;
-      dst[97] = valid ? c_jump(c, u128_mod_m(j0, j1, j2, j3)) : kInvalidC;
+      dst[97] = valid ? c_jump(c, u128_mod_m(e0, e1, e2, e3)) : kInvalidC;
     }
   }
   wave_sync();
 }
 
-// One-wave workgroups; workgroup w serves bin w mod n_bins.  The bin index
-// and everything derived from it stay wave-uniform (scalar registers).
-template <class Desc>
-__device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B) {
+// Octet qi of a bin's slices without draws.
+template <class Desc, class Hook>
+__device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, const BatchBuffers& B,
+                                               const BinInfo& bn, uint32_t qi, uint32_t* lds, const SeedLds<true>& stab,
+                                               Hook issued) {
+  const uint32_t lane = item_lane();
+  const uint32_t rl0 = bn.nsc + 8u * qi;
+  const uint32_t nv = bn.ns - rl0 < 8u ? bn.ns - rl0 : 8u;
+  jump_octet(D.octet_raw(h, bn, rl0, nv, lane), nv, lane, lds, stab, B.wtab20, issued);
+}
+
+// WPG independent one-wave workers per workgroup, sharing one copy of the
+// seeding table (filled before the only barrier); worker w serves bin
+// w mod n_bins.  The wave index is taken through readfirstlane, so the worker,
+// the bin and everything derived from them stay wave-uniform (scalar
+// registers), as they would with blockIdx.x alone.
+template <int WPG, class Desc>
+__device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B, const DirectJumps& dj) {
+  __shared__ uint32_t lds_all[WPG][kWaveLds];
+  __shared__ SeedLds<true> seed_tab;
+  if (dj.n) {
+    // The direct mapping: the octet's records are fetched before the table
+    // fill, which hides their latency; no descriptor is read.
+    const uint32_t wv = WPG == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t rl0 = 8u * (blockIdx.x * WPG + wv);
+    const uint32_t nv = rl0 < dj.n ? (dj.n - rl0 < 8u ? dj.n - rl0 : 8u) : 0u;
+    const uint4 raw = octet_load(dj.recs + 32ull * rl0, nv, lane);
+    seed_lds_fill(seed_tab, threadIdx.x, 64u * WPG);
+    __syncthreads();
+    if (nv) jump_octet(raw, nv, lane, lds_all[wv], seed_tab, B.wtab20, NoHook{});
+    return;
+  }
   const BHeader h = D.header();
-  const uint32_t lane = threadIdx.x;
-  __shared__ uint32_t lds[kWaveLds];
-  __shared__ SeedLds<false> seed_tab;
-  if (blockIdx.x >= h.n_workers) return;  // whole workgroups leave together
-  seed_lds_fill(seed_tab, lane, 64);
+  if (blockIdx.x * WPG >= h.n_workers) return;  // whole workgroups leave together
+  seed_lds_fill(seed_tab, threadIdx.x, 64u * WPG);
   __syncthreads();
-  const uint32_t x = blockIdx.x % h.n_bins;
+  const uint32_t wv = WPG == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t worker = blockIdx.x * WPG + wv;
+  if (worker >= h.n_workers) return;  // the last workgroup's spare waves (no barrier follows)
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t* lds = lds_all[wv];
+  const uint32_t x = worker % h.n_bins;
   const BinInfo bn = D.bin(x);
   uint32_t* ctr = D.counter(x, B.queue);
   const uint32_t n_jg = (bn.nsc + 1) / 2;           // jump pairs
   const uint32_t n_jq = (bn.ns - bn.nsc + 7) / 8;   // jump octets
+  // Dequeue without a lane-conditional branch: every lane executes the
+  // atomic, lane 0 adding 1 and the others 0, and lane 0's result is taken.
+  // (With `if (lane == 0) item = atomicAdd(...)` only lane 0 holds the item,
+  // and the compiler may merge that branch with other lane-0 branches of the
+  // loop body so that lanes 1..63 re-enter the body on a stale item.)
+  auto dequeue = [&]() { return atomicAdd(ctr, lane == 0 ? 1u : 0u); };
+  uint32_t got = dequeue();
   for (;;) {
-    // Dequeue without a lane-conditional branch: every lane executes the
-    // atomic, lane 0 adding 1 and the others 0, and lane 0's result is taken.
-    // (With `if (lane == 0) item = atomicAdd(...)` only lane 0 holds the item,
-    // and the compiler may merge that branch with other lane-0 branches of
-    // the loop body so that lanes 1..63 re-enter the body on a stale item.)
-    const uint32_t got = atomicAdd(ctr, lane == 0 ? 1u : 0u);
     const uint32_t item = __builtin_amdgcn_readfirstlane(got);
     if (item < bn.n_ju) {
       const uint32_t p1 = (item + 1) * bn.g < n_jg ? (item + 1) * bn.g : n_jg;
       for (uint32_t p = item * bn.g; p < p1; ++p) batch_jump_pair(D, h, B, bn, p, lds, seed_tab);
+      got = dequeue();
     } else if (item < bn.n_ju + bn.n_cg) {
       batch_chunk_pair(D, h, B, bn, item - bn.n_ju, lds);
+      got = dequeue();
     } else if (item < bn.n_ju + bn.n_cg + bn.n_qi) {
+      // Octets come last in a bin, and nothing waits for them: the next item
+      // is taken during the last octet's jump, so the atomic's round trip
+      // (microseconds, at the device's coherence point) overlaps the jump.
       const uint32_t it = item - bn.n_ju - bn.n_cg;
       const uint32_t p1 = (it + 1) * bn.gq < n_jq ? (it + 1) * bn.gq : n_jq;
-      for (uint32_t p = it * bn.gq; p < p1; ++p) batch_jump_oct(D, h, B, bn, p, lds, seed_tab);
+      for (uint32_t p = it * bn.gq; p < p1; ++p) {
+        const bool last = p + 1 == p1;
+        batch_jump_oct(D, h, B, bn, p, lds, seed_tab, [&]() {
+          if (last) got = dequeue();
+        });
+      }
     } else {
       break;
     }

@@ -457,18 +457,30 @@ __device__ __forceinline__ void apply_group(uint32_t* X, const uint32_t* B, uint
   wave_sync();
 }
 
-// jump_half for G lanes, with a table of WB-bit windows.
-template <int G, int WB>
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+// jump_half for G lanes, with a table of WB-bit windows.  `issued` runs once,
+// by the whole wave, after the first factor's loads have been issued (or at
+// once if there is none): a memory operation it starts there is waited for
+// only by loads issued after it, that is from the second factor on.
+template <int G, int WB, class Hook = NoHook>
 __device__ __forceinline__ void jump_group(uint32_t* X, uint32_t* B, const uint32_t* __restrict__ T, uint32_t j0,
-                                           uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l) {
+                                           uint32_t j1, uint32_t j2, uint32_t j3, int nwin, uint32_t l,
+                                           Hook issued = Hook{}) {
   constexpr int K = 96 / G;
   int w = next_window<WB>(j0, j1, j2, j3, 0, nwin);
-  if (w >= nwin) return;
+  if (w >= nwin) {
+    issued();
+    return;
+  }
   const uint32_t* row = window_row<WB>(T, j0, j1, j2, j3, w);
   uint32_t r[K + 1];
 #pragma unroll
   for (int k = 0; k < K; ++k) r[k] = row[l + G * k];
   r[K] = row[96];
+  issued();
   while (w < nwin) {
 #pragma unroll
     for (int k = 0; k < K; ++k) B[l + G * k] = r[k];

@@ -121,7 +121,8 @@ enum BatchVariant : int {
   BATCH_PAIRS = 5,        // slices without draws by pair items (32 lanes each) instead of octets (8 lanes)
   BATCH_HALF_GRID = 6,    // BATCH_AUTO on at most half the workgroups the device holds (fewer waves per CU)
   BATCH_QUARTER_GRID = 7, // the same on at most a quarter
-  BATCH_NUM_VARIANTS = 8
+  BATCH_DIRECT = 8,       // batches of jumps only: one octet per worker, one bin, no queue (else BATCH_AUTO)
+  BATCH_NUM_VARIANTS = 9
 };
 int batch_variant_for(uint64_t n, uint64_t draws_per_request);
 void batch_set_variant(ranmar_batch* b, int v);  // -1: from the table

@@ -378,10 +378,11 @@ def test_batch_large_prepare_in_parts(orc):
 
 
 # --- tuner over the batch executor --------------------------------------------
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(9))
 def test_batch_every_mapping_bit_identical(orc, variant):
     """Every mapping the batch tuner can pick (bins, jump items per dequeue,
-    8- or 32-lane jumps for requests without draws) on one batch that mixes
+    8- or 32-lane jumps for requests without draws, the direct mapping, which
+    falls back to the default on a batch with draws) on one batch that mixes
     20,000 jump-only requests (octet items from 16,384 on), requests with
     draws and one long request split over bins: the same bits as
     ranmar_seed_jump and the oracle."""
@@ -411,6 +412,36 @@ def test_batch_every_mapping_bit_identical(orc, variant):
     _check(orc, drawn)
 
 
+@pytest.mark.parametrize("n", [16384, 20003, 65541])
+def test_batch_direct_mapping_jumps_only(orc, n):
+    """The direct mapping (one octet of requests per worker, no queue) on
+    batches of jumps only, the last octet ragged, some requests without a
+    state record: the same bits as ranmar_seed_jump and the oracle; the
+    records left out stay untouched."""
+    s, lo, hi = synth.batch_jumps(n, 120, offset=31)
+    states = torch.full((n, 98), -7, dtype=torch.int32, device=dev())
+    skip = set(range(5, n, 997))
+    items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                  state=None if i in skip else states[i]) for i in range(n)]
+    R.ranmar_tune_set(R.RANMAR_K_BATCH, 8)
+    b = R.ranmar_batch_create(n, 1)
+    try:
+        say(f"direct mapping n={n}")
+        R.ranmar_batch_run(b, R.make_requests(items))
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+        R.ranmar_tune_set(R.RANMAR_K_BATCH, -1)
+    direct = R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev()))
+    keep = np.array([i not in skip for i in range(n)])
+    kt = torch.from_numpy(keep).to(dev())
+    assert torch.equal(states[kt], direct[kt])
+    assert bool((states[~kt] == -7).all())
+    idx = [0, 7, 8, n - 2, n - 1]
+    assert np.array_equal(u32(states)[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
+
+
 @pytest.mark.parametrize("variant", range(4))
 def test_batch_every_chunk_length_bit_identical(orc, variant):
     """Every chunk length the chunk tuner can pick (4,096 << variant draws),
@@ -438,12 +469,14 @@ def test_batch_and_chunk_tuners_pick_a_variant():
     """The tuner times every mapping and every chunk length on the device at
     a given shape and records a pick that later batches use."""
     try:
+        nv = R.ranmar_tune_variants(R.RANMAR_K_BATCH)
+        assert nv == 9
         best, ms = R.ranmar_tune_run(R.RANMAR_K_BATCH, 4096, 0)
-        assert 0 <= best < 8 and len(ms) == 8 and np.all(np.asarray(ms) > 0)
+        assert 0 <= best < nv and len(ms) == nv and np.all(np.asarray(ms) > 0)
         best_c, ms_c = R.ranmar_tune_run(R.RANMAR_K_CHUNK, 64, 100_000)
         assert 0 <= best_c < 4 and np.all(np.asarray(ms_c) > 0)
         best_b2, _ = R.ranmar_tune_run(R.RANMAR_K_BATCH, 64, 100_000)
-        assert 0 <= best_b2 < 8
+        assert 0 <= best_b2 < nv
     finally:  # later tests get the built-in defaults again
         R.ranmar_tune_clear(R.RANMAR_K_BATCH)
         R.ranmar_tune_clear(R.RANMAR_K_CHUNK)
