@@ -479,8 +479,11 @@ def run_jumps1m(R, torch, steps, warmup):
     # the tables t^(d 2^(20w)) mod phi).  Seeding (Appendix A, done in the
     # same launch) is not counted; the committed instruction counters of this
     # launch give its share.
+    # The window width of the variant the launch took (the tuner's pick).
+    name = R.ranmar_tune_variant_name(R.RANMAR_K_JUMP, R.ranmar_tune_pick(R.RANMAR_K_JUMP, n))
+    wb = int(name.split("window")[1]) if "window" in name else WIN_BITS
     Js = synth.u128_to_int(lo, hi)
-    digits = sum(sum(1 for w in range(7) if (J >> (WIN_BITS * w)) & ((1 << WIN_BITS) - 1)) for J in Js)
+    digits = sum(sum(1 for w in range(128 // wb + 1) if (J >> (wb * w)) & ((1 << wb) - 1)) for J in Js)
     macs = float(digits) * MACS_APPLY
     sqmul = sum(max(J.bit_length() - 1, 0) * MACS_SQUARE + max(bin(J).count("1") - 1, 0) * 2 for J in Js[:10000])
     ach = macs / (ms * 1e-3) / 1e12
@@ -488,11 +491,11 @@ def run_jumps1m(R, torch, steps, warmup):
         "metric": "jumps/s", "value": n / dt, "unit": "jumps/s", "ms_per_step": dt * 1e3, "dtype": "u24",
         "config": {"workload": "jumps1m: 10^6 seed+jump requests, seeds uniform on [1, 9e8], J uniform on "
                                "[0, 2^120), one launch", "requests": n},
-        "roofline": {"bound": "alu", "kernel": "k_jump_grp<8,20,seed>", "achieved": ach, "peak": VALU_PEAK_TOPS,
-                     "unit": "T lane-ops/s", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+        "roofline": {"bound": "alu", "kernel": "k_jump_grp<8,%d,seed>" % wb, "achieved": ach,
+                     "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
                      "basis": "24-bit multiply-adds of the table applications, %.0f per jump (9409 per non-zero "
-                              "20-bit digit); seeding not counted; square-and-multiply would need %.3g per jump"
-                              % (macs / n, sqmul / min(n, 10000) + MACS_APPLY),
+                              "%d-bit digit); seeding not counted; square-and-multiply would need %.3g per jump"
+                              % (macs / n, wb, sqmul / min(n, 10000) + MACS_APPLY),
                      "ops_per_launch": macs, "launch_ms": ms},
         "jump_only_launch_ms": ms_jump_only,
     }

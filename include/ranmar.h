@@ -433,6 +433,13 @@ const char *ranmar_tune_variant_name(int kernel, int variant);
 /* Forces a variant for subsequent calls (-1 = automatic). */
 int ranmar_tune_set(int kernel, int variant);
 
+/* The variant that calls of this shape take now (forced, tuned, or the
+ * built-in default), with n and count as for ranmar_tune_run (count is not
+ * used for RANMAR_K_JUMP and RANMAR_K_FAMILY).  A variant whose table
+ * cannot be allocated on the device falls back to the next narrower one when
+ * it runs.  Returns the variant index, or RANMAR_EINVAL. */
+int ranmar_tune_pick(int kernel, uint64_t n, uint64_t count);
+
 /* Times every variant of `kernel` on synthetic data of the given shape
  * (n streams/requests; count = draws, jump bits, or for RANMAR_K_FAMILY
  * log2 of the spacing delta; for RANMAR_K_BATCH and RANMAR_K_CHUNK, draws

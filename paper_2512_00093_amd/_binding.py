@@ -129,6 +129,7 @@ _SIGS = {
     "ranmar_tune_variants": (_int, [_int]),
     "ranmar_tune_variant_name": (ctypes.c_char_p, [_int, _int]),
     "ranmar_tune_set": (_int, [_int, _int]),
+    "ranmar_tune_pick": (_int, [_int, _u64, _u64]),
     "ranmar_tune_run": (_int, [_int, _u64, _u64, ctypes.POINTER(ctypes.c_double), _vp]),
     "ranmar_tune_clear": (_int, [_int]),
     "ranmar_tune_save": (_int, [ctypes.c_char_p]),
@@ -447,6 +448,10 @@ def ranmar_tune_variant_name(kernel: int, variant: int) -> str:
 
 def ranmar_tune_set(kernel: int, variant: int):
     return _check(lib().ranmar_tune_set(kernel, variant), "ranmar_tune_set")
+
+
+def ranmar_tune_pick(kernel: int, n: int, count: int = 0) -> int:
+    return _check(lib().ranmar_tune_pick(kernel, n, count), "ranmar_tune_pick")
 
 
 def ranmar_tune_run(kernel: int, n: int, count: int, stream=None):

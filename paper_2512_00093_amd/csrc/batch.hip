@@ -276,6 +276,7 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
     b->B.err = b->h_err;
     b->B.wtab = window_table();
     b->B.wtab20 = nullptr;  // set by the first batch with many requests without draws
+    b->B.wtab24 = nullptr;  // set while the jump tuner's pick for such batches is the 24-bit table
     b->B.spare = (uint32_t)b->max_slices;
     ok = b->B.wtab != nullptr;
   }
@@ -349,6 +350,17 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
     b->tried_wtab = true;
     b->B.wtab20 = window20_table();
     b->grid_node = b->grid_dnode = 0;  // forces the kernel nodes' arguments to be set again
+  }
+  // Octets take the 24-bit table where the jump kernel's pick for as many
+  // requests does (the tuner's choice: 32.5 GB, 5 factors per 120-bit offset).
+  {
+    const uint32_t* t24 = n_jo >= 16384 && b->B.wtab20 && jump_variant_for(n_jo) == JUMP_EIGHTH_WINDOW24
+                              ? window24_table()
+                              : nullptr;
+    if (t24 != b->B.wtab24) {
+      b->B.wtab24 = t24;
+      b->grid_node = b->grid_dnode = 0;  // the kernel nodes take the pointer at the next launch
+    }
   }
   // The direct mapping applies to batches of jumps only, as octets (else the
   // default mapping serves): one bin, and a grid of one worker per octet.
@@ -605,7 +617,7 @@ extern "C" int ranmar_run_unbatched(const ranmar_request* reqs, uint64_t n, void
     d.r0 = to_breq(reqs[r]);
     d.L = kDefaultChunk;
     d.epoch = ++c.epoch;
-    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), window20_table_ready(), c.queue, c.err, 1u};
+    BatchBuffers B{c.req_states, c.done, c.ptab, window_table(), window20_table_ready(), nullptr, c.queue, c.err, 1u};
     if (!B.wtab) return RANMAR_ENOMEM;
     const uint64_t items = 1 + (nq + 1) / 2;
     const unsigned grid = (unsigned)(items < maxgrid ? items : maxgrid);

@@ -198,6 +198,7 @@ struct BatchBuffers {
   const uint32_t* ptab;    // 97 words per q: P_{qL}
   const uint32_t* wtab;    // window table T[w][d], 8-bit digits
   const uint32_t* wtab20;  // window table with 20-bit digits, or nullptr
+  const uint32_t* wtab24;  // window table with 24-bit digits (octets take it when set), or nullptr
   uint32_t* queue;         // single-request launches: [0] next item, [1] finished workgroups
   int* err;                // host-visible error word
   uint32_t spare;          // index of the spare flag
@@ -259,7 +260,9 @@ __device__ __forceinline__ void batch_jump_pair(const Desc& D, const BHeader& h,
   const uint32_t c = X[97];
   const uint32_t j0 = valid ? (uint32_t)q.off_lo : 0u, j1 = valid ? (uint32_t)(q.off_lo >> 32) : 0u;
   const uint32_t j2 = valid ? (uint32_t)q.off_hi : 0u, j3 = valid ? (uint32_t)(q.off_hi >> 32) : 0u;
-  if (B.wtab20)  // uniform: 6 factors for a 120-bit offset instead of 15
+  if (B.wtab24)  // uniform: 5 factors for a 120-bit offset instead of 15
+    jump_half<24>(X, Bp, B.wtab24, j0, j1, j2, j3, wave_windows<24>(j0, j1, j2, j3), l);
+  else if (B.wtab20)  // 6 factors
     jump_half<20>(X, Bp, B.wtab20, j0, j1, j2, j3, wave_windows<20>(j0, j1, j2, j3), l);
   else
     jump_half<8>(X, Bp, B.wtab, j0, j1, j2, j3, wave_windows<8>(j0, j1, j2, j3), l);
@@ -352,7 +355,7 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
 // factor is being fetched (see jump_group).
 template <class Hook>
 __device__ __forceinline__ void jump_octet(uint4 raw, uint32_t nv, uint32_t lane, uint32_t* lds,
-                                           const SeedLds<true>& stab, const uint32_t* wtab20, Hook issued) {
+                                           const SeedLds<true>& stab, const BatchBuffers& B, Hook issued) {
   const uint32_t grp = lane >> 3, l = lane & 7u;
   const bool active = grp < nv;
   uint32_t* X = lds + grp * kOctStride;
@@ -376,7 +379,10 @@ __device__ __forceinline__ void jump_octet(uint4 raw, uint32_t nv, uint32_t lane
   wave_sync();
   const uint32_t c = X[97];
   const uint32_t e0 = valid ? j0 : 0u, e1 = valid ? j1 : 0u, e2 = valid ? j2 : 0u, e3 = valid ? j3 : 0u;
-  jump_group<8, 20>(X, Bp, wtab20, e0, e1, e2, e3, wave_windows<20>(e0, e1, e2, e3), l, issued);
+  if (B.wtab24)  // uniform: 5 factors for a 120-bit offset instead of 6
+    jump_group<8, 24>(X, Bp, B.wtab24, e0, e1, e2, e3, wave_windows<24>(e0, e1, e2, e3), l, issued);
+  else
+    jump_group<8, 20>(X, Bp, B.wtab20, e0, e1, e2, e3, wave_windows<20>(e0, e1, e2, e3), l, issued);
   if (active && st) {
     gu32* dst = gptr((void*)(uintptr_t)st);
 #pragma unroll
@@ -397,7 +403,7 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
   const uint32_t lane = item_lane();
   const uint32_t rl0 = bn.nsc + 8u * qi;
   const uint32_t nv = bn.ns - rl0 < 8u ? bn.ns - rl0 : 8u;
-  jump_octet(D.octet_raw(h, bn, rl0, nv, lane), nv, lane, lds, stab, B.wtab20, issued);
+  jump_octet(D.octet_raw(h, bn, rl0, nv, lane), nv, lane, lds, stab, B, issued);
 }
 
 // WPG independent one-wave workers per workgroup, sharing one copy of the
@@ -419,7 +425,7 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
     const uint4 raw = octet_load(dj.recs + 32ull * rl0, nv, lane);
     seed_lds_fill(seed_tab, threadIdx.x, 64u * WPG);
     __syncthreads();
-    if (nv) jump_octet(raw, nv, lane, lds_all[wv], seed_tab, B.wtab20, NoHook{});
+    if (nv) jump_octet(raw, nv, lane, lds_all[wv], seed_tab, B, NoHook{});
     return;
   }
   const BHeader h = D.header();

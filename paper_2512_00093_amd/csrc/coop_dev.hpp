@@ -198,8 +198,9 @@ __device__ __forceinline__ void apply_half(uint32_t* X, const uint32_t* B, uint3
 // `nwin`: number of low windows to consider (uniform over the wave); windows
 // whose digit is zero in every lane of the wave are skipped.  The next
 // window's row is loaded while the current one is applied.
-// Digit w of J in base 2^WB (WB = 8, 16 or 20, J as four 32-bit limbs).  A
-// 20-bit digit may straddle two limbs; the last one (bits 120..127) has 8 bits.
+// Digit w of J in base 2^WB (WB = 8, 16, 20 or 24, J as four 32-bit limbs).
+// A 20- or 24-bit digit may straddle two limbs; the last one (bits 120..127)
+// has 8 bits.
 template <int WB = kWinBits>
 __device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3, int w) {
   const int bit = w * WB;
@@ -213,7 +214,7 @@ __device__ __forceinline__ uint32_t window_digit(uint32_t j0, uint32_t j1, uint3
 }
 
 // Row of the factor t^(d 2^(WB w)) in a table of 2^WB rows per window (the
-// last window of a 20-bit table has only 2^8).
+// last window of a 20- or 24-bit table has only 2^8).
 template <int WB = kWinBits>
 __device__ __forceinline__ const uint32_t* window_row(const uint32_t* __restrict__ T, uint32_t j0, uint32_t j1,
                                                       uint32_t j2, uint32_t j3, int w) {

@@ -24,6 +24,7 @@ const uint32_t* window_table();    // T[w][d] = t^(d 2^(8w)) mod phi, per device
 const uint32_t* window16_table();  // T[w][d] = t^(d 2^(16w)) mod phi, per device (nullptr if it cannot be built)
 const uint32_t* window20_table();  // T[w][d] = t^(d 2^(20w)) mod phi: 6 x 2^20 + 2^8 rows (nullptr if it cannot be built)
 const uint32_t* window20_table_ready();  // the same if already built on this device, else nullptr (never builds)
+const uint32_t* window24_table();  // T[w][d] = t^(d 2^(24w)) mod phi: 5 x 2^24 + 2^8 rows, 32.5 GB (nullptr if it cannot be built)
 // Makes the batch's jumps use the 20-bit table (building it now if needed).
 void batch_use_wide_windows(ranmar_batch* b);
 hipError_t launch_seed_coop(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
@@ -80,7 +81,8 @@ enum JumpVariant : int {
   JUMP_EIGHTH_WINDOW = 3,   // one request per 8 lanes, 8-bit windows in LDS
   JUMP_EIGHTH_WINDOW16 = 4, // one request per 8 lanes, 16-bit windows (203 MB table)
   JUMP_EIGHTH_WINDOW20 = 5, // one request per 8 lanes, 20-bit windows (2.4 GB table)
-  JUMP_NUM_VARIANTS = 6
+  JUMP_EIGHTH_WINDOW24 = 6, // one request per 8 lanes, 24-bit windows (32.5 GB table)
+  JUMP_NUM_VARIANTS = 7
 };
 int jump_variant_for(uint64_t n);
 // Seed (seeds != nullptr) and jump with the given variant.

@@ -300,27 +300,41 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
 // Window tables, one per device and width, built by the square-and-multiply
 // kernel: T[w][d] = t^(d 2^(WB w)) mod phi.  WB = 8: 16 x 256 rows (1.6 MB,
 // L2-resident).  WB = 16: 8 x 65536 rows (203 MB), for bulk jumps, where it
-// halves the number of applications.
+// halves the number of applications; WB = 20 (2.4 GB) and WB = 24 (32.5 GB of
+// the device's 288 GB) take 6 and 5 factors for a 120-bit J instead of 15.
 // ---------------------------------------------------------------------------
+
+// J[i] = d 2^(wb w) for row r0 + i = w 2^wb + d.
+__global__ __launch_bounds__(256) void k_window_exponents(ranmar_u128* __restrict__ J, uint64_t r0, uint64_t n,
+                                                          int wb) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t r = r0 + i;
+  const uint64_t w = r >> wb, d = r & ((1ull << wb) - 1ull);
+  const unsigned __int128 v = (unsigned __int128)d << (wb * w);
+  J[i].lo = (uint64_t)v;
+  J[i].hi = (uint64_t)(v >> 64);
+}
+
 static const uint32_t* build_window_table(int wb) {
   const int windows = (128 + wb - 1) / wb;
   const uint64_t digits = 1ull << wb;
-  const int last_bits = 128 - wb * (windows - 1);  // the last window may be narrower (8 bits for wb = 20)
+  const int last_bits = 128 - wb * (windows - 1);  // the last window may be narrower (8 bits for wb = 20 or 24)
   const uint64_t n = (uint64_t)(windows - 1) * digits + (1ull << last_bits);
-  std::vector<ranmar_u128> Jh(n);
-  for (uint64_t r = 0; r < n; ++r) {
-    const uint64_t w = r >> wb, d = r & (digits - 1);
-    const unsigned __int128 v = (unsigned __int128)d << (wb * w);
-    Jh[r].lo = (uint64_t)v;
-    Jh[r].hi = (uint64_t)(v >> 64);
-  }
+  // The exponents are made on the device, a slice of rows at a time.
+  constexpr uint64_t kSlice = 1ull << 22;
+  const uint64_t slice = n < kSlice ? n : kSlice;
   uint32_t* T = nullptr;
   ranmar_u128* dJ = nullptr;
   hipStream_t st = nullptr;
-  bool ok = hipMalloc(&T, 4 * 97 * n) == hipSuccess && hipMalloc(&dJ, sizeof(ranmar_u128) * n) == hipSuccess &&
-            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-            hipMemcpyAsync(dJ, Jh.data(), sizeof(ranmar_u128) * n, hipMemcpyHostToDevice, st) == hipSuccess &&
-            launch_jump_poly(dJ, n, T, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+  bool ok = hipMalloc(&T, 4 * 97 * n) == hipSuccess && hipMalloc(&dJ, sizeof(ranmar_u128) * slice) == hipSuccess &&
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  for (uint64_t r0 = 0; ok && r0 < n; r0 += slice) {
+    const uint64_t cnt = n - r0 < slice ? n - r0 : slice;
+    hipLaunchKernelGGL(k_window_exponents, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dJ, r0, cnt, wb);
+    ok = hipGetLastError() == hipSuccess && launch_jump_poly(dJ, cnt, T + r0 * 97, st) == hipSuccess;
+  }
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
   if (st) hipStreamDestroy(st);
   hipFree(dJ);
   if (!ok) {
@@ -352,6 +366,7 @@ static const uint32_t* cached_window_table(int wb) {
 const uint32_t* window_table() { return cached_window_table(8); }
 const uint32_t* window16_table() { return cached_window_table(16); }
 const uint32_t* window20_table() { return cached_window_table(20); }
+const uint32_t* window24_table() { return cached_window_table(24); }
 
 const uint32_t* window20_table_ready() {
   int dev = 0;
@@ -378,7 +393,10 @@ static hipError_t launch_jump_grp(uint32_t* states, const int32_t* seeds, const 
   constexpr uint64_t kPerWg = 256 / G;
   if (!n) return hipSuccess;
   if ((n + kPerWg - 1) / kPerWg > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  const uint32_t* T = WB == 20 ? window20_table() : WB == 16 ? window16_table() : window_table();
+  const uint32_t* T = WB == 24   ? window24_table()
+                      : WB == 20 ? window20_table()
+                      : WB == 16 ? window16_table()
+                                 : window_table();
   if (!T) return hipErrorOutOfMemory;
   const dim3 grid((unsigned)((n + kPerWg - 1) / kPerWg));
   if (seeds)
@@ -392,10 +410,12 @@ hipError_t launch_jump_variant(int v, uint32_t* states, const int32_t* seeds, co
                                hipStream_t st) {
   if (v == JUMP_QUARTER_WINDOW) return launch_jump_grp<16, 8>(states, seeds, J, n, st);
   if (v == JUMP_EIGHTH_WINDOW) return launch_jump_grp<8, 8>(states, seeds, J, n, st);
-  // The 20- and 16-bit tables are large; without them narrower windows do
-  // the same job.
-  if (v == JUMP_EIGHTH_WINDOW20 && window20_table()) return launch_jump_grp<8, 20>(states, seeds, J, n, st);
-  if (v == JUMP_EIGHTH_WINDOW20 || v == JUMP_EIGHTH_WINDOW16) {
+  // The 24-, 20- and 16-bit tables are large; without them narrower windows
+  // do the same job.
+  if (v == JUMP_EIGHTH_WINDOW24 && window24_table()) return launch_jump_grp<8, 24>(states, seeds, J, n, st);
+  if ((v == JUMP_EIGHTH_WINDOW24 || v == JUMP_EIGHTH_WINDOW20) && window20_table())
+    return launch_jump_grp<8, 20>(states, seeds, J, n, st);
+  if (v == JUMP_EIGHTH_WINDOW24 || v == JUMP_EIGHTH_WINDOW20 || v == JUMP_EIGHTH_WINDOW16) {
     if (window16_table()) return launch_jump_grp<8, 16>(states, seeds, J, n, st);
     return launch_jump_grp<8, 8>(states, seeds, J, n, st);
   }

@@ -428,6 +428,7 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW) return "lanes8_window8";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW16) return "lanes8_window16";
   if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW20) return "lanes8_window20";
+  if (kernel == RANMAR_K_JUMP && variant == JUMP_EIGHTH_WINDOW24) return "lanes8_window24";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_RADIX) return "radix256_valu";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM) return "product_mfma_i8";
   if (kernel == RANMAR_K_FAMILY && variant == FAMILY_GEMM32) return "product_mfma32_i8";
@@ -438,6 +439,16 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   static const char* const kChunkNames[kChunkVariants] = {"chunk4096", "chunk8192", "chunk16384", "chunk32768"};
   if (kernel == RANMAR_K_CHUNK && variant >= 0 && variant < kChunkVariants) return kChunkNames[variant];
   return nullptr;
+}
+
+int ranmar_tune_pick(int kernel, uint64_t n, uint64_t count) {
+  if (ranmar_tune_variants(kernel) < 0 || n == 0) return RANMAR_EINVAL;
+  if (kernel == RANMAR_K_GENERATE) return gen_variant_for(n, count);
+  if (kernel == RANMAR_K_JUMP) return jump_variant_for(n);
+  if (kernel == RANMAR_K_FAMILY) return family_variant_for(n);
+  if (kernel == RANMAR_K_BATCH) return batch_variant_for(n, count);
+  std::lock_guard<std::mutex> g(g_mu);  // RANMAR_K_CHUNK: forced, tuned, else 16,384 draws
+  return g_forced[RANMAR_K_CHUNK] >= 0 ? g_forced[RANMAR_K_CHUNK] : g_chunk_pick >= 0 ? g_chunk_pick : 2;
 }
 
 int ranmar_tune_set(int kernel, int variant) {

@@ -86,6 +86,32 @@ def test_argument_errors_before_device_work(L):
     assert L.ranmar_jump(None, None, 0, None) == 0
 
 
+def test_tune_pick_reports_forced_tuned_and_default_variants(tmp_path):
+    """ranmar_tune_pick names the variant a call of a shape takes: a forced
+    one, else the tuned table's, else the built-in default (no device work)."""
+    from paper_2512_00093_amd import _binding as B
+    L = B.lib()
+    assert L.ranmar_tune_pick(99, 10, 10) == B.RANMAR_EINVAL and L.ranmar_tune_pick(B.RANMAR_K_JUMP, 0, 0) == B.RANMAR_EINVAL
+    names = lambda k, n, c=0: B.ranmar_tune_variant_name(k, B.ranmar_tune_pick(k, n, c))
+    try:
+        B.ranmar_tune_clear(-1)
+        assert names(B.RANMAR_K_JUMP, 10**6) == "lanes8_window20"
+        assert names(B.RANMAR_K_JUMP, 100) == "halfwave_window8"
+        assert names(B.RANMAR_K_BATCH, 10**6, 0) == "direct_jumps"
+        assert names(B.RANMAR_K_BATCH, 160, 870000) == "bins64_auto"
+        assert names(B.RANMAR_K_CHUNK, 64, 10**5) == "chunk16384"
+        B.ranmar_tune_set(B.RANMAR_K_JUMP, 6)
+        assert names(B.RANMAR_K_JUMP, 10**6) == "lanes8_window24"
+        B.ranmar_tune_set(B.RANMAR_K_JUMP, -1)
+        path = tmp_path / "t.txt"
+        path.write_text("1 19 0 4\n")           # kernel 1 (jump), log2 n = 19, variant 4
+        B.ranmar_tune_load(str(path))
+        assert names(B.RANMAR_K_JUMP, 600_000) == "lanes8_window16"
+    finally:
+        B.ranmar_tune_set(B.RANMAR_K_JUMP, -1)
+        B.ranmar_tune_clear(-1)
+
+
 def test_tune_table_roundtrip(tmp_path):
     from paper_2512_00093_amd import _binding as B
     nv = B.ranmar_tune_variants(B.RANMAR_K_GENERATE)

@@ -412,11 +412,12 @@ def test_batch_every_mapping_bit_identical(orc, variant):
     _check(orc, drawn)
 
 
-@pytest.mark.parametrize("n", [16384, 20003, 65541])
-def test_batch_direct_mapping_jumps_only(orc, n):
+@pytest.mark.parametrize("n,window", [(16384, 20), (20003, 20), (65541, 20), (20003, 24)])
+def test_batch_direct_mapping_jumps_only(orc, n, window):
     """The direct mapping (one octet of requests per worker, no queue) on
     batches of jumps only, the last octet ragged, some requests without a
-    state record: the same bits as ranmar_seed_jump and the oracle; the
+    state record, with the 20-bit table or (the jump kernel's pick forced to
+    it) the 24-bit one: the same bits as ranmar_seed_jump and the oracle; the
     records left out stay untouched."""
     s, lo, hi = synth.batch_jumps(n, 120, offset=31)
     states = torch.full((n, 98), -7, dtype=torch.int32, device=dev())
@@ -424,14 +425,16 @@ def test_batch_direct_mapping_jumps_only(orc, n):
     items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
                   state=None if i in skip else states[i]) for i in range(n)]
     R.ranmar_tune_set(R.RANMAR_K_BATCH, 8)
+    R.ranmar_tune_set(R.RANMAR_K_JUMP, 6 if window == 24 else 5)
     b = R.ranmar_batch_create(n, 1)
     try:
-        say(f"direct mapping n={n}")
+        say(f"direct mapping n={n} window={window}")
         R.ranmar_batch_run(b, R.make_requests(items))
         torch.cuda.synchronize()
     finally:
         R.ranmar_batch_destroy(b)
         R.ranmar_tune_set(R.RANMAR_K_BATCH, -1)
+        R.ranmar_tune_set(R.RANMAR_K_JUMP, -1)
     direct = R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
                                 torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev()))
     keep = np.array([i not in skip for i in range(n)])
@@ -440,6 +443,41 @@ def test_batch_direct_mapping_jumps_only(orc, n):
     assert bool((states[~kt] == -7).all())
     idx = [0, 7, 8, n - 2, n - 1]
     assert np.array_equal(u32(states)[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
+
+
+@pytest.mark.parametrize("variant", [0, 4, 5])
+def test_batch_mappings_with_the_24_bit_table(orc, variant):
+    """With the jump kernel's pick forced to the 24-bit table, a batch's
+    octets (and, once the table is set, its jump pairs) take it: a batch that
+    mixes 20,000 jump-only requests with requests with draws gives the same
+    bits as ranmar_seed_jump and the oracle under queue mappings with octets
+    and with pairs only."""
+    n = 20000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=25)
+    states = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+    items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                  state=states[i]) for i in range(n)]
+    drawn = _alloc(_mixed_requests(12, 90 + variant, max_count=70_000, with_zero=False))
+    mixed = items[:9000] + drawn + items[9000:]
+    R.ranmar_tune_set(R.RANMAR_K_BATCH, variant)
+    R.ranmar_tune_set(R.RANMAR_K_JUMP, 6)
+    b = R.ranmar_batch_create(len(mixed), 256)
+    try:
+        say(f"24-bit table, batch mapping {R.ranmar_tune_variant_name(R.RANMAR_K_BATCH, variant)}")
+        R.ranmar_batch_run(b, R.make_requests(mixed))
+        torch.cuda.synchronize()
+        R.ranmar_batch_run(b, R.make_requests(mixed))   # the same batch again: the same bits
+        torch.cuda.synchronize()
+    finally:
+        R.ranmar_batch_destroy(b)
+        R.ranmar_tune_set(R.RANMAR_K_BATCH, -1)
+        R.ranmar_tune_set(R.RANMAR_K_JUMP, -1)
+    direct = R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev()))
+    assert torch.equal(states, direct)
+    idx = [0, 8999, 9000, n - 1]
+    assert np.array_equal(u32(states)[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
+    _check(orc, drawn)
 
 
 @pytest.mark.parametrize("variant", range(4))

@@ -460,9 +460,9 @@ def test_repeatable(orc):
     assert torch.equal(R.ranmar_generate(a, 333, 1), R.ranmar_generate(b, 333, 1))
 
 
-# --- jump variants: per-lane square-and-multiply; 32, 16 or 8 lanes with 8-, 16- or 20-bit windows ---
-@pytest.fixture(params=[0, 1, 2, 3, 4, 5], ids=["lane_sqmul", "half_window", "lanes16_window", "lanes8_window",
-                                                "lanes8_window16", "lanes8_window20"])
+# --- jump variants: per-lane square-and-multiply; 32, 16 or 8 lanes with 8-, 16-, 20- or 24-bit windows ---
+@pytest.fixture(params=[0, 1, 2, 3, 4, 5, 6], ids=["lane_sqmul", "half_window", "lanes16_window", "lanes8_window",
+                                                   "lanes8_window16", "lanes8_window20", "lanes8_window24"])
 def jump_variant(request):
     R.ranmar_tune_set(R.RANMAR_K_JUMP, request.param)
     yield request.param
@@ -484,7 +484,8 @@ def test_jump_variant_edges(orc, jump_variant):
     lo, hi = synth.u128_uniform(g, 60, 120)
     Js = [0, 1, 2, 255, 256, 257, 65535, 1 << 64, (1 << 64) - 1, (1 << 120) - 1, (1 << 128) - 1,
           ((1 << 97) - 1) << 23, (1 << 20) - 1, 1 << 20, ((1 << 20) - 1) << 20, 1 << 60, (1 << 120) + 255,
-          ((1 << 8) - 1) << 120] + synth.u128_to_int(lo, hi)
+          ((1 << 8) - 1) << 120, (1 << 24) - 1, 1 << 24, ((1 << 24) - 1) << 24, ((1 << 24) - 1) << 96,
+          (1 << 72) + (1 << 71), ((1 << 48) - 1) << 40] + synth.u128_to_int(lo, hi)
     seeds = [int(s) for s in synth.seeds(len(Js), offset=18)]
     seeds[:3] = [0, 900000001, -7]       # invalid seeds leave the marker record
     say(f"seed_jump edges variant={jump_variant}")
