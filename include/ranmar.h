@@ -140,7 +140,11 @@ int ranmar_apply_poly(ranmar_state *d_states, const uint32_t *d_P, uint64_t n, v
  * ends, a 1.6 MB table of 8-bit digits and, from the first call with at
  * least 16384 requests, a 2.4 GB table of 20-bit digits (6 factors for a
  * 120-bit J instead of 15; if that allocation fails, the 16-bit table of
- * 203 MB or the 8-bit one serves; results are the same either way). */
+ * 203 MB or the 8-bit one serves; results are the same either way).  Where
+ * the RANMAR_K_JUMP variant for the call's size is lanes8_window24 (forced,
+ * or picked by the tuner), a 32.5 GB table of 24-bit digits (5 factors;
+ * built in about 0.7 s on first use, kept like the others; the 20-bit table
+ * serves if it cannot be allocated). */
 int ranmar_jump(ranmar_state *d_states, const ranmar_u128 *d_J, uint64_t n, void *stream);
 
 /* a1-a4 fused in one launch: d_out[r] = f^J(seed state of d_seeds[r]) with
@@ -413,14 +417,18 @@ int ranmar_lfg_generate(const ranmar_lfg_params *p, const uint32_t *d_in, uint32
  * bits; the tuner only picks the fastest for a shape. */
 typedef enum ranmar_kernel {
     RANMAR_K_GENERATE = 0,
-    RANMAR_K_JUMP = 1,
+    RANMAR_K_JUMP = 1,    /* ranmar_jump / ranmar_seed_jump: lanes per request
+                             and window-table width (8 to 24 bits) */
     RANMAR_K_FAMILY = 2,  /* ranmar_jump_family: radix rounds on the VALU, or
                              a matrix product on the matrix cores (MFMA) */
     RANMAR_K_BATCH = 3,   /* the batch executor's tile and lane mapping, chosen
                              by ranmar_batch_prepare per shape: bins, jump
-                             items per dequeue, and 8- or 32-lane jumps for
-                             requests without draws.  Shape: n requests of
-                             `count` draws each (0: jumps only). */
+                             items per dequeue, 8- or 32-lane jumps for
+                             requests without draws, or (batches of jumps
+                             only) the direct mapping of one 8-request octet
+                             per wave without a queue.  Its jumps take the
+                             window table of RANMAR_K_JUMP's pick.  Shape: n
+                             requests of `count` draws each (0: jumps only). */
     RANMAR_K_CHUNK = 4    /* draws per chunk of the batch executor (4096 <<
                              variant), taken by ranmar_batch_create when it is
                              given 0.  Same shape as RANMAR_K_BATCH. */
