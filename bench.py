@@ -120,7 +120,26 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--force", default="",
+                    help="kernel variants to force, e.g. jump=lanes8_window24,batch=direct_jumps (names as "
+                         "ranmar_tune_variant_name gives them; for reproducible profiles without the tuner)")
     return ap.parse_args()
+
+
+def force_variants(R, spec):
+    """Applies --force: kernel=variant-name pairs, by ranmar_tune_set."""
+    kernels = {"generate": R.RANMAR_K_GENERATE, "jump": R.RANMAR_K_JUMP, "family": R.RANMAR_K_FAMILY,
+               "batch": R.RANMAR_K_BATCH, "chunk": R.RANMAR_K_CHUNK}
+    out = {}
+    for item in filter(None, spec.split(",")):
+        k, name = item.split("=")
+        kern = kernels[k]
+        names = [R.ranmar_tune_variant_name(kern, v) for v in range(R.ranmar_tune_variants(kern))]
+        if name not in names:
+            raise SystemExit(f"--force: {k} has no variant {name!r} (variants: {', '.join(names)})")
+        R.ranmar_tune_set(kern, names.index(name))
+        out[k] = name
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -912,6 +931,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     extras = not a.no_extras and a.workload == "bulk1m"
+    forced = force_variants(R, a.force)
     tuned = {} if a.no_tune else autotune(R, a.workload, extras)
     if tuned:
         _progress("autotuned: " + json.dumps(tuned))
@@ -936,12 +956,19 @@ def main():
     for k in ("breakdown_ms", "output_write_GBps", "output_write_frac", "jump_only_launch_ms"):
         if k in res:
             line[k] = res[k]
+    if a.workload == "jumps1m":
+        # The same requests through the batch executor (one graph launch).
+        r = run_jumps1m_batched(R, torch, a.steps, a.warmup)
+        line["batched"] = {k: r[k] for k in ("value", "unit", "launch_ms", "host_prepare_ms")}
+        _progress("jumps1m_batched done")
     if a.workload == "bulk1m":
         ceil = run_store_ceiling(torch, a.steps, a.warmup)
         line["store_ceiling"] = ceil
         line["output_write_frac_of_store_ceiling"] = res["output_write_GBps"] / ceil["GBps"]
         _progress("store ceiling done")
     line["tuned"] = tuned
+    if forced:
+        line["forced"] = forced
     if extras:
         also = {}
         r = run_family65k(R, torch, 10, 2, a.jump)
