@@ -434,27 +434,35 @@ __device__ __forceinline__ void apply_group(uint32_t* X, const uint32_t* B, uint
     wave_sync();
   }
   const uint32_t* Xl = X + (uint32_t)K * l;
-  uint32_t w[K], a[K + 1];
+  uint32_t w[K], a[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) w[k] = Xl[k];
 #pragma unroll
-  for (int k = 0; k <= K; ++k) a[k] = 0;
+  for (int k = 0; k < K; ++k) a[k] = 0;
 #pragma unroll K
   for (int i = 0; i < 97; ++i) {
     const uint32_t wn = Xl[i + K];
     const uint32_t b = B[i];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = mad24(b, w[k], a[k]);
-    a[K] = mad24(b, wn, a[K]);
 #pragma unroll
     for (int k = 0; k + 1 < K; ++k) w[k] = w[k + 1];
     w[K - 1] = wn;
   }
+  // Output 96 (the 97th of G K = 96 tiled ones) as a dot product split over
+  // the group: lane l takes terms K l .. K l + K - 1, the last lane term 96
+  // too; a butterfly over the G lanes sums them.
+  uint32_t d = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) d = mad24(B[K * l + k], X[96 + K * l + k], d);
+  d = mad24(l == G - 1 ? B[96] : 0u, X[192], d);
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) d += (uint32_t)__shfl_xor((int)d, off);
   wave_sync();
   uint32_t* Xo = X + (uint32_t)K * l;
 #pragma unroll
   for (int k = 0; k < K; ++k) Xo[k] = a[k] & kMask;
-  if (l == G - 1) X[96] = a[K] & kMask;
+  if (l == G - 1) X[96] = d & kMask;
   wave_sync();
 }
 
