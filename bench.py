@@ -700,8 +700,10 @@ def run_paper_table2(R, torch, reps=20):
         bits = J.bit_length()
         jt = torch.from_numpy(np.array([[J & ((1 << 64) - 1), J >> 64]], dtype=np.uint64).view(np.int64)).to(dev)
         st = R.ranmar_seed_batch(torch.tensor([12345], dtype=torch.int32, device=dev))
-        for name, fn in (("jump_poly_us", lambda: R.ranmar_jump_poly(jt)),
-                         ("windowed_jump_us", lambda: R.ranmar_jump(st, jt))):
+        for name, poly, fn in (("jump_poly_us", -1, lambda: R.ranmar_jump_poly(jt)),
+                               ("jump_poly_square_multiply_us", 0, lambda: R.ranmar_jump_poly(jt)),
+                               ("windowed_jump_us", -1, lambda: R.ranmar_jump(st, jt))):
+            R.ranmar_tune_set(R.RANMAR_K_POLY, poly)
             for _ in range(3):
                 fn()
             torch.cuda.synchronize()
@@ -711,12 +713,13 @@ def run_paper_table2(R, torch, reps=20):
                 fn()
                 e.record()
             torch.cuda.synchronize()
+            R.ranmar_tune_set(R.RANMAR_K_POLY, -1)
             res.setdefault(f"J=2^{bits}-1", {})[name] = tm.mean_ms(f"{name}{bits}") * 1e3
     res["paper_us_cpu_ntl"] = {"J=2^64-1": {"apple": 1347, "arm": 10395, "ryzen": 946, "intel": 2702},
                                "J=2^120-1": {"apple": 2556, "arm": 21411, "ryzen": 1946, "intel": 4697}}
     res["config"] = {"workload": "paper Table 2 shape: one all-ones J per launch; jump_poly = t^J mod phi alone "
-                                 "(square-and-multiply, one lane), windowed_jump = the whole jump of one state "
-                                 "(table factors, 32 lanes)"}
+                                 "(window-table products, one wave; _square_multiply: the paper's method, one "
+                                 "lane), windowed_jump = the whole jump of one state (table factors, 32 lanes)"}
     return res
 
 

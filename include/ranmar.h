@@ -122,8 +122,11 @@ int ranmar_seed_batch(const int32_t *d_seeds, uint64_t n, ranmar_state *d_out, v
 
 /* a3: d_P[r*97 + i] = coefficient b_i of P_J(t) = t^J mod phi(t) over
  * Z/2^24 for J = d_J[r] (Sec. 3.1; the quantity the paper times in
- * Table 2).  Left-to-right square-and-multiply.  d_J: n values; d_P: 97*n
- * uint32, each < 2^24. */
+ * Table 2).  By default one wave per J multiplies the window table's factors
+ * t^(d 2^(8w)) (2^(20w) once that table exists) over J's nonzero digits,
+ * reducing each product mod phi; RANMAR_K_POLY variant 0 is left-to-right
+ * square-and-multiply, one J per lane (the paper's method).  Both give the
+ * same coefficients.  d_J: n values; d_P: 97*n uint32, each < 2^24. */
 int ranmar_jump_poly(const ranmar_u128 *d_J, uint64_t n, uint32_t *d_P, void *stream);
 
 /* a4: in place, x <- x P(A) for each state, with P = d_P[r*97 .. r*97+96]
@@ -429,9 +432,12 @@ typedef enum ranmar_kernel {
                              per wave without a queue.  Its jumps take the
                              window table of RANMAR_K_JUMP's pick.  Shape: n
                              requests of `count` draws each (0: jumps only). */
-    RANMAR_K_CHUNK = 4    /* draws per chunk of the batch executor (4096 <<
+    RANMAR_K_CHUNK = 4,   /* draws per chunk of the batch executor (4096 <<
                              variant), taken by ranmar_batch_create when it is
                              given 0.  Same shape as RANMAR_K_BATCH. */
+    RANMAR_K_POLY = 5     /* ranmar_jump_poly: square-and-multiply per lane, or
+                             window-table products per wave.  Shape: n
+                             exponents of `count` bits. */
 } ranmar_kernel;
 
 /* Number of variants of a kernel, and a short name for each. */

@@ -42,6 +42,7 @@ RANMAR_K_JUMP = 1
 RANMAR_K_FAMILY = 2
 RANMAR_K_BATCH = 3
 RANMAR_K_CHUNK = 4
+RANMAR_K_POLY = 5
 STATE_WORDS = 98
 
 

@@ -123,7 +123,8 @@ int ranmar_jump_poly(const ranmar_u128* d_J, uint64_t n, uint32_t* d_P, void* st
   if (overlap(d_J, 16 * n, d_P, 388 * n)) return RANMAR_EINVAL;
   int rc = ensure_init();
   if (rc) return rc;
-  return hip_status(launch_jump_poly(d_J, n, d_P, (hipStream_t)stream));
+  return hip_status(poly_variant_for(n) == POLY_TABLE ? launch_jump_poly_tab(d_J, n, d_P, (hipStream_t)stream)
+                                                      : launch_jump_poly(d_J, n, d_P, (hipStream_t)stream));
 }
 
 int ranmar_apply_poly(ranmar_state* d_states, const uint32_t* d_P, uint64_t n, void* stream) {

@@ -42,19 +42,7 @@ __device__ void wg_square(uint32_t* pad, uint32_t* prod) {
     prod[k] = s0 + s1;
   }
   __syncthreads();
-  // Reduce with t^(97+j) mod phi expressed in low powers (h_j = c_(97+j)):
-  // j <= 32: t^j - t^(64+j);  33..65: t^j - t^(j-33) + t^(j+31);
-  // 66..95: t^j - t^(j-33) + t^(j-66) - t^(j-2).
-  uint32_t v = 0;
-  if (k < 97) {
-    const uint32_t* h = prod + 97;
-    v = prod[k];
-    if (k <= 95) v += h[k];
-    if (k >= 64) v = v - h[k - 64] + h[k - 31];
-    if (k <= 62) v -= h[k + 33];
-    if (k <= 29) v += h[k + 66];
-    if (k >= 64 && k <= 93) v -= h[k + 2];
-  }
+  const uint32_t v = k < 97 ? fold_phi(prod, k) : 0u;
   __syncthreads();
   if (k < 97) pad[96 + k] = v & kMask;
   __syncthreads();

@@ -11,7 +11,14 @@ namespace ranmar {
 // seeds -> state records at offset 0
 hipError_t launch_seed(const int32_t* seeds, uint64_t n, uint32_t* out, hipStream_t st);
 // t^J mod phi, 97 words per request
-hipError_t launch_jump_poly(const ranmar_u128* J, uint64_t n, uint32_t* P, hipStream_t st);
+hipError_t launch_jump_poly(const ranmar_u128* J, uint64_t n, uint32_t* P, hipStream_t st);  // lane square-and-multiply
+hipError_t launch_jump_poly_tab(const ranmar_u128* J, uint64_t n, uint32_t* P, hipStream_t st);  // window-table products
+enum PolyVariant : int {
+  POLY_LANE_SQMUL = 0,  // one J per lane, left-to-right square-and-multiply in VGPRs
+  POLY_TABLE = 1,       // one J per wave, products of window-table factors
+  POLY_NUM_VARIANTS = 2
+};
+int poly_variant_for(uint64_t n);
 // x <- x P(A)
 hipError_t launch_apply_poly(uint32_t* states, const uint32_t* P, uint64_t n, hipStream_t st);
 // in-place f^J, optionally seeding first (seeds != nullptr)

@@ -8,6 +8,7 @@
 #include "common.hpp"
 #include "coop_dev.hpp"
 #include "internal.hpp"
+#include "jump_dev.hpp"
 
 namespace ranmar {
 
@@ -372,6 +373,93 @@ const uint32_t* window20_table_ready() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   return g_t20_ready[dev].load(std::memory_order_acquire);
+}
+
+// t^J mod phi (Sec. 3.1), one J per wave, as the product of the window
+// table's factors t^(d_w 2^(WB w)) over J's nonzero digits: with the 8-bit
+// table at most 15 products of two 97-coefficient polynomials, each reduced
+// mod phi, where square-and-multiply takes up to 122 squarings.  Lane l makes
+// coefficients 3l .. 3l + 2 of each product with a register window over the
+// running product a, which slides by one coefficient per term.
+template <int WB>
+__global__ __launch_bounds__(256) void k_jump_poly_tab(const ranmar_u128* __restrict__ J, uint64_t n,
+                                                       uint32_t* __restrict__ P, const uint32_t* __restrict__ T) {
+  constexpr int kPad = 96 + 97 + 96;  // a with 96 zeros on each side
+  __shared__ uint32_t lds[4][kPad + 97 + 193];
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63u;
+  const uint64_t r = (uint64_t)blockIdx.x * 4u + wv;
+  if (r >= n) return;  // whole waves leave; no barrier follows
+  uint32_t* pad = lds[wv];
+  uint32_t* b = pad + kPad;   // the factor
+  uint32_t* prod = b + 97;    // the unreduced product
+  const uint64_t lo = J[r].lo, hi = J[r].hi;
+  const uint32_t j0 = (uint32_t)lo, j1 = (uint32_t)(lo >> 32), j2 = (uint32_t)hi, j3 = (uint32_t)(hi >> 32);
+  for (uint32_t i = l; i < (uint32_t)kPad; i += 64) pad[i] = i == 96 ? 1u : 0u;
+  constexpr int kWin = (128 + WB - 1) / WB;
+  // The next factor's row is fetched while the current product runs.
+  int w = next_window<WB>(j0, j1, j2, j3, 0, kWin);
+  uint32_t r0 = 0, r1 = 0;
+  if (w < kWin) {
+    const uint32_t* row = window_row<WB>(T, j0, j1, j2, j3, w);
+    r0 = row[l];
+    r1 = l < 33 ? row[64 + l] : 0u;
+  }
+  while (w < kWin) {
+    b[l] = r0;
+    if (l < 33) b[64 + l] = r1;
+    wave_sync();
+    w = next_window<WB>(j0, j1, j2, j3, w + 1, kWin);
+    if (w < kWin) {
+      const uint32_t* row = window_row<WB>(T, j0, j1, j2, j3, w);
+      r0 = row[l];
+      r1 = l < 33 ? row[64 + l] : 0u;
+    }
+    // w0, w1, w2 = a_(3l-i), a_(3l+1-i), a_(3l+2-i) at term i.
+    const uint32_t* al = pad + 96 + 3 * l;
+    uint32_t w0 = al[0], w1 = al[1], w2 = al[2], c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll 8
+    for (int i = 0; i < 96; ++i) {
+      const uint32_t bi = b[i];
+      c0 = mad24(bi, w0, c0);
+      c1 = mad24(bi, w1, c1);
+      c2 = mad24(bi, w2, c2);
+      w2 = w1;
+      w1 = w0;
+      w0 = al[-(i + 1)];
+    }
+    c0 = mad24(b[96], w0, c0);
+    c1 = mad24(b[96], w1, c1);
+    c2 = mad24(b[96], w2, c2);
+    const uint32_t c192 = mad24(b[96], pad[96 + 96], 0u);  // the top coefficient, a_96 b_96
+    prod[3 * l] = c0;
+    prod[3 * l + 1] = c1;
+    prod[3 * l + 2] = c2;
+    if (l == 0) prod[192] = c192;
+    wave_sync();
+    const uint32_t v0 = fold_phi(prod, (int)l);
+    const uint32_t v1 = l < 33 ? fold_phi(prod, (int)l + 64) : 0u;
+    wave_sync();
+    pad[96 + l] = v0 & kMask;
+    if (l < 33) pad[160 + l] = v1 & kMask;
+    wave_sync();
+  }
+  uint32_t* dst = P + r * 97u;
+  dst[l] = pad[96 + l];
+  if (l < 33) dst[64 + l] = pad[160 + l];
+}
+
+hipError_t launch_jump_poly_tab(const ranmar_u128* J, uint64_t n, uint32_t* P, hipStream_t st) {
+  if (!n) return hipSuccess;
+  if ((n + 3) / 4 > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n + 3) / 4));
+  if (const uint32_t* T20 = window20_table_ready()) {  // 6 factors for 120 bits instead of 15
+    hipLaunchKernelGGL(k_jump_poly_tab<20>, grid, dim3(256), 0, st, J, n, P, T20);
+  } else {
+    const uint32_t* T = window_table();
+    if (!T) return hipErrorOutOfMemory;
+    hipLaunchKernelGGL(k_jump_poly_tab<8>, grid, dim3(256), 0, st, J, n, P, T);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,

@@ -105,6 +105,21 @@ __device__ __forceinline__ void mul_t_if(uint32_t (&a)[97], bool bit) {
   a[64] -= bit ? top : 0u;
 }
 
+// Coefficient k (< 97) of a product of degree <= 192, prod[0..192], reduced
+// mod phi (unmasked).  With h_j = prod[97 + j] and t^97 = 1 - t^64, t^(97+j)
+// in low powers is: j <= 32: t^j - t^(64+j); 33..65: t^j - t^(j-33) +
+// t^(j+31); 66..95: t^j - t^(j-33) + t^(j-66) - t^(j-2).
+__device__ __forceinline__ uint32_t fold_phi(const uint32_t* prod, int k) {
+  const uint32_t* h = prod + 97;
+  uint32_t v = prod[k];
+  if (k <= 95) v += h[k];
+  if (k >= 64) v = v - h[k - 64] + h[k - 31];
+  if (k <= 62) v -= h[k + 33];
+  if (k <= 29) v += h[k + 66];
+  if (k >= 64 && k <= 93) v -= h[k + 2];
+  return v;
+}
+
 // 128-bit helpers on four 32-bit limbs.
 __device__ __forceinline__ int u128_bitlen(uint32_t j0, uint32_t j1, uint32_t j2, uint32_t j3) {
   if (j3) return 128 - __clz(j3);

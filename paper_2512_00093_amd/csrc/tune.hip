@@ -22,7 +22,7 @@ namespace ranmar {
 
 namespace {
 std::mutex g_mu;
-int g_forced[5] = {-1, -1, -1, -1, -1};
+int g_forced[6] = {-1, -1, -1, -1, -1, -1};
 int g_chunk_pick = -1;  // last tuned or loaded RANMAR_K_CHUNK variant
 std::map<std::tuple<int, int, int>, int> g_table;  // (kernel, log2 n, log2 count) -> variant
 
@@ -49,6 +49,17 @@ int jump_variant_for(uint64_t n) {
   // each (a third of the latency per request, more workgroups) and the 1.6 MB
   // table.
   return n >= 16384 ? JUMP_EIGHTH_WINDOW20 : JUMP_HALF_WINDOW;
+}
+
+int poly_variant_for(uint64_t n) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (g_forced[RANMAR_K_POLY] >= 0) return g_forced[RANMAR_K_POLY];
+  auto it = g_table.find({RANMAR_K_POLY, ilog2(n), 0});
+  if (it != g_table.end()) return it->second;
+  // Table products: a fourth of square-and-multiply's multiply-adds for a
+  // uniform 120-bit J with the 8-bit table, and one wave per J instead of one
+  // lane (latency of one J: microseconds against a millisecond).
+  return POLY_TABLE;
 }
 
 int family_variant_for(uint64_t n) {
@@ -122,6 +133,46 @@ static int time_variants(int nv, Run run, double* ms_out, hipEvent_t e0, hipEven
     if (best[v] < best[bv]) bv = v;
   }
   return bv;
+}
+
+// Times the t^J mod phi variants on n uniform `bits`-bit exponents.
+static int tune_poly(uint64_t n, int bits, double* ms_out, hipStream_t st) {
+  if (n > (1ull << 24) || bits < 1 || bits > 128) return RANMAR_EINVAL;
+  std::vector<ranmar_u128> J(n);
+  uint64_t x = 0x2545F4914F6CDD1Dull;
+  for (uint64_t i = 0; i < n; ++i) {
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    const uint64_t lo = x * 0x9E3779B97F4A7C15ull, hi = x;
+    J[i].lo = bits >= 64 ? lo : lo & ((1ull << bits) - 1);
+    J[i].hi = bits > 64 ? (bits == 128 ? hi : hi & ((1ull << (bits - 64)) - 1)) : 0;
+  }
+  ranmar_u128* d_J = nullptr;
+  uint32_t* d_P = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = RANMAR_EHIP;
+  int best_v = 0;
+  if (hipMalloc(&d_J, 16 * n) != hipSuccess || hipMalloc(&d_P, 388 * n) != hipSuccess) goto done;
+  if (hipMemcpyAsync(d_J, J.data(), 16 * n, hipMemcpyHostToDevice, st) != hipSuccess) goto done;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+  best_v = time_variants(
+      POLY_NUM_VARIANTS,
+      [&](int v) { return v == POLY_TABLE ? launch_jump_poly_tab(d_J, n, d_P, st) : launch_jump_poly(d_J, n, d_P, st); },
+      ms_out, e0, e1, st, 3, 2);
+  if (best_v < 0) goto done;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table[{RANMAR_K_POLY, ilog2(n), 0}] = best_v;
+  }
+  rc = best_v;
+done:
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  hipFree(d_P);
+  hipFree(d_J);
+  return rc;
 }
 
 // Times the jump variants on n seed+jump requests with `bits`-bit offsets.
@@ -417,6 +468,7 @@ int ranmar_tune_variants(int kernel) {
   if (kernel == RANMAR_K_FAMILY) return FAMILY_NUM_VARIANTS;
   if (kernel == RANMAR_K_BATCH) return BATCH_NUM_VARIANTS;
   if (kernel == RANMAR_K_CHUNK) return kChunkVariants;
+  if (kernel == RANMAR_K_POLY) return POLY_NUM_VARIANTS;
   return RANMAR_EINVAL;
 }
 
@@ -438,6 +490,8 @@ const char* ranmar_tune_variant_name(int kernel, int variant) {
   if (kernel == RANMAR_K_BATCH && variant >= 0 && variant < BATCH_NUM_VARIANTS) return kBatchNames[variant];
   static const char* const kChunkNames[kChunkVariants] = {"chunk4096", "chunk8192", "chunk16384", "chunk32768"};
   if (kernel == RANMAR_K_CHUNK && variant >= 0 && variant < kChunkVariants) return kChunkNames[variant];
+  if (kernel == RANMAR_K_POLY && variant == POLY_LANE_SQMUL) return "lane_square_multiply";
+  if (kernel == RANMAR_K_POLY && variant == POLY_TABLE) return "window_products";
   return nullptr;
 }
 
@@ -447,6 +501,7 @@ int ranmar_tune_pick(int kernel, uint64_t n, uint64_t count) {
   if (kernel == RANMAR_K_JUMP) return jump_variant_for(n);
   if (kernel == RANMAR_K_FAMILY) return family_variant_for(n);
   if (kernel == RANMAR_K_BATCH) return batch_variant_for(n, count);
+  if (kernel == RANMAR_K_POLY) return poly_variant_for(n);
   std::lock_guard<std::mutex> g(g_mu);  // RANMAR_K_CHUNK: forced, tuned, else 16,384 draws
   return g_forced[RANMAR_K_CHUNK] >= 0 ? g_forced[RANMAR_K_CHUNK] : g_chunk_pick >= 0 ? g_chunk_pick : 2;
 }
@@ -469,6 +524,7 @@ int ranmar_tune_run(int kernel, uint64_t n, uint64_t count, double* ms_out, void
   if (kernel == RANMAR_K_FAMILY) return tune_family(n, count ? (int)count : 40, ms_out, st);
   if (kernel == RANMAR_K_BATCH) return tune_batch(n, count, ms_out, st);
   if (kernel == RANMAR_K_CHUNK) return tune_chunk(n, count, ms_out, st);
+  if (kernel == RANMAR_K_POLY) return tune_poly(n, count ? (int)count : 120, ms_out, st);
   if (count == 0 || n > (1ull << 24) || count > (1ull << 24) || n * count > (1ull << 31)) return RANMAR_EINVAL;
   // Synthetic states: seeds 1..n at offset 0.
   int32_t* d_seeds = nullptr;

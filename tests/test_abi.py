@@ -100,6 +100,7 @@ def test_tune_pick_reports_forced_tuned_and_default_variants(tmp_path):
         assert names(B.RANMAR_K_BATCH, 10**6, 0) == "direct_jumps"
         assert names(B.RANMAR_K_BATCH, 160, 870000) == "bins64_auto"
         assert names(B.RANMAR_K_CHUNK, 64, 10**5) == "chunk16384"
+        assert names(B.RANMAR_K_POLY, 1, 120) == "window_products"
         B.ranmar_tune_set(B.RANMAR_K_JUMP, 6)
         assert names(B.RANMAR_K_JUMP, 10**6) == "lanes8_window24"
         B.ranmar_tune_set(B.RANMAR_K_JUMP, -1)

@@ -63,26 +63,51 @@ def test_seed_batch_invalid_marks_record():
 
 
 # --- a3: t^J mod phi ------------------------------------------------------------
-def test_jump_poly(orc):
+@pytest.fixture(params=[0, 1], ids=["lane_square_multiply", "window_products"])
+def poly_variant(request):
+    R.ranmar_tune_set(R.RANMAR_K_POLY, request.param)
+    yield request.param
+    R.ranmar_tune_set(R.RANMAR_K_POLY, -1)
+
+
+def test_jump_poly(orc, poly_variant):
     g = synth.rng(210)
     lo, hi = synth.u128_uniform(g, 120, 120)
-    Js = [0, 1, 2, 5, 63, 64, 65, 96, 97, 98, 129, 130, 193, 1 << 20, 10 ** 6, (1 << 128) - 1] + TABLE2 + \
+    Js = [0, 1, 2, 5, 63, 64, 65, 96, 97, 98, 129, 130, 193, 255, 256, 257, 1 << 20, 10 ** 6, (1 << 128) - 1,
+          ((1 << 8) - 1) << 120, (1 << 127) + 1] + TABLE2 + \
         synth.u128_to_int(lo, hi) + [int(v) for v in g.integers(0, 1 << 40, size=20)]
-    say(f"jump_poly n={len(Js)}")
+    say(f"jump_poly n={len(Js)} variant={poly_variant}")
     P = u32(R.ranmar_jump_poly(jumps_t(Js)))
     ref = orc.xpow_many(Js)
     bad = [Js[r] for r in range(len(Js)) if not np.array_equal(P[r], ref[r])]
     assert not bad, bad[:5]
 
 
-def test_jump_poly_waves_of_mixed_length(orc):
-    """Lanes of one wave with very different exponent lengths (the loop runs
-    over the wave's longest; short exponents carry leading zeros)."""
-    Js = [(1 << (k % 128)) + k for k in range(200)]
-    say("jump_poly mixed lengths n=200")
+def test_jump_poly_waves_of_mixed_length(orc, poly_variant):
+    """Lanes of one wave with very different exponent lengths (the lane
+    variant's loop runs over the wave's longest; short exponents carry leading
+    zeros), and a count that leaves the last workgroup's waves partly idle."""
+    Js = [(1 << (k % 128)) + k for k in range(203)]
+    say(f"jump_poly mixed lengths n=203 variant={poly_variant}")
     P = u32(R.ranmar_jump_poly(jumps_t(Js)))
     ref = orc.xpow_many(Js)
     assert np.array_equal(P, ref)
+
+
+def test_jump_poly_variants_agree_at_scale():
+    """The two t^J mod phi variants on 20,000 uniform 120-bit exponents
+    (with the 20-bit table built, the window products take it)."""
+    s, lo, hi = synth.batch_jumps(20000, 120, offset=33)
+    J = limbs_t(lo, hi)
+    R.ranmar_seed_jump(seeds_t(s), J)   # 20,000 requests: builds the 20-bit window table
+    try:
+        R.ranmar_tune_set(R.RANMAR_K_POLY, 0)
+        a = R.ranmar_jump_poly(J)
+        R.ranmar_tune_set(R.RANMAR_K_POLY, 1)
+        b = R.ranmar_jump_poly(J)
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_POLY, -1)
+    assert torch.equal(a, b)
 
 
 # --- a4: apply ----------------------------------------------------------------
@@ -519,6 +544,11 @@ def test_jump_variants_agree_at_scale(jump_variant):
 def test_tune_run_jump_and_generate():
     best, ms = R.ranmar_tune_run(R.RANMAR_K_JUMP, 4096, 120)
     assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_JUMP) and all(m > 0 for m in ms)
+    try:
+        best, ms = R.ranmar_tune_run(R.RANMAR_K_POLY, 4096, 120)
+        assert 0 <= best < 2 and len(ms) == 2 and all(m > 0 for m in ms)
+    finally:
+        R.ranmar_tune_clear(R.RANMAR_K_POLY)
     best, ms = R.ranmar_tune_run(R.RANMAR_K_GENERATE, 4096, 4096)
     assert 0 <= best < R.ranmar_tune_variants(R.RANMAR_K_GENERATE) and all(m > 0 for m in ms)
     best, ms = R.ranmar_tune_run(R.RANMAR_K_FAMILY, 20000, 40)
