@@ -146,7 +146,7 @@ int ranmar_apply_poly(ranmar_state *d_states, const uint32_t *d_P, uint64_t n, v
  * 203 MB or the 8-bit one serves; results are the same either way).  Where
  * the RANMAR_K_JUMP variant for the call's size is lanes8_window24 (forced,
  * or picked by the tuner), a 32.5 GB table of 24-bit digits (5 factors;
- * built in about 0.7 s on first use, kept like the others; the 20-bit table
+ * built in about 0.2 s on first use, kept like the others; the 20-bit table
  * serves if it cannot be allocated). */
 int ranmar_jump(ranmar_state *d_states, const ranmar_u128 *d_J, uint64_t n, void *stream);
 

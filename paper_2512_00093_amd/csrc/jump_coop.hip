@@ -317,7 +317,13 @@ __global__ __launch_bounds__(256) void k_window_exponents(ranmar_u128* __restric
   J[i].hi = (uint64_t)(v >> 64);
 }
 
-static const uint32_t* build_window_table(int wb) {
+template <int WB>
+__global__ __launch_bounds__(256) void k_jump_poly_tab(const ranmar_u128* __restrict__ J, uint64_t n,
+                                                       uint32_t* __restrict__ P, const uint32_t* __restrict__ T);
+
+// T8: the 8-bit table when wb > 8 (the wider tables are products of its
+// factors), else nullptr.
+static const uint32_t* build_window_table(int wb, const uint32_t* T8) {
   const int windows = (128 + wb - 1) / wb;
   const uint64_t digits = 1ull << wb;
   const int last_bits = 128 - wb * (windows - 1);  // the last window may be narrower (8 bits for wb = 20 or 24)
@@ -330,10 +336,19 @@ static const uint32_t* build_window_table(int wb) {
   hipStream_t st = nullptr;
   bool ok = hipMalloc(&T, 4 * 97 * n) == hipSuccess && hipMalloc(&dJ, sizeof(ranmar_u128) * slice) == hipSuccess &&
             hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  // The 8-bit table is built by square-and-multiply; the wider ones as
+  // products of its factors (a 24-bit digit spans three 8-bit ones: at most
+  // two products per row, where square-and-multiply takes up to 122 squarings).
   for (uint64_t r0 = 0; ok && r0 < n; r0 += slice) {
     const uint64_t cnt = n - r0 < slice ? n - r0 : slice;
     hipLaunchKernelGGL(k_window_exponents, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dJ, r0, cnt, wb);
-    ok = hipGetLastError() == hipSuccess && launch_jump_poly(dJ, cnt, T + r0 * 97, st) == hipSuccess;
+    ok = hipGetLastError() == hipSuccess;
+    if (ok && T8)
+      hipLaunchKernelGGL(k_jump_poly_tab<8>, dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st, dJ, cnt, T + r0 * 97,
+                         T8);
+    else if (ok)
+      ok = launch_jump_poly(dJ, cnt, T + r0 * 97, st) == hipSuccess;
+    ok = ok && hipGetLastError() == hipSuccess;
   }
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   if (st) hipStreamDestroy(st);
@@ -351,6 +366,10 @@ static const uint32_t* build_window_table(int wb) {
 static std::atomic<const uint32_t*> g_t20_ready[64];
 
 static const uint32_t* cached_window_table(int wb) {
+  // A wider table is built from the 8-bit one, which is taken first (its
+  // own call holds the lock below only while it builds).
+  const uint32_t* T8 = wb > 8 ? cached_window_table(8) : nullptr;
+  if (wb > 8 && !T8) return nullptr;
   static std::mutex mu;
   static std::map<std::pair<int, int>, const uint32_t*> tabs;  // (device, width) -> table; failures cached too
   int dev = 0;
@@ -358,7 +377,7 @@ static const uint32_t* cached_window_table(int wb) {
   std::lock_guard<std::mutex> g(mu);
   auto it = tabs.find({dev, wb});
   if (it != tabs.end()) return it->second;
-  const uint32_t* T = build_window_table(wb);
+  const uint32_t* T = build_window_table(wb, T8);
   tabs[{dev, wb}] = T;
   if (wb == 20 && dev >= 0 && dev < 64) g_t20_ready[dev].store(T, std::memory_order_release);
   return T;
