@@ -208,7 +208,8 @@ struct BatchBuffers {
 constexpr int kHalfLds = 193 + 97;
 // LDS per 8-lane group of a jump octet (stride 1 mod 4: see k_jump_grp).
 constexpr int kOctStride = 193 + 97 + 3;
-constexpr int kWaveLds = 8 * kOctStride > 2 * kHalfLds ? 8 * kOctStride : 2 * kHalfLds;
+constexpr int kWaveLds = 8 * kOctStride > 2 * kHalfLds + 256 ? 8 * kOctStride : 2 * kHalfLds + 256;
+static_assert(2 * kHalfLds + 256 <= kWaveLds, "chunk pairs: two half-wave windows and their transpose buffers");
 
 // Hand-off of a slice's start state from the wave that jumped it to the waves
 // that generate its chunks, which may run on other XCDs (each XCD has its own
@@ -341,8 +342,14 @@ __device__ __forceinline__ void batch_chunk_pair(const Desc& D, const BHeader& h
   wave_sync();
   if (active) {
     uint32_t* dst = (ch.last && rq.state) ? (uint32_t*)rq.state : nullptr;
-    gen_stream32<FMT_RUNTIME, true>(l, lane, X, dst, ch.draws, rq.fmt == RANMAR_F32,
-                                    (char*)rq.out + (uint64_t)ch.q * h.L * 4u);
+    char* row = (char*)rq.out + (uint64_t)ch.q * h.L * 4u;
+    // A 16-byte aligned row (always, from a server's arena) is written four
+    // blocks at a time, 16 bytes per lane, through 128 words of LDS per half.
+    if (((uintptr_t)row & 15u) == 0)
+      gen_stream32_wide<FMT_RUNTIME, true>(l, lane, X, dst, ch.draws, rq.fmt == RANMAR_F32, row,
+                                           lds + 2 * kHalfLds + 128u * half);
+    else
+      gen_stream32<FMT_RUNTIME, true>(l, lane, X, dst, ch.draws, rq.fmt == RANMAR_F32, row);
   }
   wave_sync();
 }
@@ -413,7 +420,7 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
 // registers), as they would with blockIdx.x alone.
 template <int WPG, class Desc>
 __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B, const DirectJumps& dj) {
-  __shared__ uint32_t lds_all[WPG][kWaveLds];
+  __shared__ __align__(16) uint32_t lds_all[WPG][kWaveLds];  // 16-byte rows: chunk transposes read u32x4
   __shared__ SeedLds<true> seed_tab;
   if (dj.n) {
     // The direct mapping: the octet's records are fetched before the table

@@ -60,6 +60,31 @@ def _check(orc, items, sample=None):
         assert np.array_equal(u32(it["state"]), ref_st[0]), (r, it["count"])
 
 
+def test_batch_outputs_at_every_alignment(orc):
+    """Outputs that start 0, 4, 8 or 12 bytes past a 16-byte boundary: the
+    aligned chunks are written 16 bytes per lane, the others 4 bytes per lane
+    (both kinds can share a wave); every draw and final state is the oracle's."""
+    items = _mixed_requests(24, 7, max_count=60_000)
+    for k, it in enumerate(items):
+        dt = torch.float32 if it["fmt"] else torch.int32
+        shift = k % 4
+        it["buf"] = torch.full((max(it["count"], 1) + 4,), -3, dtype=dt, device=dev())
+        it["out"] = it["buf"][shift:shift + max(it["count"], 1)]
+        it["state"] = torch.zeros(98, dtype=torch.int32, device=dev())
+    b = R.ranmar_batch_create(64, 4096, 8192)
+    try:
+        say(f"batch outputs at every alignment n={len(items)}")
+        R.ranmar_batch_run(b, R.make_requests(items))
+        torch.cuda.synchronize()
+        _check(orc, items)
+        for k, it in enumerate(items):   # nothing written outside the output
+            shift, n = k % 4, max(it["count"], 1)
+            outside = torch.cat([it["buf"][:shift], it["buf"][shift + n:]])
+            assert bool((u32(outside) == u32(torch.full_like(outside, -3))).all()), k
+    finally:
+        R.ranmar_batch_destroy(b)
+
+
 def test_batch_matches_oracle(orc):
     items = _alloc(_mixed_requests(40, 1))
     b = R.ranmar_batch_create(64, 4096)
