@@ -75,9 +75,11 @@ def test_lfg_generate(orc, name, fmt):
     n = 37 if g.r < 2000 else 5  # ragged: not a multiple of the streams per wave
     st = synth.lfg_states(g.r, g.e, g.m, n, offset=24)
     p = _params(name)
-    for count in (0, 1, 3, g.s, g.r + 1, 1000, 4097):
-        say(f"lfg_generate {name} n={n} count={count} fmt={fmt}")
-        ld = count + 5
+    # Row pitches of count + 5 and of count rounded up to a multiple of 4,
+    # plus 4 (every row start 16-byte aligned).
+    for count, pad in [(c, pad) for c in (0, 1, 3, g.s, g.r + 1, 1000, 4097) for pad in (5, None)]:
+        ld = count + pad if pad is not None else (count + 3) // 4 * 4 + 4
+        say(f"lfg_generate {name} n={n} count={count} ld={ld} fmt={fmt}")
         d_in = _states_t(st)
         d_st = torch.full_like(d_in, -1)
         dt = torch.float32 if fmt else torch.int32
