@@ -759,33 +759,42 @@ def run_jumps1m_batched(R, torch, steps, warmup):
             e.record()
             torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        # The same requests by ranmar_seed_jump, in alternation with the batch
-        # launches, so that both see the same clock (it drifts down over a
-        # long run): the batch executor's device time against the plain launch.
-        seeds = torch.from_numpy(s.copy()).to(dev)
-        offs = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
-        direct = torch.empty_like(out)
-        R.ranmar_seed_jump(seeds, offs, out=direct)
-        for _ in range(steps):
-            R.ranmar_batch_prepare(b, reqs)
-            torch.cuda.synchronize()
-            a, e = tm.span("alt_batch")
-            a.record()
-            R.ranmar_batch_launch(b)
-            e.record()
-            a, e = tm.span("alt_direct")
-            a.record()
-            R.ranmar_seed_jump(seeds, offs, out=direct)
-            e.record()
-        torch.cuda.synchronize()
-        same = bool(torch.equal(out, direct))
-        # Two batch objects in turn: the host prepares one batch while the
-        # device runs the other (prepare waits only for its own object's
-        # previous launch), as a serving loop would.
         b2 = R.ranmar_batch_create(n, 1)
         try:
             pair = (b, b2)
             R.ranmar_batch_run(b2, reqs)
+            # The same requests by ranmar_seed_jump, in alternation with the
+            # batch launches, so that both see the same clock (it drifts over
+            # a run): the batch executor's device time against the plain
+            # launch.  The host prepares the next batch (the other object)
+            # while the device runs both launches, so neither follows an idle
+            # device, and the order alternates between steps.
+            seeds = torch.from_numpy(s.copy()).to(dev)
+            offs = torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev)
+            direct = torch.empty_like(out)
+            R.ranmar_seed_jump(seeds, offs, out=direct)
+            torch.cuda.synchronize()
+            R.ranmar_batch_prepare(pair[0], reqs)
+            for k in range(2 * steps):
+                def batch_launch():
+                    a, e = tm.span("alt_batch")
+                    a.record()
+                    R.ranmar_batch_launch(pair[k % 2])
+                    e.record()
+
+                def direct_launch():
+                    a, e = tm.span("alt_direct")
+                    a.record()
+                    R.ranmar_seed_jump(seeds, offs, out=direct)
+                    e.record()
+                for fn in ((batch_launch, direct_launch) if k % 2 == 0 else (direct_launch, batch_launch)):
+                    fn()
+                R.ranmar_batch_prepare(pair[(k + 1) % 2], reqs)
+            torch.cuda.synchronize()
+            same = bool(torch.equal(out, direct))
+            # Two batch objects in turn: the host prepares one batch while the
+            # device runs the other (prepare waits only for its own object's
+            # previous launch), as a serving loop would.
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for k in range(steps):

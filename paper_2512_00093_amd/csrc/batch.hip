@@ -38,14 +38,19 @@ namespace ranmar {
 // waves keeps the LDS of 16 waves within a CU's 160 KB.
 constexpr uint32_t kBatchWpg = 4;
 
+// The kernels of the two graphs take the same arguments (the direct graph's
+// kernel reads only B and dj, the other only desc, hdesc and B).
 __global__ __launch_bounds__(64 * kBatchWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tables(
-    uint8_t* desc, const uint8_t* hdesc, BatchBuffers B, DirectJumps dj) {
-  batch_persistent<kBatchWpg>(TableDesc{desc, hdesc}, B, dj);
+    uint8_t* desc, const uint8_t* hdesc, BatchBuffers B, DirectJumps) {
+  batch_persistent<kBatchWpg>(TableDesc{desc, hdesc}, B);
 }
 
-__global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers B) {
-  batch_persistent<1>(d, B, DirectJumps{nullptr, 0u, 0u});
+__global__ __launch_bounds__(64 * kBatchWpg) void k_batch_direct(uint8_t*, const uint8_t*, BatchBuffers B,
+                                                                 DirectJumps dj) {
+  batch_direct<kBatchWpg>(B, dj);
 }
+
+__global__ __launch_bounds__(64) void k_batch_single(SingleDesc d, BatchBuffers B) { batch_persistent<1>(d, B); }
 
 constexpr uint32_t kDefaultChunk = 16384;
 constexpr uint32_t kMaxChunkDraws = 1u << 24;
@@ -177,13 +182,13 @@ struct ranmar_batch {
   int variant = -1;           // mapping (BatchVariant); -1: the tuner's table
 };
 
-static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned workers) {
+static hipKernelNodeParams kernel_params(ranmar_batch* b, unsigned workers, bool direct) {
   hipKernelNodeParams kp{};
   b->kargs[0] = (void*)&b->kdesc;
   b->kargs[1] = (void*)&b->khdesc;
   b->kargs[2] = (void*)&b->B;
   b->kargs[3] = (void*)&b->kdirect;
-  kp.func = (void*)k_batch_tables;
+  kp.func = direct ? (void*)k_batch_direct : (void*)k_batch_tables;
   kp.gridDim = dim3((workers + kBatchWpg - 1) / kBatchWpg);
   kp.blockDim = dim3(64 * kBatchWpg);
   kp.sharedMemBytes = 0;
@@ -288,11 +293,12 @@ int ranmar_batch_create(uint64_t max_requests, uint64_t max_chunks, uint64_t chu
                                  hipMemcpyHostToDevice) == hipSuccess;
     if (ok) {
       const unsigned grid = b->workers_max;  // workers
-      const hipKernelNodeParams kp = kernel_params(b, grid);
+      const hipKernelNodeParams kp = kernel_params(b, grid, false);
+      const hipKernelNodeParams kpd = kernel_params(b, grid, true);
       ok = hipGraphAddKernelNode(&b->kern, b->graph, &b->cpy, 1, &kp) == hipSuccess &&
            hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess &&
            hipGraphCreate(&b->graph_d, 0) == hipSuccess &&
-           hipGraphAddKernelNode(&b->kern_d, b->graph_d, nullptr, 0, &kp) == hipSuccess &&
+           hipGraphAddKernelNode(&b->kern_d, b->graph_d, nullptr, 0, &kpd) == hipSuccess &&
            hipGraphInstantiate(&b->exec_d, b->graph_d, nullptr, nullptr, 0) == hipSuccess;
       b->grid_node = grid;
       b->grid_dnode = 0;
@@ -510,7 +516,7 @@ int ranmar_batch_launch(ranmar_batch* b, void* stream) {
     if (b->grid_prepared != b->grid_dnode || b->dj_prepared.recs != b->kdirect_d.recs ||
         b->dj_prepared.n != b->kdirect_d.n) {
       b->kdirect = b->dj_prepared;
-      const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared);
+      const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared, true);
       if (hipGraphExecKernelNodeSetParams(b->exec_d, b->kern_d, &kp) != hipSuccess) return RANMAR_EHIP;
       b->kdirect_d = b->dj_prepared;
       b->grid_dnode = b->grid_prepared;
@@ -522,7 +528,7 @@ int ranmar_batch_launch(ranmar_batch* b, void* stream) {
       return RANMAR_EHIP;
     if (b->grid_prepared != b->grid_node) {
       b->kdirect = DirectJumps{nullptr, 0u, 0u};
-      const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared);
+      const hipKernelNodeParams kp = kernel_params(b, b->grid_prepared, false);
       if (hipGraphExecKernelNodeSetParams(b->exec, b->kern, &kp) != hipSuccess) return RANMAR_EHIP;
       b->grid_node = b->grid_prepared;
     }

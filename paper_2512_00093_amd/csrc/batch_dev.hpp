@@ -419,22 +419,9 @@ __device__ __forceinline__ void batch_jump_oct(const Desc& D, const BHeader& h, 
 // the bin and everything derived from them stay wave-uniform (scalar
 // registers), as they would with blockIdx.x alone.
 template <int WPG, class Desc>
-__device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B, const DirectJumps& dj) {
+__device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffers& B) {
   __shared__ __align__(16) uint32_t lds_all[WPG][kWaveLds];  // 16-byte rows: chunk transposes read u32x4
   __shared__ SeedLds<true> seed_tab;
-  if (dj.n) {
-    // The direct mapping: the octet's records are fetched before the table
-    // fill, which hides their latency; no descriptor is read.
-    const uint32_t wv = WPG == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t rl0 = 8u * (blockIdx.x * WPG + wv);
-    const uint32_t nv = rl0 < dj.n ? (dj.n - rl0 < 8u ? dj.n - rl0 : 8u) : 0u;
-    const uint4 raw = octet_load(dj.recs + 32ull * rl0, nv, lane);
-    seed_lds_fill(seed_tab, threadIdx.x, 64u * WPG);
-    __syncthreads();
-    if (nv) jump_octet(raw, nv, lane, lds_all[wv], seed_tab, B, NoHook{});
-    return;
-  }
   const BHeader h = D.header();
   if (blockIdx.x * WPG >= h.n_workers) return;  // whole workgroups leave together
   seed_lds_fill(seed_tab, threadIdx.x, 64u * WPG);
@@ -482,6 +469,23 @@ __device__ __forceinline__ void batch_persistent(const Desc& D, const BatchBuffe
     }
   }
   D.finish(B.queue);
+}
+
+// The direct mapping of a batch of jumps only: wave w of the grid seeds and
+// jumps requests 8w .. 8w + 7 (no bins, no queue, no descriptor).  The
+// octet's records are fetched before the table fill, which hides their latency.
+template <int WPG>
+__device__ __forceinline__ void batch_direct(const BatchBuffers& B, const DirectJumps& dj) {
+  __shared__ uint32_t lds_all[WPG][8 * kOctStride];
+  __shared__ SeedLds<true> seed_tab;
+  const uint32_t wv = WPG == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t rl0 = 8u * (blockIdx.x * WPG + wv);
+  const uint32_t nv = rl0 < dj.n ? (dj.n - rl0 < 8u ? dj.n - rl0 : 8u) : 0u;
+  const uint4 raw = octet_load(dj.recs + 32ull * rl0, nv, lane);
+  seed_lds_fill(seed_tab, threadIdx.x, 64u * WPG);
+  __syncthreads();
+  if (nv) jump_octet(raw, nv, lane, lds_all[wv], seed_tab, B, NoHook{});
 }
 
 }  // namespace ranmar
