@@ -471,7 +471,9 @@ hipError_t launch_jump_poly_tab(const ranmar_u128* J, uint64_t n, uint32_t* P, h
   if (!n) return hipSuccess;
   if ((n + 3) / 4 > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((n + 3) / 4));
-  if (const uint32_t* T20 = window20_table_ready()) {  // 6 factors for 120 bits instead of 15
+  // The 20-bit table (6 factors for 120 bits instead of 15) where it exists,
+  // and built for bulk calls, as the jump kernels do.
+  if (const uint32_t* T20 = n >= 16384 ? window20_table() : window20_table_ready()) {
     hipLaunchKernelGGL(k_jump_poly_tab<20>, grid, dim3(256), 0, st, J, n, P, T20);
   } else {
     const uint32_t* T = window_table();
