@@ -14,7 +14,7 @@ namespace ranmar {
 
 constexpr int kHalfWords = 193 + 97;  // extended window + polynomial
 
-template <bool SEED>
+template <bool SEED, int WB>
 __global__ __launch_bounds__(256) void k_jump_coop(uint32_t* __restrict__ states, const int32_t* __restrict__ seeds,
                                                    const ranmar_u128* __restrict__ J, uint64_t n,
                                                    const uint32_t* __restrict__ T) {
@@ -48,8 +48,7 @@ __global__ __launch_bounds__(256) void k_jump_coop(uint32_t* __restrict__ states
   }
   if (!valid) X[l] = X[l + 32] = X[l + 64] = 0;  // keep the idle half's arithmetic defined
   wave_sync();
-  const int nwin = wave_windows(j0, j1, j2, j3);
-  jump_half(X, B, T, j0, j1, j2, j3, nwin, l);
+  jump_half<WB>(X, B, T, j0, j1, j2, j3, wave_windows<WB>(j0, j1, j2, j3), l);
   if (valid) {
     slot[l] = X[l];
     slot[l + 32] = X[l + 32];
@@ -486,13 +485,22 @@ hipError_t launch_jump_poly_tab(const ranmar_u128* J, uint64_t n, uint32_t* P, h
 hipError_t launch_jump_coop(uint32_t* states, const int32_t* seeds, const ranmar_u128* J, uint64_t n,
                             hipStream_t st) {
   if (!n) return hipSuccess;
+  const dim3 grid((unsigned)((n + 7) / 8));
+  // Few requests: the 20-bit table's 6 factors where the table already
+  // exists (it is not built for them), else the 8-bit table's.
+  if (const uint32_t* T20 = window20_table_ready()) {
+    if (seeds)
+      hipLaunchKernelGGL((k_jump_coop<true, 20>), grid, dim3(256), 0, st, states, seeds, J, n, T20);
+    else
+      hipLaunchKernelGGL((k_jump_coop<false, 20>), grid, dim3(256), 0, st, states, seeds, J, n, T20);
+    return hipGetLastError();
+  }
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
-  const dim3 grid((unsigned)((n + 7) / 8));
   if (seeds)
-    hipLaunchKernelGGL(k_jump_coop<true>, grid, dim3(256), 0, st, states, seeds, J, n, T);
+    hipLaunchKernelGGL((k_jump_coop<true, 8>), grid, dim3(256), 0, st, states, seeds, J, n, T);
   else
-    hipLaunchKernelGGL(k_jump_coop<false>, grid, dim3(256), 0, st, states, seeds, J, n, T);
+    hipLaunchKernelGGL((k_jump_coop<false, 8>), grid, dim3(256), 0, st, states, seeds, J, n, T);
   return hipGetLastError();
 }
 

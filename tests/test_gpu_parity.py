@@ -504,13 +504,17 @@ def test_jump_variant_seeding(orc, jump_variant):
     assert np.array_equal(got, np.stack([orc.state_from_seed(s) for s in seeds]))
 
 
-def test_jump_variant_edges(orc, jump_variant):
+def _edge_jumps():
     g = synth.rng(220)
     lo, hi = synth.u128_uniform(g, 60, 120)
-    Js = [0, 1, 2, 255, 256, 257, 65535, 1 << 64, (1 << 64) - 1, (1 << 120) - 1, (1 << 128) - 1,
-          ((1 << 97) - 1) << 23, (1 << 20) - 1, 1 << 20, ((1 << 20) - 1) << 20, 1 << 60, (1 << 120) + 255,
-          ((1 << 8) - 1) << 120, (1 << 24) - 1, 1 << 24, ((1 << 24) - 1) << 24, ((1 << 24) - 1) << 96,
-          (1 << 72) + (1 << 71), ((1 << 48) - 1) << 40] + synth.u128_to_int(lo, hi)
+    return [0, 1, 2, 255, 256, 257, 65535, 1 << 64, (1 << 64) - 1, (1 << 120) - 1, (1 << 128) - 1,
+            ((1 << 97) - 1) << 23, (1 << 20) - 1, 1 << 20, ((1 << 20) - 1) << 20, 1 << 60, (1 << 120) + 255,
+            ((1 << 8) - 1) << 120, (1 << 24) - 1, 1 << 24, ((1 << 24) - 1) << 24, ((1 << 24) - 1) << 96,
+            (1 << 72) + (1 << 71), ((1 << 48) - 1) << 40] + synth.u128_to_int(lo, hi)
+
+
+def test_jump_variant_edges(orc, jump_variant):
+    Js = _edge_jumps()
     seeds = [int(s) for s in synth.seeds(len(Js), offset=18)]
     seeds[:3] = [0, 900000001, -7]       # invalid seeds leave the marker record
     say(f"seed_jump edges variant={jump_variant}")
@@ -539,6 +543,52 @@ def test_jump_variants_agree_at_scale(jump_variant):
         R.ranmar_tune_set(R.RANMAR_K_JUMP, other)
         b = R.ranmar_seed_jump(seeds_t(s), limbs_t(lo, hi))
         assert torch.equal(a, b), other
+
+
+_HALF_WINDOW_FRESH = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import paper_2512_00093_amd as R
+from tests.gpu_util import jumps_t, seeds_t, u32
+from tests.test_gpu_parity import _edge_jumps
+torch.cuda.set_device(0)
+R.ranmar_init()
+R.ranmar_tune_set(R.RANMAR_K_JUMP, 1)
+Js = _edge_jumps()
+seeds = [4711 + 1000 * k for k in range(len(Js))]
+np.save(sys.argv[2], u32(R.ranmar_seed_jump(seeds_t(seeds), jumps_t(Js))))
+"""
+
+
+def test_half_window_jump_with_either_table(orc, tmp_path):
+    """The half-wave jump multiplies the 20-bit table's factors once that
+    table exists and the 8-bit table's before. A fresh process, in which
+    nothing has built the 20-bit table (few requests never do), checks the
+    8-bit route; this process checks the 20-bit route after a forced 20-bit
+    jump has built the table."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    Js = _edge_jumps()
+    seeds = [4711 + 1000 * k for k in range(len(Js))]
+    ref = orc.seed_jump_many(seeds, Js)
+    out = tmp_path / "fresh.npy"
+    say("half-window jump in a fresh process (8-bit table)")
+    subprocess.run([sys.executable, "-c", _HALF_WINDOW_FRESH, root, str(out)], cwd=root, check=True,
+                   timeout=300)
+    assert np.array_equal(np.load(out), ref)
+    try:
+        R.ranmar_tune_set(R.RANMAR_K_JUMP, 5)
+        R.ranmar_seed_jump(seeds_t(seeds[:8]), jumps_t(Js[:8]))       # builds the 20-bit table
+        R.ranmar_tune_set(R.RANMAR_K_JUMP, 1)
+        say("half-window jump with the 20-bit table")
+        got = u32(R.ranmar_seed_jump(seeds_t(seeds), jumps_t(Js)))
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_JUMP, -1)
+    assert np.array_equal(got, ref)
 
 
 def test_tune_run_jump_and_generate():
