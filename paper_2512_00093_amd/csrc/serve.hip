@@ -27,6 +27,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -84,7 +85,8 @@ struct ranmar_server {
   uint32_t L = 16384;
   uint64_t max_tick_requests = 8192;
 
-  std::map<uint64_t, uint64_t> free_list;  // offset -> size
+  std::map<uint64_t, uint64_t> free_list;           // offset -> size
+  std::set<std::pair<uint64_t, uint64_t>> by_size;  // (size, offset) of the same free blocks
   uint64_t in_use = 0, peak = 0, inflight = 0;
   uint64_t queued_bytes = 0;  // output bytes of submitted, not yet admitted requests
 
@@ -106,37 +108,45 @@ struct ranmar_server {
   uint64_t t_first = 0, t_last = 0;
   int err = 0;
 
-  // -- arena allocator (first fit, coalescing) --
+  // -- arena allocator (best fit, coalescing; logarithmic in the free blocks) --
+  void add_free(uint64_t off, uint64_t bytes) {
+    free_list.emplace(off, bytes);
+    by_size.emplace(bytes, off);
+  }
+  void drop_free(std::map<uint64_t, uint64_t>::iterator it) {
+    by_size.erase({it->second, it->first});
+    free_list.erase(it);
+  }
   bool alloc(uint64_t bytes, uint64_t* off) {
-    for (auto it = free_list.begin(); it != free_list.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const uint64_t rest = it->second - bytes, at = it->first + bytes;
-        free_list.erase(it);
-        if (rest) free_list[at] = rest;
-        in_use += bytes;
-        peak = std::max(peak, in_use);
-        return true;
-      }
-    }
-    return false;
+    const auto b = by_size.lower_bound({bytes, 0});
+    if (b == by_size.end()) return false;
+    const uint64_t size = b->first, at = b->second;
+    by_size.erase(b);
+    free_list.erase(at);
+    if (size > bytes) add_free(at + bytes, size - bytes);
+    *off = at;
+    in_use += bytes;
+    peak = std::max(peak, in_use);
+    return true;
   }
   void dealloc(uint64_t off, uint64_t bytes) {
     if (!bytes) return;
     in_use -= bytes;
-    auto it = free_list.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_list.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_list.erase(nx);
+    auto nx = free_list.lower_bound(off);
+    if (nx != free_list.end() && off + bytes == nx->first) {
+      bytes += nx->second;
+      auto gone = nx++;
+      drop_free(gone);
     }
-    if (it != free_list.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_list.erase(it);
+    if (nx != free_list.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        bytes += pv->second;
+        drop_free(pv);
       }
     }
+    add_free(off, bytes);
   }
 
   void complete(uint64_t t, Req& R, uint64_t when) {
@@ -331,7 +341,7 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
     return RANMAR_EINVAL;
   }
   s->L = (uint32_t)s->cfg.chunk_draws;
-  s->free_list[0] = s->arena_bytes;
+  s->add_free(0, s->arena_bytes);
   s->lanes.resize(s->cfg.lanes);
   for (Lane& ln : s->lanes) {
     if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess ||
@@ -492,23 +502,29 @@ int ranmar_serve_replay(ranmar_server* s, uint64_t n, const double* t_arrival_s,
     }
   });
   const uint64_t t0 = now_ns();
-  for (uint64_t r = 0; r < n; ++r) {
-    const uint64_t due = t0 + (uint64_t)(t_arrival_s[r] * 1e9);
+  auto due_of = [&](uint64_t r) { return t0 + (uint64_t)(t_arrival_s[r] * 1e9); };
+  for (uint64_t r = 0; r < n;) {
+    const uint64_t due = due_of(r);
     while (now_ns() < due) {
       const uint64_t left = due - now_ns();
       if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
     }
-    uint64_t t = 0;
-    int rc;
-    {
-      std::lock_guard<std::mutex> g(s->mu);
-      rc = s->submit_locked(seeds[r], offsets[r], counts[r], fmt, due, r + 1, &t);
-    }
-    if (rc != RANMAR_OK) {
-      int z = 0;
-      first_err.compare_exchange_strong(z, rc);
-      n_rejected.fetch_add(1, std::memory_order_release);
-    }
+    // Every request that has arrived by now is handed over under one lock
+    // (at most 256, so the server thread is not held off), each with its own
+    // arrival time, from which its latency counts.
+    const uint64_t now = now_ns();
+    std::lock_guard<std::mutex> g(s->mu);
+    const uint64_t end = std::min<uint64_t>(n, r + 256);
+    do {
+      uint64_t t = 0;
+      const int rc = s->submit_locked(seeds[r], offsets[r], counts[r], fmt, due_of(r), r + 1, &t);
+      if (rc != RANMAR_OK) {
+        int z = 0;
+        first_err.compare_exchange_strong(z, rc);
+        n_rejected.fetch_add(1, std::memory_order_release);
+      }
+      ++r;
+    } while (r < end && due_of(r) <= now);
   }
   rel.join();
   {
