@@ -142,8 +142,9 @@ int ranmar_apply_poly(ranmar_state *d_states, const uint32_t *d_P, uint64_t n, v
  * nonzero digit of J.  The library keeps, per device and until the process
  * ends, a 1.6 MB table of 8-bit digits and, from the first call with at
  * least 16384 requests, a 2.4 GB table of 20-bit digits (6 factors for a
- * 120-bit J instead of 15; if that allocation fails, the 16-bit table of
- * 203 MB or the 8-bit one serves; results are the same either way).  Where
+ * 120-bit J instead of 15), which later calls of any size then use; if that
+ * allocation fails, the 16-bit table of 203 MB or the 8-bit one serves;
+ * results are the same either way.  Where
  * the RANMAR_K_JUMP variant for the call's size is lanes8_window24 (forced,
  * or picked by the tuner), a 32.5 GB table of 24-bit digits (5 factors;
  * built in about 0.2 s on first use, kept like the others; the 20-bit table
