@@ -93,7 +93,7 @@ static int check_request(const ranmar_request& q, uint32_t L, uint64_t* nq) {
   // count) as 128-bit offsets of their own: the last must not pass 2^128 - 1.
   const unsigned __int128 off = ((unsigned __int128)q.offset.hi << 64) | q.offset.lo;
   if (q.count > 0 && off > ~(unsigned __int128)0 - (q.count - 1)) return RANMAR_EINVAL;
-  *nq = (q.count + L - 1) / L;
+  *nq = q.count ? (q.count - 1) / L + 1 : 0;  // no division for a jump
   return RANMAR_OK;
 }
 
@@ -119,14 +119,20 @@ static uint32_t host_parts(uint64_t n) {
   return std::max(1u, std::min(8u, hw ? hw : 1u));
 }
 
-static BJump to_bjump(const ranmar_request& q) {
-  BJump b{};
-  b.seed = q.seed;
-  b.off_lo = q.offset.lo;
-  b.off_hi = q.offset.hi;
-  b.state = (uint64_t)(uintptr_t)q.d_state;
-  return b;
+// A jump record written to the staging buffer with streaming stores (two
+// 16-byte halves; the buffer is only read by the device, so the host need not
+// fetch its lines first).  stage_fence() orders them before the launch.
+typedef long long v2i64 __attribute__((vector_size(16)));
+static void stage_bjump(BJump* dst, const ranmar_request& q) {
+  v2i64 a, b;
+  a[0] = (long long)(uint32_t)q.seed;
+  a[1] = (long long)q.offset.lo;
+  b[0] = (long long)q.offset.hi;
+  b[1] = (long long)(uintptr_t)q.d_state;
+  __builtin_nontemporal_store(a, (v2i64*)dst);
+  __builtin_nontemporal_store(b, (v2i64*)dst + 1);
 }
+static void stage_fence() { __builtin_ia32_sfence(); }
 
 static BReq to_breq(const ranmar_request& q) {
   BReq b{};
@@ -221,6 +227,9 @@ static void batch_free(ranmar_batch* b) {
 // (a batch of jumps copies only its header and bins).
 static uint64_t chunk_offset(uint32_t nb) { return 64 + sizeof(BBin) * (uint64_t)nb; }
 static uint64_t align16(uint64_t v) { return (v + 15) & ~15ull; }
+// Where a batch of jumps only keeps its records: past the header and the most
+// bins any batch has (no slices or chunks precede them).
+constexpr uint64_t kJumpsOnlyOff = 64 + sizeof(BBin) * (uint64_t)kMaxBins;
 
 namespace ranmar {
 void batch_set_variant(ranmar_batch* b, int v) {
@@ -317,7 +326,14 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   b->prepared_bytes = 0;
   if (n > b->max_req) return RANMAR_ENOMEM;
   if (n == 0) return RANMAR_OK;
-  // Validation and counts, in parts (large batches on several threads).
+  // The staging buffer may still be read by the previous run's copy and kernel.
+  if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
+  // Validation and counts, in parts (large batches on several threads).  A
+  // batch that starts with a request without draws is taken for one of jumps
+  // only: its records are staged in the same pass, at the fixed place such a
+  // batch keeps them (entry r for request r), and kept if the guess holds.
+  const bool guess_jumps = reqs[0].count == 0;
+  BJump* jo_fixed = (BJump*)(b->h_desc + kJumpsOnlyOff);
   const uint32_t parts = host_parts(n);
   std::vector<uint64_t> p_total(parts, 0), p_jo(parts, 0), p_draws(parts, 0);
   std::vector<int> p_rc(parts, RANMAR_OK);
@@ -333,7 +349,9 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
       tot += nq;
       jo += nq == 0;
       dr += reqs[r].count;
+      if (guess_jumps && nq == 0) stage_bjump(jo_fixed + r, reqs[r]);
     }
+    if (guess_jumps) stage_fence();  // before anything later writes the same lines
     p_total[t] = tot;
     p_jo[t] = jo;
     p_draws[t] = dr;
@@ -377,8 +395,6 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   const uint64_t cost = n + total;
   const uint32_t nb = (uint32_t)std::min<uint64_t>(max_bins, std::max<uint64_t>(1, cost / 4));
   const uint64_t chunk_off = chunk_offset(nb), req_off = align16(chunk_off + sizeof(BChunk) * total);
-  // The staging buffer may still be read by the previous run's copy and kernel.
-  if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return RANMAR_EHIP;
   BHeader* h = (BHeader*)b->h_desc;
   BBin* bins = (BBin*)(b->h_desc + 64);
   BReq* sl = (BReq*)(b->h_desc + req_off);  // slices with draws
@@ -476,17 +492,20 @@ int ranmar_batch_prepare(ranmar_batch* b, const ranmar_request* reqs, uint64_t n
   // Requests without draws: the k-th of them (in order) is entry k of their
   // table and belongs to bin i with n_jo i / nb <= k < n_jo (i + 1) / nb,
   // after that bin's slices with draws.
-  const uint64_t jo_off = align16(req_off + sizeof(BReq) * ti);
+  // A batch of jumps only keeps them at a fixed place (staged above when the
+  // first request had no draws); a mixed batch right after its slices.
+  const uint64_t jo_off = n_jo == n ? kJumpsOnlyOff : align16(req_off + sizeof(BReq) * ti);
   BJump* jo = (BJump*)(b->h_desc + jo_off);
-  if (n_jo) {
+  if (n_jo && !(n_jo == n && guess_jumps)) {
     std::vector<uint64_t> jo_before(parts, 0);
     for (uint32_t t = 1; t < parts; ++t) jo_before[t] = jo_before[t - 1] + p_jo[t - 1];
     parallel_parts(n, parts, [&](uint64_t lo, uint64_t hi, uint32_t t) {
       uint64_t k = jo_before[t];
       for (uint64_t r = lo; r < hi && k < n_jo; ++r) {
         if (reqs[r].count != 0) continue;
-        jo[k++] = to_bjump(reqs[r]);
+        stage_bjump(jo + k++, reqs[r]);
       }
+      stage_fence();
     });
   }
   h->n_bins = nb;

@@ -402,6 +402,35 @@ def test_batch_large_prepare_in_parts(orc):
     _check(orc, drawn)
 
 
+def test_batch_jumps_only_then_mixed_on_one_object(orc):
+    """A batch whose first request has no draws has its jump records staged
+    while it is validated; they are kept when every request is a jump and
+    staged again when one is not.  One batch object runs a batch of jumps
+    only, a batch that starts with jumps and holds draws, and jumps only
+    again: every jump equals ranmar_seed_jump, the draws the oracle."""
+    n = 70_000
+    s, lo, hi = synth.batch_jumps(n, 120, offset=31)
+    direct = u32(R.ranmar_seed_jump(torch.from_numpy(s.copy()).to(dev()),
+                                    torch.from_numpy(np.stack([lo, hi], 1).view(np.int64).copy()).to(dev())))
+    b = R.ranmar_batch_create(n + 3, 64)
+    try:
+        for rep, with_draws in enumerate((False, True, False)):
+            states = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+            items = [dict(seed=int(s[i]), offset=(int(hi[i]) << 64) | int(lo[i]), count=0, fmt=0, out=None,
+                          state=states[i]) for i in range(n)]
+            drawn = _alloc(_mixed_requests(3, 62 + rep, max_count=40_000, with_zero=False)) if with_draws else []
+            mixed = items[:20_000] + drawn[:1] + items[20_000:50_000] + drawn[1:] + items[50_000:]
+            say(f"batch jumps first rep={rep} draws={with_draws} n={len(mixed)}")
+            R.ranmar_batch_run(b, R.make_requests(mixed))
+            torch.cuda.synchronize()
+            assert np.array_equal(u32(states), direct), rep
+            _check(orc, drawn)
+    finally:
+        R.ranmar_batch_destroy(b)
+    idx = [0, 19_999, 20_000, n - 1]
+    assert np.array_equal(direct[idx], orc.seed_jump_many(s[idx], synth.u128_to_int(lo[idx], hi[idx])))
+
+
 # --- tuner over the batch executor --------------------------------------------
 @pytest.mark.parametrize("variant", range(9))
 def test_batch_every_mapping_bit_identical(orc, variant):
