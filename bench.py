@@ -342,7 +342,7 @@ class Timer:
         self.spans.setdefault(name, []).append((a, b))
         return a, b
 
-    def mean_ms(self, name):
+    def all_ms(self, name):
         import ctypes
         v = []
         for a, b in self.spans.get(name, []):
@@ -350,7 +350,15 @@ class Timer:
             if self.hip.hipEventSynchronize(b.h) != 0 or self.hip.hipEventElapsedTime(ctypes.byref(ms), a.h, b.h) != 0:
                 raise RuntimeError("hipEventElapsedTime failed")
             v.append(ms.value)
+        return v
+
+    def mean_ms(self, name):
+        v = self.all_ms(name)
         return sum(v) / len(v) if v else float("nan")
+
+    def median_ms(self, name):
+        v = sorted(self.all_ms(name))
+        return v[len(v) // 2] if v else float("nan")
 
 
 def run_family65k(R, torch, steps, warmup, jump_mode):
@@ -714,10 +722,11 @@ def run_paper_table2(R, torch, reps=20):
                 e.record()
             torch.cuda.synchronize()
             R.ranmar_tune_set(R.RANMAR_K_POLY, -1)
-            res.setdefault(f"J=2^{bits}-1", {})[name] = tm.mean_ms(f"{name}{bits}") * 1e3
+            res.setdefault(f"J=2^{bits}-1", {})[name] = tm.median_ms(f"{name}{bits}") * 1e3
     res["paper_us_cpu_ntl"] = {"J=2^64-1": {"apple": 1347, "arm": 10395, "ryzen": 946, "intel": 2702},
                                "J=2^120-1": {"apple": 2556, "arm": 21411, "ryzen": 1946, "intel": 4697}}
-    res["config"] = {"workload": "paper Table 2 shape: one all-ones J per launch; jump_poly = t^J mod phi alone "
+    res["config"] = {"workload": "paper Table 2 shape: one all-ones J per launch, median of 20 launches; "
+                                 "jump_poly = t^J mod phi alone "
                                  "(window-table products, one wave; _square_multiply: the paper's method, one "
                                  "lane), windowed_jump = the whole jump of one state (table factors, 32 lanes)"}
     return res
