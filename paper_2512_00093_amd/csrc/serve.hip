@@ -27,12 +27,12 @@
 #include <deque>
 #include <map>
 #include <mutex>
-#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/ranmar.h"
+#include "arena.hpp"
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -85,9 +85,8 @@ struct ranmar_server {
   uint32_t L = 16384;
   uint64_t max_tick_requests = 8192;
 
-  std::map<uint64_t, uint64_t> free_list;           // offset -> size
-  std::set<std::pair<uint64_t, uint64_t>> by_size;  // (size, offset) of the same free blocks
-  uint64_t in_use = 0, peak = 0, inflight = 0;
+  ranmar::ArenaAlloc arena_alloc;
+  uint64_t inflight = 0;
   uint64_t queued_bytes = 0;  // output bytes of submitted, not yet admitted requests
 
   std::unordered_map<uint64_t, Req> reqs;
@@ -108,47 +107,6 @@ struct ranmar_server {
   uint64_t t_first = 0, t_last = 0;
   int err = 0;
 
-  // -- arena allocator (best fit, coalescing; logarithmic in the free blocks) --
-  void add_free(uint64_t off, uint64_t bytes) {
-    free_list.emplace(off, bytes);
-    by_size.emplace(bytes, off);
-  }
-  void drop_free(std::map<uint64_t, uint64_t>::iterator it) {
-    by_size.erase({it->second, it->first});
-    free_list.erase(it);
-  }
-  bool alloc(uint64_t bytes, uint64_t* off) {
-    const auto b = by_size.lower_bound({bytes, 0});
-    if (b == by_size.end()) return false;
-    const uint64_t size = b->first, at = b->second;
-    by_size.erase(b);
-    free_list.erase(at);
-    if (size > bytes) add_free(at + bytes, size - bytes);
-    *off = at;
-    in_use += bytes;
-    peak = std::max(peak, in_use);
-    return true;
-  }
-  void dealloc(uint64_t off, uint64_t bytes) {
-    if (!bytes) return;
-    in_use -= bytes;
-    auto nx = free_list.lower_bound(off);
-    if (nx != free_list.end() && off + bytes == nx->first) {
-      bytes += nx->second;
-      auto gone = nx++;
-      drop_free(gone);
-    }
-    if (nx != free_list.begin()) {
-      auto pv = std::prev(nx);
-      if (pv->first + pv->second == off) {
-        off = pv->first;
-        bytes += pv->second;
-        drop_free(pv);
-      }
-    }
-    add_free(off, bytes);
-  }
-
   void complete(uint64_t t, Req& R, uint64_t when) {
     R.st = DONE;
     R.t_done = when;
@@ -160,7 +118,7 @@ struct ranmar_server {
   }
 
   void release_locked(std::unordered_map<uint64_t, Req>::iterator it) {
-    dealloc(it->second.aoff, it->second.count ? it->second.bytes : 0);
+    arena_alloc.release(it->second.aoff, it->second.count ? it->second.bytes : 0);
     --inflight;
     ++released;
     reqs.erase(it);
@@ -198,7 +156,7 @@ struct ranmar_server {
         const uint64_t t = queue.front();
         Req& R = reqs[t];
         uint64_t off = 0;
-        if (!alloc(R.bytes, &off)) break;
+        if (!arena_alloc.alloc(R.bytes, &off)) break;
         R.aoff = off;
         R.st = ADMITTED;
         ++inflight;
@@ -283,7 +241,7 @@ int ranmar_server::submit_locked(int32_t seed, ranmar_u128 offset, uint64_t coun
     return RANMAR_ENOMEM;
   }
   if (!cfg.queue_when_full &&
-      (in_use + queued_bytes + nbytes > arena_bytes || inflight + queue.size() >= cfg.max_inflight)) {
+      (arena_alloc.in_use() + queued_bytes + nbytes > arena_bytes || inflight + queue.size() >= cfg.max_inflight)) {
     ++rejected;
     return RANMAR_EAGAIN;
   }
@@ -341,7 +299,7 @@ int ranmar_serve_create(void* d_arena, uint64_t arena_bytes, const ranmar_serve_
     return RANMAR_EINVAL;
   }
   s->L = (uint32_t)s->cfg.chunk_draws;
-  s->add_free(0, s->arena_bytes);
+  s->arena_alloc.reset(s->arena_bytes);
   s->lanes.resize(s->cfg.lanes);
   for (Lane& ln : s->lanes) {
     if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess ||
@@ -432,8 +390,8 @@ int ranmar_serve_stats_get(ranmar_server* s, ranmar_serve_stats* out) {
   out->rejected = s->rejected;
   out->ticks = s->ticks;
   out->draws = s->draws;
-  out->bytes_in_use = s->in_use;
-  out->bytes_peak = s->peak;
+  out->bytes_in_use = s->arena_alloc.in_use();
+  out->bytes_peak = s->arena_alloc.peak();
   if (!s->lat.empty()) {
     std::vector<double> v = s->lat;
     std::sort(v.begin(), v.end());
