@@ -276,7 +276,7 @@ hipError_t launch_family_window(const uint32_t* base, ranmar_u128 delta, uint64_
   if (n > 1 && D > kMax / (n - 1)) return hipErrorInvalidValue;
   const uint32_t* T = window_table();
   if (!T) return hipErrorOutOfMemory;
-  // Round 1 reads the base record and also writes start 0 (the base itself)
+  // The first radix round reads the base record and also writes start 0 (the base itself)
   // unless the family is built in place.
   for (uint64_t M = 1, first = (base != out) ? 0 : 1; M < n || first < M; first = M) {
     const uint64_t top = (M <= n / 256) ? 256 * M : n;  // starts [first, top) this round
