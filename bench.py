@@ -877,8 +877,10 @@ def run_serve(R, torch, n_req, light_qps, lanes, capacity_only=False):
     for arm, ub in (("batched", False), ("one_launch_per_request", True)):
         res = {}
         # The batched arm's capacity run takes about 0.15 s and varies by a few
-        # percent: the median of three sets the loaded rates below.
-        caps = sorted((serve_arm(R, torch, tr, n_req, 1e12, lanes, ub, arena) for _ in range(1 if ub else 3)),
+        # percent: the median of three sets the loaded rates below (one run
+        # when only the capacity is asked for, as under a profiler).
+        reps = 1 if ub or capacity_only else 3
+        caps = sorted((serve_arm(R, torch, tr, n_req, 1e12, lanes, ub, arena) for _ in range(reps)),
                       key=lambda c: c["req_per_s"])
         cap = caps[len(caps) // 2]
         if len(caps) > 1:
