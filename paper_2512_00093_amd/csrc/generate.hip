@@ -88,6 +88,7 @@ const char* gen_variant_name(int v) {
     case GEN_LANES32_NT_R3: return "lanes32_nt_res3";
     case GEN_WIDE4_NT_R4: return "lanes32_wide4_nt_res4";
     case GEN_WIDE4_NT_R6: return "lanes32_wide4_nt_res6";
+    case GEN_WIDE4_NT_R5: return "lanes32_wide4_nt_res5";
     default: return "?";
   }
 }
@@ -119,8 +120,9 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   if (variant == GEN_LANES32_NT_R2 || variant == GEN_LANES32_NT_R3) {
     cap_lds = residency_lds(variant == GEN_LANES32_NT_R2 ? 2 : 3, 0);
     variant = GEN_LANES32_NT;
-  } else if (variant == GEN_WIDE4_NT_R4 || variant == GEN_WIDE4_NT_R6) {
-    cap_lds = residency_lds(variant == GEN_WIDE4_NT_R4 ? 4 : 6, wide_ok ? 8 * 128 * 4 : 0);
+  } else if (variant == GEN_WIDE4_NT_R4 || variant == GEN_WIDE4_NT_R5 || variant == GEN_WIDE4_NT_R6) {
+    cap_lds = residency_lds(variant == GEN_WIDE4_NT_R4 ? 4 : variant == GEN_WIDE4_NT_R5 ? 5 : 6,
+                            wide_ok ? 8 * 128 * 4 : 0);
     variant = GEN_WIDE4_NT;
   }
   if (!wide_ok && variant == GEN_WIDE4) variant = GEN_LANES32;

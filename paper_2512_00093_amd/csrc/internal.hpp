@@ -110,7 +110,8 @@ enum GenVariant : int {
   GEN_LANES32_NT_R3 = 6,
   GEN_WIDE4_NT_R4 = 7,
   GEN_WIDE4_NT_R6 = 8,
-  GEN_NUM_VARIANTS = 9
+  GEN_WIDE4_NT_R5 = 9,
+  GEN_NUM_VARIANTS = 10
 };
 const char* gen_variant_name(int v);
 hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uint64_t n, uint64_t count, int fmt,
