@@ -81,7 +81,8 @@ def source_digest(src=None):
 
 
 def profiled_traffic(kernel, grid, src):
-    """HBM bytes (fetched + written) per dispatch of `kernel` at `grid` threads
+    """HBM bytes (fetched + written) per dispatch of `kernel` (a prefix of the
+    kernel's name, e.g. without its last template argument) at `grid` threads
     from the committed rocprofv3 counter summaries, or None when no summary was
     taken from the current sources of that kernel (`src` and its includes)."""
     digest = source_digest(src)
@@ -463,7 +464,7 @@ def run_bulk1m(R, torch, steps, warmup):
         "output_write_frac": 4 * draws / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "k_gen32_wide<f32>", "achieved": algo / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_gen32_wide<1, true>", n // 8 * 256, "generate.hip"),
+                     "traffic": profiled_traffic("k_gen32_wide<1, true", n // 8 * 256, "generate.hip"),
                      "bytes_per_launch": algo, "launch_ms": ms},
     }
 

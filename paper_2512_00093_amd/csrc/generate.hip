@@ -8,16 +8,18 @@
 
 namespace ranmar {
 
-// The stream of half-wave j (0..7) of workgroup b in the wide-store kernel.
-// The dispatcher hands workgroup b to XCD b mod 8, so workgroup 8k + x takes
-// streams 64k + 8j + x: neighbouring rows of the output are written from
-// different XCDs.  On 2^20 rows of 4 KB this measured 4% faster than eight
-// neighbouring rows per workgroup (10% without a residency cap); on 65,536
-// rows of 16 KB the plain kernel measured 9% slower with it, and keeps eight
+// The stream of half-wave j (0..H-1) of workgroup b in the wide-store kernel
+// (H half-waves per workgroup).  The dispatcher hands workgroup b to XCD
+// b mod 8, so workgroup 8k + x takes streams 8 (kH + j) + x: neighbouring rows
+// of the output are written from different XCDs.  On 2^20 rows of 4 KB this
+// measured 4% faster than H neighbouring rows per workgroup (10% without a
+// residency cap, and 14% with 16 half-waves per workgroup); on 65,536 rows of
+// 16 KB the plain kernel measured 9% slower with it, and keeps eight
 // neighbouring rows per workgroup.  Grids are a multiple of 8 workgroups;
 // streams past n leave.
+template <int H>
 __device__ __forceinline__ uint64_t spread_stream(uint32_t b, uint32_t j) {
-  return ((uint64_t)(b >> 3) * 8u + j) * 8u + (b & 7u);
+  return ((uint64_t)(b >> 3) * H + j) * 8u + (b & 7u);
 }
 
 template <int FMT, bool NT>
@@ -63,15 +65,15 @@ __global__ __launch_bounds__(256) void k_gen32_pipe(const uint32_t* __restrict__
   }
 }
 
-// Wide-store variant: eight half-waves per workgroup, each with a 512-byte LDS
-// transpose buffer.
-template <int FMT, bool NT>
-__global__ __launch_bounds__(256) void k_gen32_wide(const uint32_t* __restrict__ sin, uint32_t* sout, uint64_t n,
-                                                    uint64_t count, void* __restrict__ out, uint64_t ld) {
-  __shared__ uint32_t bufs[8 * 128];
+// Wide-store variant: H half-waves per workgroup (8 or 16), each with a
+// 512-byte LDS transpose buffer.
+template <int FMT, bool NT, int H>
+__global__ __launch_bounds__(32 * H) void k_gen32_wide(const uint32_t* __restrict__ sin, uint32_t* sout, uint64_t n,
+                                                       uint64_t count, void* __restrict__ out, uint64_t ld) {
+  __shared__ uint32_t bufs[H * 128];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t l = lane & 31u;
-  const uint64_t s = spread_stream(blockIdx.x, threadIdx.x >> 5);
+  const uint64_t s = spread_stream<H>(blockIdx.x, threadIdx.x >> 5);
   if (s >= n) return;
   gen_stream32_wide<FMT, NT>(l, lane, sin + s * kWords, sout ? sout + s * kWords : nullptr, count,
                              FMT == RANMAR_F32, (char*)out + s * ld * 4u, bufs + (threadIdx.x >> 5) * 128);
@@ -89,6 +91,8 @@ const char* gen_variant_name(int v) {
     case GEN_WIDE4_NT_R4: return "lanes32_wide4_nt_res4";
     case GEN_WIDE4_NT_R6: return "lanes32_wide4_nt_res6";
     case GEN_WIDE4_NT_R5: return "lanes32_wide4_nt_res5";
+    case GEN_WIDE16_NT_R2: return "lanes32_wide4_nt_wg16_res2";
+    case GEN_WIDE16_NT_R3: return "lanes32_wide4_nt_wg16_res3";
     default: return "?";
   }
 }
@@ -113,6 +117,7 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   const unsigned wg = 256;
   const uint64_t per_wg = wg / 32;
   const dim3 grid((unsigned)(((n + per_wg - 1) / per_wg + 7) & ~7ull));  // whole groups of 8 (spread_stream)
+  const dim3 grid16((unsigned)(((n + 15) / 16 + 7) & ~7ull));             // 16 half-waves per workgroup
   // The wide stores need 16-byte aligned rows, and write one format.
   const bool wide_ok = (((uintptr_t)out & 15) == 0) && (ld % 4 == 0) && FMT != RANMAR_U24_F32;
   const uint64_t plane = n * ld;  // second plane of RANMAR_U24_F32
@@ -124,6 +129,15 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
     cap_lds = residency_lds(variant == GEN_WIDE4_NT_R4 ? 4 : variant == GEN_WIDE4_NT_R5 ? 5 : 6,
                             wide_ok ? 8 * 128 * 4 : 0);
     variant = GEN_WIDE4_NT;
+  } else if (variant == GEN_WIDE16_NT_R2 || variant == GEN_WIDE16_NT_R3) {
+    if (wide_ok) {
+      cap_lds = residency_lds(variant == GEN_WIDE16_NT_R2 ? 2 : 3, 16 * 128 * 4);
+      if constexpr (FMT != RANMAR_U24_F32)
+        hipLaunchKernelGGL((k_gen32_wide<FMT, true, 16>), grid16, dim3(512), cap_lds, st, sin, sout, n, count, out,
+                           ld);
+      return hipGetLastError();
+    }
+    variant = GEN_LANES32_NT;  // unaligned rows: 4-byte stores
   }
   if (!wide_ok && variant == GEN_WIDE4) variant = GEN_LANES32;
   if (!wide_ok && variant == GEN_WIDE4_NT) variant = GEN_LANES32_NT;
@@ -145,11 +159,11 @@ static hipError_t launch_fmt(int variant, const uint32_t* sin, uint32_t* sout, u
   switch (variant) {
     case GEN_WIDE4:
       if constexpr (FMT != RANMAR_U24_F32)
-        hipLaunchKernelGGL((k_gen32_wide<FMT, false>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
+        hipLaunchKernelGGL((k_gen32_wide<FMT, false, 8>), grid, dim3(wg), 0, st, sin, sout, n, count, out, ld);
       break;
     case GEN_WIDE4_NT:
       if constexpr (FMT != RANMAR_U24_F32)
-        hipLaunchKernelGGL((k_gen32_wide<FMT, true>), grid, dim3(wg), cap_lds, st, sin, sout, n, count, out, ld);
+        hipLaunchKernelGGL((k_gen32_wide<FMT, true, 8>), grid, dim3(wg), cap_lds, st, sin, sout, n, count, out, ld);
       break;
     case GEN_LANES32_NT:
       hipLaunchKernelGGL((k_gen32<FMT, true>), grid, dim3(wg), cap_lds, st, sin, sout, n, count, out, ld, plane);

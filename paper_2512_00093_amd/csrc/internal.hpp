@@ -111,7 +111,11 @@ enum GenVariant : int {
   GEN_WIDE4_NT_R4 = 7,
   GEN_WIDE4_NT_R6 = 8,
   GEN_WIDE4_NT_R5 = 9,
-  GEN_NUM_VARIANTS = 10
+  // The wide form with 16 half-waves per workgroup (512 threads), at most R
+  // such workgroups per CU.
+  GEN_WIDE16_NT_R2 = 10,
+  GEN_WIDE16_NT_R3 = 11,
+  GEN_NUM_VARIANTS = 12
 };
 const char* gen_variant_name(int v);
 hipError_t launch_generate(int variant, const uint32_t* sin, uint32_t* sout, uint64_t n, uint64_t count, int fmt,

@@ -98,13 +98,15 @@ int gen_variant_for(uint64_t n, uint64_t count) {
   auto it = g_table.find({RANMAR_K_GENERATE, ilog2(n), ilog2(count)});
   if (it != g_table.end()) return it->second;
   // Measured (float32, ms per launch): 2^20 streams x 1,024 draws: 16-byte
-  // stores with at most 5 workgroups per CU 0.76-0.77, 6 0.765-0.77, 7 0.80,
-  // 4 0.82, uncapped 0.83 (neighbouring streams on different XCDs); 65,536 x
+  // stores, neighbouring streams on different XCDs, 16 half-waves per
+  // workgroup with at most 3 workgroups per CU 0.71-0.73, at most 2 0.74-0.75,
+  // 4 0.74; 8 half-waves per workgroup with at most 5 per CU 0.755-0.76, 6
+  // 0.765-0.77, 7 0.80, 4 0.82, uncapped 0.83; 32 half-waves 0.76-0.78; 65,536 x
   // 4,096: 4-byte stores with at most 2 workgroups per CU 0.172, uncapped
   // 0.190; 16,384 x 16,384 (every workgroup resident at once anyway):
   // ordinary 16-byte stores 0.203, the capped forms 0.21-0.23.  The wide
   // forms fall back to 4-byte stores for unaligned rows.
-  if (count <= 2048) return GEN_WIDE4_NT_R5;
+  if (count <= 2048) return GEN_WIDE16_NT_R3;
   return n >= 32768 ? GEN_LANES32_NT_R2 : GEN_WIDE4;
 }
 
