@@ -1,5 +1,6 @@
 // Bulk generation over many independent streams: one stream per half-wave,
-// two per wave64, eight per workgroup (see gen_dev.hpp for the mapping).
+// two per wave64, eight (or, in the wide-store kernel, sixteen) per workgroup
+// (see gen_dev.hpp for the mapping).
 #include <algorithm>
 
 #include "common.hpp"
