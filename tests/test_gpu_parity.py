@@ -302,6 +302,32 @@ def test_generate_variants_bit_identical(orc):
         R.ranmar_tune_set(R.RANMAR_K_GENERATE, -1)
 
 
+@pytest.mark.parametrize("n,count,ld", [(1, 33, 36), (131, 2048, 2048), (131, 1000, 1003), (257, 64, 68),
+                                        (2053, 160, 160)])
+def test_generate_variants_ragged_grids_and_pitches(orc, n, count, ld):
+    """Every generation variant on stream counts that leave workgroups (of 8
+    or 16 half-waves, in groups of 8 workgroups) partly empty, with row
+    pitches that allow 16-byte stores (ld a multiple of 4) or not (the wide
+    forms then fall back to 4-byte stores): draws, untouched padding and the
+    states written back, bit for bit."""
+    st = np.stack([orc.state_from_seed(900 + 7 * k) for k in range(n)])
+    ref, ref_st = orc.draws_many(st, count)
+    nv = R.ranmar_tune_variants(R.RANMAR_K_GENERATE)
+    try:
+        for v in range(nv):
+            R.ranmar_tune_set(R.RANMAR_K_GENERATE, v)
+            say(f"generate ragged n={n} count={count} ld={ld} variant={v}")
+            out = torch.full((n, ld), -5, dtype=torch.float32, device=dev())
+            so = torch.zeros((n, 98), dtype=torch.int32, device=dev())
+            R.ranmar_generate(states_t(st), count, R.RANMAR_F32, out=out, states_out=so, ld=ld)
+            w = u32(out)
+            assert np.array_equal(w[:, :count], f32_words(ref)), v
+            assert (w[:, count:] == u32(torch.full((1,), -5, dtype=torch.float32))[0]).all(), v
+            assert np.array_equal(u32(so), ref_st), v
+    finally:
+        R.ranmar_tune_set(R.RANMAR_K_GENERATE, -1)
+
+
 # --- stream families -----------------------------------------------------------
 @pytest.mark.parametrize("n,delta", [(1, (1 << 40) + 12345), (2, (1 << 40) + 12345), (3, (1 << 40) + 12345),
                                      (64, (1 << 40) + 12345), (100, (1 << 40) + 12345),
